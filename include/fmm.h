@@ -1,0 +1,232 @@
+/*
+ * fmm.h - C interface of the MI355X (gfx950) dual-tree-traversal fast
+ * multipole method for the 3-D Laplace kernel.
+ *
+ * Method: R. Yokota, "An FMM Based on Dual Tree Traversal for Many-core
+ * Architectures" (arXiv:1209.3516).  A Morton-key octree with at most ncrit
+ * bodies per leaf (section 3.3), interaction lists from a dual tree traversal
+ * under the multipole acceptance criterion theta (section 3.2; section 3.3,
+ * Algorithms 3 and 4), Cartesian Taylor expansions (section 3.1, Table 2), and
+ * the P2M, M2M, M2L, P2P, L2L and L2P kernels.
+ *
+ * Quantities (the paper states no formulas; these are the textbook ones):
+ *   phi_i  = sum_{j : |x_j - x_i| > 0} q_j / |x_j - x_i|
+ *   grad_i = d phi / d x (x_i) = sum_j q_j (x_j - x_i) / |x_j - x_i|^3
+ * No 1/(4 pi) factor and no softening.  Order p keeps multipole and local
+ * terms of total degree 0..p-1, p(p+1)(p+2)/6 coefficients per cell.
+ *
+ * Conventions for every function:
+ *  - Return 0 (FMM_OK) or a negative fmm_status; nothing aborts or exits.
+ *    fmm_last_error() gives a message for the last failure on this thread.
+ *  - Arguments are checked before any GPU call, so FMM_EINVAL cases never
+ *    touch the device.
+ *  - Host pointers are borrowed for the duration of the call only.
+ *  - "Device" pointers are HIP device allocations of the caller (for example
+ *    torch tensors); they are read or written asynchronously on the given
+ *    HIP stream (hipStream_t passed as void*; NULL = the null stream).  The
+ *    call returns after enqueueing; the caller synchronises.
+ *  - Handles (fmm_tree, fmm_lists) own host memory and, once a device call
+ *    has been made, device memory; a handle is used from one host thread and
+ *    one stream at a time.
+ */
+#ifndef PAPER_1209_3516_AMD_FMM_H
+#define PAPER_1209_3516_AMD_FMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fmm_status {
+  FMM_OK = 0,
+  FMM_EINVAL = -1,  /* bad argument (NaN position, theta outside (0,1), p out of range...) */
+  FMM_ENOMEM = -2,  /* host or device allocation failed */
+  FMM_EDEVICE = -3, /* a HIP call failed; fmm_last_error() holds hipGetErrorString */
+  FMM_ESTATE = -4   /* handles that do not belong together (lists of another tree) */
+};
+
+enum fmm_precision {
+  FMM_MIXED = 0, /* P2P, M2L, P2M, L2P in FP32; P2P sums Kahan-compensated */
+  FMM_FP64 = 1   /* every kernel in FP64, plain sums */
+};
+
+enum fmm_traverse_flags {
+  FMM_MAC_FIRST = 0u, /* test the MAC before the leaf test (default) */
+  FMM_LEAF_FIRST = 1u /* leaf test first, as printed in Algorithm 4 */
+};
+
+enum fmm_list_kind { FMM_P2P = 0, FMM_M2L = 1 };
+
+enum fmm_eval_flags {
+  FMM_EVAL_TIMING = 1, /* record per-phase device times (fmm_last_timings) */
+  FMM_EVAL_KEEP_STAGES = 2 /* keep a copy of the locals after M2L (fmm_copy_expansions) */
+};
+
+/* Phases reported by fmm_last_timings, in this order. */
+enum fmm_phase {
+  FMM_PHASE_GATHER = 0, /* charges into Morton order */
+  FMM_PHASE_P2P = 1,    /* near field */
+  FMM_PHASE_P2M = 2,
+  FMM_PHASE_M2M = 3,
+  FMM_PHASE_M2L = 4,
+  FMM_PHASE_L2L = 5,
+  FMM_PHASE_L2P = 6, /* L2P + near/far combine + scatter to user order */
+  FMM_PHASE_TOTAL = 7,
+  FMM_NUM_PHASES = 8
+};
+
+#define FMM_MAX_P 8
+#define FMM_MAX_LEVEL 21
+
+typedef struct fmm_tree fmm_tree;
+typedef struct fmm_lists fmm_lists;
+
+typedef struct fmm_eval_opts {
+  int p;               /* expansion order, 1..FMM_MAX_P (degrees 0..p-1) */
+  int precision;       /* enum fmm_precision */
+  int fp64_top_levels; /* FMM_MIXED only: multipoles/locals of cells at level <= this are
+                          kept and translated (M2M, L2L) in FP64; -1 = automatic
+                          (3 when p >= 8, otherwise none); -2 = none */
+  int flags;           /* enum fmm_eval_flags */
+} fmm_eval_opts;
+
+/* Read-only view of a tree (library-owned host arrays, valid until the tree is freed). */
+typedef struct fmm_tree_view_t {
+  int64_t n;         /* bodies */
+  int64_t n_cells;   /* cells, numbered breadth first (children contiguous) */
+  int64_t n_leaves;
+  int32_t max_level; /* deepest level (root = 0) */
+  int32_t fp32_exact; /* 1 if every position is exactly representable in FP32 */
+  const int32_t *perm;        /* [n]  Morton position -> user index */
+  const uint64_t *keys;       /* [n]  63-bit Morton keys in Morton order */
+  const int32_t *level;       /* [n_cells] */
+  const int32_t *parent;      /* [n_cells] -1 for the root */
+  const int32_t *child_begin; /* [n_cells] first child (0 for a leaf) */
+  const int32_t *n_child;     /* [n_cells] 0 for a leaf */
+  const int64_t *body_begin;  /* [n_cells] first body (Morton position) */
+  const int64_t *n_body;      /* [n_cells] */
+  const double *center;       /* [n_cells][3] expansion centre: middle of the cell's tight bounding box */
+  const double *radius;       /* [n_cells] largest centre-to-body distance */
+} fmm_tree_view_t;
+
+typedef struct fmm_lists_stats_t {
+  int64_t p2p_entries; /* leaf pairs in the P2P list */
+  int64_t m2l_entries; /* cell pairs in the M2L list */
+  int64_t p2p_pairs;   /* body-body interactions: sum over entries n_A*n_B, minus n_A for (A,A) */
+  int64_t p2p_work_items; /* GPU work items of the P2P kernel (0 before the first evaluation) */
+  int64_t p2p_max_row_sources; /* largest number of source bodies of one target leaf */
+} fmm_lists_stats_t;
+
+/*
+ * Build the octree (section 3.3: Morton keys, ncrit bodies per leaf).
+ *   xyz   host, n x 3 row-major FP64 positions in user order; finite.
+ *   n     >= 0 (0 gives an empty tree whose evaluation is a no-op).
+ *   ncrit >= 1: a cell with more than ncrit bodies is split (up to level 21).
+ * Root cube: centre (lo+hi)/2, half-width max_d (hi_d-lo_d)/2.  Keys use 21 bits
+ * per axis (x in the lowest bit of each triplet); bodies are sorted stably by key.
+ * Cells with more than ncrit bodies get one child per non-empty octant.
+ * Host only: no GPU is touched.  *out is owned by the caller until fmm_tree_free.
+ */
+int fmm_tree_build(const double *xyz, int64_t n, int ncrit, fmm_tree **out);
+
+/*
+ * Replace the positions (host, n x 3, user order) while keeping the structure
+ * (keys, cells, centres, radii) frozen - used for finite-difference checks of
+ * the gradient, which differentiate the method with its tree held fixed.
+ * Host only; device copies are refreshed by the next evaluation.
+ */
+int fmm_tree_set_positions(fmm_tree *t, const double *xyz);
+
+int fmm_tree_view(const fmm_tree *t, fmm_tree_view_t *v);
+void fmm_tree_free(fmm_tree *t);
+
+/*
+ * Dual tree traversal (section 3.3, Algorithms 3 and 4) from (root, root).
+ * MAC (section 3.2): (A, B) is well separated iff
+ *   (theta*theta) * ((dx*dx + dy*dy) + dz*dz) > (B_A + B_B)^2   (FP64, strict),
+ * d the distance between expansion centres, B the cell radii; 0 < theta < 1.
+ * Not separated: both leaves -> P2P; a self pair (A, A) splits into all pairs
+ * of children; otherwise the cell with the larger radius is split (equal radii:
+ * the lower-numbered one), never a leaf.  The lists are symmetric.
+ * flags: FMM_MAC_FIRST (default) or FMM_LEAF_FIRST.
+ * Output: two CSR lists (P2P, M2L), one row per target cell, sources ascending.
+ * Host only: no GPU is touched.
+ */
+int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out);
+
+/* CSR view of one list (library-owned host arrays, valid until fmm_lists_free).
+ * nrows = number of cells; row_ptr[nrows+1] int64; col[nnz] int32. */
+int fmm_lists_view(const fmm_lists *l, int kind, const int64_t **row_ptr, const int32_t **col,
+                   int64_t *nrows, int64_t *nnz);
+int fmm_lists_stats(const fmm_lists *l, fmm_lists_stats_t *s);
+void fmm_lists_free(fmm_lists *l);
+
+/*
+ * Forward evaluation (all of P2M, M2M, M2L, L2L, L2P and P2P) on one GPU.
+ *   q_dev    device, [n] charges in user order (float for FMM_MIXED, double for FMM_FP64)
+ *   phi_dev  device, [n] potentials out (same dtype)
+ *   grad_dev device, [n][3] gradients out (same dtype), or NULL
+ *   stream   hipStream_t or NULL.
+ * l must come from fmm_traverse(t, ...) (else FMM_ESTATE).  The first call on a
+ * (tree, lists, p, precision) uploads the tree, lists and work plan and
+ * allocates device scratch (hipMalloc); later calls reuse them.  No float
+ * atomics: repeated calls give bitwise identical results.
+ */
+int fmm_evaluate(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o, const void *q_dev,
+                 void *phi_dev, void *grad_dev, void *stream);
+
+/*
+ * Backward of L = sum_i w_i phi_i for the forward above, with the tree, lists,
+ * centres and radii held fixed (the method is linear in q and its far-field
+ * operator is symmetric when the lists are):
+ *   dq_dev[i]    = dL/dq_i = phi_i[w]                       (an evaluation with charges w)
+ *   dx_dev[i][d] = dL/dx_i = w_i grad_i[q] + q_i grad_i[w]
+ *   grad_q_dev   device [n][3]: grad[q] from the forward (required when dx_dev != NULL)
+ *   w_dev        device [n]: upstream gradient dL/dphi
+ * Same dtype/stream rules as fmm_evaluate; dq_dev or dx_dev may be NULL.
+ */
+int fmm_evaluate_backward(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o,
+                          const void *q_dev, const void *grad_q_dev, const void *w_dev,
+                          void *dq_dev, void *dx_dev, void *stream);
+
+/*
+ * Direct O(N) sum per target in FP64 on the GPU (zero-distance pairs skipped),
+ * the reference the method approximates; used to report accuracy.
+ *   xyz_dev     device, double [n][3] positions (user order)
+ *   q_dev       device, double [n] charges
+ *   targets_dev device, int64 [m] target indices in [0, n)
+ *   phi_dev     device, double [m]; grad_dev device, double [m][3] or NULL
+ */
+int fmm_direct(const void *xyz_dev, const void *q_dev, int64_t n, const int64_t *targets_dev,
+               int64_t m, void *phi_dev, void *grad_dev, void *stream);
+
+/*
+ * Per-phase device times (milliseconds, enum fmm_phase order) of the last
+ * fmm_evaluate on these lists that was called with FMM_EVAL_TIMING.  Waits for
+ * that evaluation to finish.  ms must hold FMM_NUM_PHASES doubles.
+ */
+int fmm_last_timings(const fmm_lists *l, double *ms);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char *fmm_last_error(void);
+
+/* Number of expansion coefficients p(p+1)(p+2)/6, or -1 for p out of range. */
+int fmm_num_terms(int p);
+
+/*
+ * Copy a device-side expansion array of the last evaluation into host memory,
+ * for staged parity checks: kind 0 = multipoles M after the upward pass,
+ * 1 = locals after M2L (before L2L), 2 = locals after L2L.  dst: host double
+ * [n_cells][fmm_num_terms(p)], coefficient t having exponents exps[t] as given
+ * by fmm_term_exponents (int32 [T][3]).  Synchronises the device.  kind 1
+ * requires the last evaluation to have been called with FMM_EVAL_KEEP_STAGES.
+ */
+int fmm_copy_expansions(const fmm_lists *l, int kind, double *dst);
+int fmm_term_exponents(int p, int32_t *exps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_1209_3516_AMD_FMM_H */

@@ -1,0 +1,699 @@
+// C interface of the GPU FMM library (declared in include/fmm.h).
+//
+// Tree build and traversal run on the host and never touch the GPU.  The
+// first evaluation on a (tree, lists) pair uploads the tree, the lists and
+// the P2P work plan; device scratch is sized per (p, precision).  Every
+// kernel of one evaluation is enqueued on the caller's stream with no host
+// synchronisation in between.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fmm.h"
+#include "fmm_internal.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_error;
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+std::atomic<uint64_t> g_next_tree_id{1};
+
+// Fault injection for the failure-handling tests: FMM_FAULT_INJECT=launch:K
+// makes the K-th kernel launch of every evaluation (counted from 1) report a
+// device error instead of launching.
+int fault_launch_target() {
+  const char *s = std::getenv("FMM_FAULT_INJECT");
+  if (!s || std::strncmp(s, "launch:", 7) != 0) return -1;
+  return std::atoi(s + 7);
+}
+thread_local int g_launch_counter = 0;
+
+struct DevTree {
+  int device = -1;
+  int64_t n = 0, n_cells = 0;
+  uint64_t pos_version_32 = ~0ull, pos_version_64 = ~0ull;
+  void *b32 = nullptr;  // float4[n]
+  void *b64 = nullptr;  // double4[n]
+  int32_t *perm = nullptr;
+  double *geo = nullptr;  // double4[n_cells]: centre, radius
+  int32_t *body_begin = nullptr, *n_body = nullptr, *child_begin = nullptr, *n_child = nullptr,
+          *parent = nullptr;
+  void release() {
+    void *ptrs[] = {b32, b64, perm, geo, body_begin, n_body, child_begin, n_child, parent};
+    for (void *p : ptrs)
+      if (p) (void)hipFree(p);
+    *this = DevTree();
+  }
+};
+
+struct DevLists {
+  int device = -1;
+  bool uploaded = false;
+  fmmlib::P2PPlan plan;
+  std::vector<int32_t> m2l_rows_host;
+  int64_t *m2l_ptr = nullptr;
+  int32_t *m2l_col = nullptr, *m2l_rows = nullptr;
+  fmmlib::P2PItem *items = nullptr;
+  int32_t *run_body = nullptr, *run_prefix = nullptr;
+  int32_t *leaf_cell = nullptr, *leaf_pbase = nullptr, *leaf_nchunk = nullptr, *body_leaf = nullptr;
+  // scratch for one (p, precision, top) configuration
+  int p = 0, prec = -1;
+  int64_t n_top = -1;
+  void *M = nullptr, *L = nullptr, *Lstage = nullptr;
+  double *M64 = nullptr, *L64 = nullptr, *L64stage = nullptr;
+  void *part_s = nullptr, *part_c = nullptr;
+  void *tmp_phi = nullptr, *tmp_grad = nullptr;
+  bool stage_valid = false;
+  // timing
+  hipEvent_t ev[FMM_NUM_PHASES] = {};
+  bool have_events = false, timing_valid = false;
+  void release_scratch() {
+    void *ptrs[] = {M, L, Lstage, M64, L64, L64stage, part_s, part_c, tmp_phi, tmp_grad};
+    for (void *p2 : ptrs)
+      if (p2) (void)hipFree(p2);
+    M = L = Lstage = part_s = part_c = tmp_phi = tmp_grad = nullptr;
+    M64 = L64 = L64stage = nullptr;
+    p = 0;
+    prec = -1;
+    n_top = -1;
+    stage_valid = false;
+  }
+  void release() {
+    release_scratch();
+    void *ptrs[] = {m2l_ptr, m2l_col, m2l_rows, items, run_body, run_prefix,
+                    leaf_cell, leaf_pbase, leaf_nchunk, body_leaf};
+    for (void *p2 : ptrs)
+      if (p2) (void)hipFree(p2);
+    if (have_events)
+      for (auto &e : ev) (void)hipEventDestroy(e);
+    *this = DevLists();
+  }
+};
+
+}  // namespace
+
+struct fmm_tree {
+  fmmlib::TreeData data;
+  DevTree dev;
+};
+
+struct fmm_lists {
+  fmmlib::ListData data;
+  DevLists dev;
+};
+
+namespace {
+
+int hip_fail(hipError_t e, const char *what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? FMM_ENOMEM : FMM_EDEVICE;
+}
+
+#define HIP_TRY(call)                                 \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+#define LAUNCH_TRY(call)                                                        \
+  do {                                                                          \
+    const int tgt_ = fault_launch_target();                                     \
+    if (tgt_ > 0 && ++g_launch_counter == tgt_) {                               \
+      set_error(std::string("injected device fault before ") + #call);          \
+      return FMM_EDEVICE;                                                       \
+    }                                                                           \
+    int e_ = (call);                                                            \
+    if (e_ != 0) return hip_fail((hipError_t)e_, #call);                        \
+  } while (0)
+
+template <typename T>
+int dev_upload(T **dst, const T *src, size_t count) {
+  // Empty arrays still get a valid (one-element) allocation.
+  HIP_TRY(hipMalloc((void **)dst, std::max<size_t>(1, count) * sizeof(T)));
+  if (src && count > 0) HIP_TRY(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return FMM_OK;
+}
+
+int current_device(int *dev) {
+  HIP_TRY(hipGetDevice(dev));
+  return FMM_OK;
+}
+
+int ensure_tree_device(fmm_tree *t, bool fp64) {
+  const fmmlib::TreeData &d = t->data;
+  DevTree &dv = t->dev;
+  int dev;
+  if (int rc = current_device(&dev)) return rc;
+  if (dv.device >= 0 && dv.device != dev) {
+    set_error("tree was first used on another device");
+    return FMM_ESTATE;
+  }
+  if (dv.device < 0) {
+    dv.device = dev;
+    dv.n = d.n;
+    dv.n_cells = d.n_cells();
+    const int64_t nc = d.n_cells();
+    std::vector<double> geo(4 * nc);
+    std::vector<int32_t> bb(nc), nb(nc);
+    for (int64_t c = 0; c < nc; ++c) {
+      for (int k = 0; k < 3; ++k) geo[4 * c + k] = d.center[3 * c + k];
+      geo[4 * c + 3] = d.radius[c];
+      bb[c] = (int32_t)d.body_begin[c];
+      nb[c] = (int32_t)d.n_body[c];
+    }
+    if (int rc = dev_upload(&dv.perm, d.perm.data(), d.n)) return rc;
+    if (int rc = dev_upload(&dv.geo, geo.data(), 4 * nc)) return rc;
+    if (int rc = dev_upload(&dv.body_begin, bb.data(), nc)) return rc;
+    if (int rc = dev_upload(&dv.n_body, nb.data(), nc)) return rc;
+    if (int rc = dev_upload(&dv.child_begin, d.child_begin.data(), nc)) return rc;
+    if (int rc = dev_upload(&dv.n_child, d.n_child.data(), nc)) return rc;
+    if (int rc = dev_upload(&dv.parent, d.parent.data(), nc)) return rc;
+  }
+  if (fp64 && dv.pos_version_64 != d.pos_version) {
+    std::vector<double> b(4 * d.n);
+    for (int64_t i = 0; i < d.n; ++i) {
+      for (int k = 0; k < 3; ++k) b[4 * i + k] = d.pos[3 * i + k];
+      b[4 * i + 3] = 0.0;
+    }
+    if (!dv.b64) HIP_TRY(hipMalloc(&dv.b64, std::max<int64_t>(1, d.n) * 32));
+    HIP_TRY(hipMemcpy(dv.b64, b.data(), d.n * 32, hipMemcpyHostToDevice));
+    dv.pos_version_64 = d.pos_version;
+  }
+  if (!fp64 && dv.pos_version_32 != d.pos_version) {
+    std::vector<float> b(4 * d.n);
+    for (int64_t i = 0; i < d.n; ++i) {
+      for (int k = 0; k < 3; ++k) b[4 * i + k] = (float)d.pos[3 * i + k];
+      b[4 * i + 3] = 0.0f;
+    }
+    if (!dv.b32) HIP_TRY(hipMalloc(&dv.b32, std::max<int64_t>(1, d.n) * 16));
+    HIP_TRY(hipMemcpy(dv.b32, b.data(), d.n * 16, hipMemcpyHostToDevice));
+    dv.pos_version_32 = d.pos_version;
+  }
+  return FMM_OK;
+}
+
+int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
+  DevLists &dv = l->dev;
+  if (dv.uploaded) {
+    if (dv.device != t->dev.device) {
+      set_error("lists were first used on another device");
+      return FMM_ESTATE;
+    }
+    return FMM_OK;
+  }
+  const fmmlib::TreeData &td = t->data;
+  const fmmlib::ListData &ld = l->data;
+  fmmlib::build_p2p_plan(td, ld, dv.plan);
+  for (int64_t a = 0; a < ld.n_rows; ++a)
+    if (ld.m2l_ptr[a + 1] > ld.m2l_ptr[a]) dv.m2l_rows_host.push_back((int32_t)a);
+  const auto &pl = dv.plan;
+  if (int rc = dev_upload(&dv.m2l_ptr, ld.m2l_ptr.data(), ld.m2l_ptr.size())) return rc;
+  if (int rc = dev_upload(&dv.m2l_col, ld.m2l_col.data(), ld.m2l_col.size())) return rc;
+  if (int rc = dev_upload(&dv.m2l_rows, dv.m2l_rows_host.data(), dv.m2l_rows_host.size()))
+    return rc;
+  if (int rc = dev_upload(&dv.items, pl.items.data(), pl.items.size())) return rc;
+  if (int rc = dev_upload(&dv.run_body, pl.run_body.data(), pl.run_body.size())) return rc;
+  if (int rc = dev_upload(&dv.run_prefix, pl.run_prefix.data(), pl.run_prefix.size())) return rc;
+  if (int rc = dev_upload(&dv.leaf_cell, pl.leaf_cell.data(), pl.leaf_cell.size())) return rc;
+  if (int rc = dev_upload(&dv.leaf_pbase, pl.leaf_pbase.data(), pl.leaf_pbase.size())) return rc;
+  if (int rc = dev_upload(&dv.leaf_nchunk, pl.leaf_nchunk.data(), pl.leaf_nchunk.size()))
+    return rc;
+  if (int rc = dev_upload(&dv.body_leaf, pl.body_leaf.data(), pl.body_leaf.size())) return rc;
+  dv.device = t->dev.device;
+  dv.uploaded = true;
+  return FMM_OK;
+}
+
+int64_t top_cells(const fmmlib::TreeData &t, const fmm_eval_opts *o) {
+  if (o->precision != FMM_MIXED) return 0;
+  int top = o->fp64_top_levels;
+  if (top == -1) top = o->p >= 8 ? 3 : -1;
+  if (top < 0) return 0;
+  top = std::min(top, t.max_level);
+  return t.level_begin[top + 1];
+}
+
+int ensure_scratch(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o) {
+  DevLists &dv = l->dev;
+  const bool fp64 = o->precision == FMM_FP64;
+  const int64_t n_top = top_cells(t->data, o);
+  if (dv.p == o->p && dv.prec == o->precision && dv.n_top == n_top) return FMM_OK;
+  dv.release_scratch();
+  const int64_t nc = t->data.n_cells(), n = t->data.n;
+  const size_t real = fp64 ? 8 : 4;
+  const size_t coef = (size_t)nc * fmmlib::dev::stride(o->p);
+  HIP_TRY(hipMalloc(&dv.M, coef * real));
+  HIP_TRY(hipMalloc(&dv.L, coef * real));
+  HIP_TRY(hipMalloc(&dv.Lstage, coef * real));
+  if (n_top > 0) {
+    const size_t tc = (size_t)n_top * fmmlib::dev::stride(o->p);
+    HIP_TRY(hipMalloc((void **)&dv.M64, tc * 8));
+    HIP_TRY(hipMalloc((void **)&dv.L64, tc * 8));
+    HIP_TRY(hipMalloc((void **)&dv.L64stage, tc * 8));
+  }
+  const size_t np = std::max<int64_t>(1, dv.plan.n_partials);
+  HIP_TRY(hipMalloc(&dv.part_s, np * 4 * real));
+  if (!fp64) HIP_TRY(hipMalloc(&dv.part_c, np * 4 * real));
+  HIP_TRY(hipMalloc(&dv.tmp_phi, std::max<int64_t>(1, n) * real));
+  HIP_TRY(hipMalloc(&dv.tmp_grad, std::max<int64_t>(1, n) * 3 * real));
+  dv.p = o->p;
+  dv.prec = o->precision;
+  dv.n_top = n_top;
+  return FMM_OK;
+}
+
+int check_opts(const fmm_eval_opts *o) {
+  if (!o) {
+    set_error("opts is NULL");
+    return FMM_EINVAL;
+  }
+  if (o->p < 1 || o->p > FMM_MAX_P) {
+    set_error("p must be in 1..8");
+    return FMM_EINVAL;
+  }
+  if (o->precision != FMM_MIXED && o->precision != FMM_FP64) {
+    set_error("precision must be FMM_MIXED or FMM_FP64");
+    return FMM_EINVAL;
+  }
+  if (o->fp64_top_levels < -2 || o->fp64_top_levels > FMM_MAX_LEVEL) {
+    set_error("fp64_top_levels must be -2, -1 or 0..21");
+    return FMM_EINVAL;
+  }
+  if (o->flags & ~(FMM_EVAL_TIMING | FMM_EVAL_KEEP_STAGES)) {
+    set_error("unknown evaluation flags");
+    return FMM_EINVAL;
+  }
+  return FMM_OK;
+}
+
+int check_pair(const fmm_tree *t, const fmm_lists *l) {
+  if (!t || !l) {
+    set_error("tree or lists is NULL");
+    return FMM_EINVAL;
+  }
+  if (l->data.tree_id != t->data.id) {
+    set_error("lists were built from another tree");
+    return FMM_ESTATE;
+  }
+  return FMM_OK;
+}
+
+// Enqueue one forward evaluation; outputs in user order.
+int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void *q, void *phi,
+                  void *grad, void *stream) {
+  namespace D = fmmlib::dev;
+  const fmmlib::TreeData &td = t->data;
+  const bool fp64 = o->precision == FMM_FP64;
+  if (int rc = ensure_tree_device(t, fp64)) return rc;
+  if (int rc = ensure_lists_device(t, l)) return rc;
+  if (int rc = ensure_scratch(t, l, o)) return rc;
+  DevLists &dv = l->dev;
+  DevTree &dt = t->dev;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool timing = (o->flags & FMM_EVAL_TIMING) != 0;
+  if (timing && !dv.have_events) {
+    for (int k = 0; k < FMM_NUM_PHASES; ++k) HIP_TRY(hipEventCreate(&dv.ev[k]));
+    dv.have_events = true;
+  }
+  dv.timing_valid = false;
+  g_launch_counter = 0;
+  auto mark = [&](int k) -> int {
+    if (timing) HIP_TRY(hipEventRecord(dv.ev[k], s));
+    return FMM_OK;
+  };
+  const int p = o->p;
+  const int S = D::stride(p);
+  void *bodies = fp64 ? dt.b64 : dt.b32;
+  const auto &pl = dv.plan;
+  const int64_t n_top = dv.n_top;
+  const int max_level = td.max_level;
+  const double *geo = dt.geo;
+  const size_t real = fp64 ? 8 : 4;
+
+  if (int rc = mark(0)) return rc;
+  LAUNCH_TRY(D::gather_charges(fp64, td.n, dt.perm, q, bodies, stream));
+  if (int rc = mark(1)) return rc;
+  // Bodies of different leaves never coincide for a tree built from these
+  // positions (equal positions share a key, hence a leaf), nor in FP32 when
+  // every position is FP32-representable; otherwise test every pair.
+  const bool mask_all = td.moved || (!fp64 && !td.fp32_exact);
+  LAUNCH_TRY(D::p2p(fp64, mask_all, (int64_t)pl.items.size(), dv.items,
+                    dv.run_body, dv.run_prefix, bodies, dv.part_s, dv.part_c, stream));
+  if (int rc = mark(2)) return rc;
+  LAUNCH_TRY(D::p2m(p, fp64, (int64_t)pl.leaf_cell.size(), dv.leaf_cell, dt.body_begin, dt.n_body,
+                    geo, bodies, dv.M, dv.M64, n_top, stream));
+  if (int rc = mark(3)) return rc;
+  for (int lev = max_level - 1; lev >= 0; --lev) {
+    const int64_t c0 = td.level_begin[lev], c1 = td.level_begin[lev + 1];
+    const bool out64 = c1 <= n_top;        // this level is kept in FP64
+    const bool child64 = td.level_begin[lev + 2] <= n_top;
+    LAUNCH_TRY(D::m2m(p, fp64, c0, c1, dt.child_begin, dt.n_child, geo, dv.M, dv.M64, child64,
+                      out64, stream));
+  }
+  if (int rc = mark(4)) return rc;
+  LAUNCH_TRY(D::zero(dv.L, (int64_t)td.n_cells() * S * real, stream));
+  if (n_top > 0) LAUNCH_TRY(D::zero(dv.L64, n_top * S * 8, stream));
+  {
+    const auto &rows = dv.m2l_rows_host;
+    const int64_t split =
+        std::lower_bound(rows.begin(), rows.end(), (int32_t)n_top) - rows.begin();
+    if (split > 0)
+      LAUNCH_TRY(D::m2l(p, fp64, 0, split, dv.m2l_rows, dv.m2l_ptr, dv.m2l_col, geo, dv.M, dv.L,
+                        dv.L64, true, stream));
+    LAUNCH_TRY(D::m2l(p, fp64, split, (int64_t)rows.size(), dv.m2l_rows, dv.m2l_ptr, dv.m2l_col,
+                      geo, dv.M, dv.L, dv.L64, false, stream));
+  }
+  if (o->flags & FMM_EVAL_KEEP_STAGES) {
+    HIP_TRY(hipMemcpyAsync(dv.Lstage, dv.L, (size_t)td.n_cells() * S * real,
+                           hipMemcpyDeviceToDevice, s));
+    if (n_top > 0)
+      HIP_TRY(hipMemcpyAsync(dv.L64stage, dv.L64, (size_t)n_top * S * 8, hipMemcpyDeviceToDevice,
+                             s));
+    dv.stage_valid = true;
+  } else {
+    dv.stage_valid = false;
+  }
+  if (int rc = mark(5)) return rc;
+  for (int lev = 1; lev <= max_level; ++lev) {
+    const int64_t c0 = td.level_begin[lev], c1 = td.level_begin[lev + 1];
+    const bool parent64 = td.level_begin[lev] <= n_top && n_top > 0;
+    const bool child64 = c1 <= n_top;
+    LAUNCH_TRY(D::l2l(p, fp64, c0, c1, dt.parent, geo, dv.L, dv.L64, parent64, child64, stream));
+  }
+  if (n_top > 0) LAUNCH_TRY(D::copy_top_locals(p, n_top, dv.L64, (float *)dv.L, stream));
+  if (int rc = mark(6)) return rc;
+  LAUNCH_TRY(D::l2p_combine(p, fp64, td.n, dv.body_leaf, dv.leaf_cell, dv.leaf_pbase,
+                            dv.leaf_nchunk, dt.body_begin, dt.n_body, geo, dv.L, bodies,
+                            dv.part_s, dv.part_c, dt.perm, phi, grad, stream));
+  if (int rc = mark(7)) return rc;
+  dv.timing_valid = timing;
+  return FMM_OK;
+}
+
+// Library ordering of expansion terms: by degree, then z exponent, then y.
+void term_exps(int p, int32_t *e) {
+  int t = 0;
+  for (int d = 0; d < p; ++d)
+    for (int c = 0; c <= d; ++c)
+      for (int b = 0; b <= d - c; ++b) {
+        e[3 * t] = d - b - c;
+        e[3 * t + 1] = b;
+        e[3 * t + 2] = c;
+        ++t;
+      }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fmm_last_error(void) { return g_error.c_str(); }
+
+int fmm_num_terms(int p) { return (p < 1 || p > FMM_MAX_P) ? -1 : fmmlib::dev::terms(p); }
+
+int fmm_term_exponents(int p, int32_t *exps) {
+  if (p < 1 || p > FMM_MAX_P || !exps) {
+    set_error("fmm_term_exponents: bad argument");
+    return FMM_EINVAL;
+  }
+  term_exps(p, exps);
+  return FMM_OK;
+}
+
+int fmm_tree_build(const double *xyz, int64_t n, int ncrit, fmm_tree **out) {
+  if (!out || n < 0 || ncrit < 1 || (n > 0 && !xyz)) {
+    set_error("fmm_tree_build: need out != NULL, n >= 0, ncrit >= 1, xyz != NULL");
+    return FMM_EINVAL;
+  }
+  if (n > (int64_t)INT32_MAX - 1) {
+    set_error("fmm_tree_build: n must be below 2^31 - 1");
+    return FMM_EINVAL;
+  }
+  *out = nullptr;
+  fmm_tree *t = nullptr;
+  try {
+    t = new fmm_tree();
+    std::string err;
+    const int rc = fmmlib::build_tree(xyz, n, ncrit, t->data, err);
+    if (rc != FMM_OK) {
+      delete t;
+      set_error(err);
+      return rc;
+    }
+  } catch (const std::bad_alloc &) {
+    delete t;
+    set_error("fmm_tree_build: out of host memory");
+    return FMM_ENOMEM;
+  }
+  t->data.id = g_next_tree_id++;
+  *out = t;
+  return FMM_OK;
+}
+
+int fmm_tree_set_positions(fmm_tree *t, const double *xyz) {
+  if (!t || (t->data.n > 0 && !xyz)) {
+    set_error("fmm_tree_set_positions: bad argument");
+    return FMM_EINVAL;
+  }
+  fmmlib::TreeData &d = t->data;
+  for (int64_t i = 0; i < 3 * d.n; ++i)
+    if (!std::isfinite(xyz[i])) {
+      set_error("fmm_tree_set_positions: positions must be finite");
+      return FMM_EINVAL;
+    }
+  for (int64_t i = 0; i < d.n; ++i)
+    for (int k = 0; k < 3; ++k) d.pos[3 * i + k] = xyz[3 * (int64_t)d.perm[i] + k];
+  // Moved bodies may now coincide with bodies of other leaves: from here on
+  // every P2P pair is tested for zero distance.
+  d.moved = true;
+  d.pos_version++;
+  return FMM_OK;
+}
+
+int fmm_tree_view(const fmm_tree *t, fmm_tree_view_t *v) {
+  if (!t || !v) {
+    set_error("fmm_tree_view: NULL argument");
+    return FMM_EINVAL;
+  }
+  const fmmlib::TreeData &d = t->data;
+  v->n = d.n;
+  v->n_cells = d.n_cells();
+  v->n_leaves = d.n_leaves;
+  v->max_level = d.max_level;
+  v->fp32_exact = d.fp32_exact ? 1 : 0;
+  v->perm = d.perm.data();
+  v->keys = d.keys.data();
+  v->level = d.level.data();
+  v->parent = d.parent.data();
+  v->child_begin = d.child_begin.data();
+  v->n_child = d.n_child.data();
+  v->body_begin = d.body_begin.data();
+  v->n_body = d.n_body.data();
+  v->center = d.center.data();
+  v->radius = d.radius.data();
+  return FMM_OK;
+}
+
+void fmm_tree_free(fmm_tree *t) {
+  if (!t) return;
+  t->dev.release();
+  delete t;
+}
+
+int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out) {
+  if (!t || !out) {
+    set_error("fmm_traverse: NULL argument");
+    return FMM_EINVAL;
+  }
+  if (!(theta > 0.0 && theta < 1.0)) {
+    set_error("fmm_traverse: theta must be in (0, 1)");
+    return FMM_EINVAL;
+  }
+  if (flags & ~(unsigned)FMM_LEAF_FIRST) {
+    set_error("fmm_traverse: unknown flags");
+    return FMM_EINVAL;
+  }
+  *out = nullptr;
+  fmm_lists *l = nullptr;
+  try {
+    l = new fmm_lists();
+    fmmlib::dual_traverse(t->data, theta, (flags & FMM_LEAF_FIRST) != 0, l->data);
+  } catch (const std::bad_alloc &) {
+    delete l;
+    set_error("fmm_traverse: out of host memory");
+    return FMM_ENOMEM;
+  }
+  *out = l;
+  return FMM_OK;
+}
+
+int fmm_lists_view(const fmm_lists *l, int kind, const int64_t **row_ptr, const int32_t **col,
+                   int64_t *nrows, int64_t *nnz) {
+  if (!l || !row_ptr || !col || !nrows || !nnz || (kind != FMM_P2P && kind != FMM_M2L)) {
+    set_error("fmm_lists_view: bad argument");
+    return FMM_EINVAL;
+  }
+  const fmmlib::ListData &d = l->data;
+  *row_ptr = kind == FMM_P2P ? d.p2p_ptr.data() : d.m2l_ptr.data();
+  *col = kind == FMM_P2P ? d.p2p_col.data() : d.m2l_col.data();
+  *nrows = d.n_rows;
+  *nnz = (int64_t)(kind == FMM_P2P ? d.p2p_col.size() : d.m2l_col.size());
+  return FMM_OK;
+}
+
+int fmm_lists_stats(const fmm_lists *l, fmm_lists_stats_t *s) {
+  if (!l || !s) {
+    set_error("fmm_lists_stats: NULL argument");
+    return FMM_EINVAL;
+  }
+  s->p2p_entries = (int64_t)l->data.p2p_col.size();
+  s->m2l_entries = (int64_t)l->data.m2l_col.size();
+  s->p2p_pairs = l->data.p2p_pairs;
+  s->p2p_work_items = (int64_t)l->dev.plan.items.size();
+  s->p2p_max_row_sources = l->data.max_row_sources;
+  return FMM_OK;
+}
+
+void fmm_lists_free(fmm_lists *l) {
+  if (!l) return;
+  l->dev.release();
+  delete l;
+}
+
+int fmm_evaluate(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o, const void *q_dev,
+                 void *phi_dev, void *grad_dev, void *stream) {
+  if (int rc = check_pair(t, l)) return rc;
+  if (int rc = check_opts(o)) return rc;
+  if (t->data.n == 0) return FMM_OK;
+  if (!q_dev || !phi_dev) {
+    set_error("fmm_evaluate: q and phi must not be NULL");
+    return FMM_EINVAL;
+  }
+  try {
+    return evaluate_impl(const_cast<fmm_tree *>(t), const_cast<fmm_lists *>(l), o, q_dev, phi_dev,
+                         grad_dev, stream);
+  } catch (const std::bad_alloc &) {
+    set_error("fmm_evaluate: out of host memory");
+    return FMM_ENOMEM;
+  }
+}
+
+int fmm_evaluate_backward(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o,
+                          const void *q_dev, const void *grad_q_dev, const void *w_dev,
+                          void *dq_dev, void *dx_dev, void *stream) {
+  if (int rc = check_pair(t, l)) return rc;
+  if (int rc = check_opts(o)) return rc;
+  if (t->data.n == 0) return FMM_OK;
+  if (!w_dev || (dx_dev && (!q_dev || !grad_q_dev))) {
+    set_error("fmm_evaluate_backward: w is required; dx needs q and grad_q");
+    return FMM_EINVAL;
+  }
+  if (!dq_dev && !dx_dev) return FMM_OK;
+  fmm_tree *tt = const_cast<fmm_tree *>(t);
+  fmm_lists *ll = const_cast<fmm_lists *>(l);
+  try {
+    const bool fp64 = o->precision == FMM_FP64;
+    if (int rc = ensure_tree_device(tt, fp64)) return rc;
+    if (int rc = ensure_lists_device(tt, ll)) return rc;
+    if (int rc = ensure_scratch(tt, ll, o)) return rc;
+    void *phi_w = dq_dev ? dq_dev : ll->dev.tmp_phi;
+    void *grad_w = dx_dev ? ll->dev.tmp_grad : nullptr;
+    if (int rc = evaluate_impl(tt, ll, o, w_dev, phi_w, grad_w, stream)) return rc;
+    if (dx_dev)
+      LAUNCH_TRY(fmmlib::dev::backward_combine(fp64, t->data.n, q_dev, w_dev, grad_q_dev, grad_w,
+                                               dx_dev, stream));
+    return FMM_OK;
+  } catch (const std::bad_alloc &) {
+    set_error("fmm_evaluate_backward: out of host memory");
+    return FMM_ENOMEM;
+  }
+}
+
+int fmm_direct(const void *xyz_dev, const void *q_dev, int64_t n, const int64_t *targets_dev,
+               int64_t m, void *phi_dev, void *grad_dev, void *stream) {
+  if (n < 0 || m < 0 || (m > 0 && (!xyz_dev || !q_dev || !targets_dev || !phi_dev))) {
+    set_error("fmm_direct: bad argument");
+    return FMM_EINVAL;
+  }
+  if (m > (int64_t)INT32_MAX) {
+    set_error("fmm_direct: too many targets");
+    return FMM_EINVAL;
+  }
+  LAUNCH_TRY(fmmlib::dev::direct_sum((const double *)xyz_dev, (const double *)q_dev, n,
+                                     targets_dev, m, (double *)phi_dev, (double *)grad_dev,
+                                     stream));
+  return FMM_OK;
+}
+
+int fmm_last_timings(const fmm_lists *l, double *ms) {
+  if (!l || !ms) {
+    set_error("fmm_last_timings: NULL argument");
+    return FMM_EINVAL;
+  }
+  const DevLists &dv = l->dev;
+  if (!dv.timing_valid) {
+    set_error("fmm_last_timings: last evaluation was not timed");
+    return FMM_ESTATE;
+  }
+  HIP_TRY(hipEventSynchronize(dv.ev[7]));
+  for (int k = 0; k < 7; ++k) {
+    float f = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&f, dv.ev[k], dv.ev[k + 1]));
+    ms[k] = f;
+  }
+  float tot = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&tot, dv.ev[0], dv.ev[7]));
+  ms[FMM_PHASE_TOTAL] = tot;
+  return FMM_OK;
+}
+
+int fmm_copy_expansions(const fmm_lists *l, int kind, double *dst) {
+  if (!l || !dst || kind < 0 || kind > 2) {
+    set_error("fmm_copy_expansions: bad argument");
+    return FMM_EINVAL;
+  }
+  const DevLists &dv = l->dev;
+  if (dv.p == 0) {
+    set_error("fmm_copy_expansions: no evaluation yet");
+    return FMM_ESTATE;
+  }
+  if (kind == 1 && !dv.stage_valid) {
+    set_error("fmm_copy_expansions: evaluate with FMM_EVAL_KEEP_STAGES first");
+    return FMM_ESTATE;
+  }
+  const int T = fmmlib::dev::terms(dv.p), S = fmmlib::dev::stride(dv.p);
+  const int64_t nc = l->data.n_rows;
+  const void *src = kind == 0 ? dv.M : (kind == 1 ? dv.Lstage : dv.L);
+  const double *src64 = kind == 0 ? dv.M64 : (kind == 1 ? dv.L64stage : dv.L64);
+  HIP_TRY(hipDeviceSynchronize());
+  if (dv.prec == FMM_FP64) {
+    std::vector<double> h((size_t)nc * S);
+    HIP_TRY(hipMemcpy(h.data(), src, h.size() * 8, hipMemcpyDeviceToHost));
+    for (int64_t c = 0; c < nc; ++c)
+      for (int t = 0; t < T; ++t) dst[c * T + t] = h[c * S + t];
+  } else {
+    std::vector<float> h((size_t)nc * S);
+    HIP_TRY(hipMemcpy(h.data(), src, h.size() * 4, hipMemcpyDeviceToHost));
+    for (int64_t c = 0; c < nc; ++c)
+      for (int t = 0; t < T; ++t) dst[c * T + t] = h[c * S + t];
+    if (dv.n_top > 0) {
+      std::vector<double> h64((size_t)dv.n_top * S);
+      HIP_TRY(hipMemcpy(h64.data(), src64, h64.size() * 8, hipMemcpyDeviceToHost));
+      for (int64_t c = 0; c < dv.n_top; ++c)
+        for (int t = 0; t < T; ++t) dst[c * T + t] = h64[c * S + t];
+    }
+  }
+  return FMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal host-side data structures of the GPU FMM library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fmm.h"
+
+namespace fmmlib {
+
+// Octree in Morton order, cells numbered breadth first (section 3.3).
+struct TreeData {
+  int64_t n = 0;
+  int ncrit = 0;
+  int max_level = 0;
+  int64_t n_leaves = 0;
+  bool fp32_exact = true;
+  bool moved = false;        // positions replaced after the build
+  uint64_t id = 0;           // identifies the tree for lists built from it
+  uint64_t pos_version = 0;  // bumped by set_positions
+  double root_center[3] = {0, 0, 0};
+  double root_half = 0.0;
+  std::vector<double> pos;  // [n][3] positions in Morton order
+  std::vector<int32_t> perm;
+  std::vector<uint64_t> keys;
+  std::vector<int32_t> level, parent, child_begin, n_child;
+  std::vector<int64_t> body_begin, n_body;
+  std::vector<double> center, radius;  // center [n_cells][3]
+  std::vector<int64_t> level_begin;    // cells of level L: [level_begin[L], level_begin[L+1])
+  int64_t n_cells() const { return (int64_t)level.size(); }
+};
+
+// The two interaction lists as CSR, one row per target cell.
+struct ListData {
+  uint64_t tree_id = 0;
+  double theta = 0.0;
+  unsigned flags = 0;
+  int64_t n_rows = 0;
+  std::vector<int64_t> p2p_ptr, m2l_ptr;
+  std::vector<int32_t> p2p_col, m2l_col;
+  int64_t p2p_pairs = 0;
+  int64_t max_row_sources = 0;
+};
+
+// GPU work plan of the P2P kernel.  A work item is one group of at most 64
+// target bodies of one leaf against one chunk of that leaf's source leaves.
+// Source leaves whose bodies are contiguous in Morton order are merged into
+// runs.  The self pair (A, A) is kept out of the runs and handled with a
+// zero-distance mask.
+struct P2PItem {
+  int32_t tgt_begin;  // first target body (Morton position)
+  int32_t tgt_cfg;    // n_tgt | R << 8 | L << 16 | K << 24 (lane layout)
+  int32_t run_begin;  // first run of this item
+  int32_t n_runs;
+  int32_t n_src;       // source bodies in the runs
+  int32_t self_begin;  // first body of the target leaf if this item holds (A, A)
+  int32_t self_n;      // 0 if not
+  int32_t out_off;     // partial-sum slot of the item's first target
+};
+
+struct P2PPlan {
+  std::vector<P2PItem> items;
+  std::vector<int32_t> run_body;    // first body of each run
+  std::vector<int32_t> run_prefix;  // offset of each run within its item's source list
+  // Per leaf (compact numbering in cell order): cell id, first partial slot,
+  // number of source chunks.  Body b of leaf a, chunk c uses partial slot
+  // leaf_pbase[a] + c * n_body + (b - body_begin).
+  std::vector<int32_t> leaf_cell, leaf_pbase, leaf_nchunk;
+  std::vector<int32_t> body_leaf;  // Morton body -> compact leaf
+  int64_t n_partials = 0;
+  int32_t max_row_sources = 0;
+};
+
+// Lane layout of a P2P work item with nt targets: K streams of L lanes, each
+// lane holding R targets (R*L >= nt, K*L <= 64).
+void p2p_lane_layout(int nt, int *R, int *L, int *K);
+
+constexpr int kP2PMaxRuns = 256;
+constexpr int kP2PChunkSources = 8192;
+
+int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string &err);
+void dual_traverse(const TreeData &t, double theta, bool leaf_first, ListData &l);
+void build_p2p_plan(const TreeData &t, const ListData &l, P2PPlan &plan);
+
+}  // namespace fmmlib

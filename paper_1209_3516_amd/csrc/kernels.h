@@ -1,0 +1,64 @@
+// Host-side launchers of the gfx950 kernels (implemented in kernels.hip).
+// Plain pointers and sizes only; every launcher enqueues on `stream`
+// (a hipStream_t) and returns the hipError_t of the launch as an int.
+#pragma once
+
+#include <cstdint>
+
+#include "fmm_internal.h"
+
+namespace fmmlib {
+namespace dev {
+
+// Expansion coefficients per cell are stored with a row stride padded to a
+// multiple of 4 (16-byte rows for FP32).
+inline int terms(int p) { return p * (p + 1) * (p + 2) / 6; }
+inline int stride(int p) { return (terms(p) + 3) & ~3; }
+
+// bodies: [n] float4/double4 (x, y, z, q) in Morton order.
+int gather_charges(bool fp64, int64_t n, const int32_t *perm, const void *q_user, void *bodies,
+                   void *stream);
+
+int p2p(bool fp64, bool mask_all, int64_t n_items, const P2PItem *items, const int32_t *run_body,
+        const int32_t *run_prefix, const void *bodies, void *part_s, void *part_c, void *stream);
+
+// geo: [n_cells] double4 (centre x, y, z, radius).
+int p2m(int p, bool fp64, int64_t n_leaves, const int32_t *leaf_cell, const int32_t *cell_body_begin,
+        const int32_t *cell_n_body, const double *geo, const void *bodies, void *M, double *M64,
+        int64_t n_top, void *stream);
+
+// Parents are the cells [c0, c1) of one level; leaves among them are skipped.
+// child_fp64: children's multipoles are read from M64 (else from M).
+// out_fp64: the parent is accumulated in FP64 into M64 and copied to M.
+int m2m(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *child_begin,
+        const int32_t *n_child, const double *geo, void *M, double *M64, bool child_fp64,
+        bool out_fp64, void *stream);
+
+// Rows [r0, r1) of `rows` (target cells with M2L entries); acc_fp64: the row
+// accumulates in FP64 into L64, else into L (FP32 in mixed mode).
+int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int32_t *rows, const int64_t *ptr,
+        const int32_t *col, const double *geo, const void *M, void *L, double *L64,
+        bool acc_fp64, void *stream);
+
+// Children are the cells [c0, c1) of one level.
+int l2l(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *parent, const double *geo,
+        void *L, double *L64, bool parent_fp64, bool child_fp64, void *stream);
+
+int copy_top_locals(int p, int64_t n_top, const double *L64, float *L, void *stream);
+
+int l2p_combine(int p, bool fp64, int64_t n, const int32_t *body_leaf, const int32_t *leaf_cell,
+                const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
+                const int32_t *cell_body_begin, const int32_t *cell_n_body, const double *geo,
+                const void *L, const void *bodies, const void *part_s, const void *part_c,
+                const int32_t *perm, void *phi, void *grad, void *stream);
+
+int backward_combine(bool fp64, int64_t n, const void *q, const void *w, const void *grad_q,
+                     const void *grad_w, void *dx, void *stream);
+
+int zero(void *ptr, int64_t bytes, void *stream);
+
+int direct_sum(const double *xyz, const double *q, int64_t n, const int64_t *targets, int64_t m,
+               double *phi, double *grad, void *stream);
+
+}  // namespace dev
+}  // namespace fmmlib

@@ -1,0 +1,113 @@
+// Work plan of the GPU P2P kernel, built once per (tree, lists) on the host.
+#include <cmath>
+
+#include "fmm_internal.h"
+
+namespace fmmlib {
+
+// Lane layout for a work item of nt <= 64 targets on one 64-lane wave:
+// K source streams of L lanes; lane (s, u) holds targets u, u+L, ..., u+(R-1)L
+// and visits every K-th staged source.  Maximise the useful fraction
+// nt*K / (64*R) of lane-pair slots; on ties take the larger R (more targets
+// per staged source read).
+void p2p_lane_layout(int nt, int *R, int *L, int *K) {
+  double best = -1.0;
+  int bR = 1, bL = nt, bK = 1;
+  for (int r = 1; r <= 8; ++r) {
+    const int l = (nt + r - 1) / r;
+    if (l > 64) continue;
+    const int k = 64 / l;
+    const double eff = (double)nt * k / (64.0 * r);
+    if (eff > best + 1e-12 || std::fabs(eff - best) <= 1e-12) {
+      best = eff;
+      bR = r;
+      bL = l;
+      bK = k;
+    }
+  }
+  *R = bR;
+  *L = bL;
+  *K = bK;
+}
+
+void build_p2p_plan(const TreeData &t, const ListData &l, P2PPlan &plan) {
+  plan = P2PPlan();
+  const int64_t nc = t.n_cells();
+  plan.body_leaf.assign(t.n, 0);
+  int64_t pbase = 0;
+  for (int64_t a = 0; a < nc; ++a) {
+    if (t.n_child[a] != 0) continue;
+    const int32_t leaf = (int32_t)plan.leaf_cell.size();
+    const int64_t nA = t.n_body[a], bA = t.body_begin[a];
+    for (int64_t i = bA; i < bA + nA; ++i) plan.body_leaf[i] = leaf;
+
+    // Split the row into source chunks of at most kP2PChunkSources bodies and
+    // kP2PMaxRuns runs; merge entries with contiguous bodies into runs.
+    struct Chunk {
+      int32_t run_begin = 0, n_runs = 0, n_src = 0;
+      bool self = false;
+    };
+    std::vector<Chunk> chunks;
+    Chunk cur;
+    cur.run_begin = (int32_t)plan.run_body.size();
+    int64_t last_end = -1;  // body end of the last run of the current chunk
+    int64_t row_src = 0;
+    for (int64_t e = l.p2p_ptr[a]; e < l.p2p_ptr[a + 1]; ++e) {
+      const int32_t b = l.p2p_col[e];
+      const int64_t nb = t.n_body[b], bb = t.body_begin[b];
+      row_src += nb;
+      const bool contiguous = (b != a) && cur.n_runs > 0 && last_end == bb;
+      const bool full = (cur.n_src + (cur.self ? nA : 0) + nb > kP2PChunkSources &&
+                         (cur.n_src > 0 || cur.self)) ||
+                        (!contiguous && b != a && cur.n_runs >= kP2PMaxRuns);
+      if (full) {
+        chunks.push_back(cur);
+        cur = Chunk();
+        cur.run_begin = (int32_t)plan.run_body.size();
+        last_end = -1;
+      }
+      if (b == a) {
+        cur.self = true;
+        last_end = -1;  // the self leaf interrupts a run
+        continue;
+      }
+      if (cur.n_runs > 0 && last_end == bb) {
+        last_end = bb + nb;
+      } else {
+        plan.run_body.push_back((int32_t)bb);
+        plan.run_prefix.push_back(cur.n_src);
+        cur.n_runs++;
+        last_end = bb + nb;
+      }
+      cur.n_src += (int32_t)nb;
+    }
+    if (cur.n_src > 0 || cur.self || chunks.empty()) chunks.push_back(cur);
+    plan.max_row_sources = std::max<int32_t>(plan.max_row_sources, (int32_t)row_src);
+
+    const int32_t nch = (int32_t)chunks.size();
+    plan.leaf_cell.push_back((int32_t)a);
+    plan.leaf_pbase.push_back((int32_t)pbase);
+    plan.leaf_nchunk.push_back(nch);
+    for (int64_t g = 0; g < nA; g += 64) {
+      const int nt = (int)std::min<int64_t>(64, nA - g);
+      int R, L, K;
+      p2p_lane_layout(nt, &R, &L, &K);
+      for (int32_t c = 0; c < nch; ++c) {
+        P2PItem it;
+        it.tgt_begin = (int32_t)(bA + g);
+        it.tgt_cfg = nt | (R << 8) | (L << 16) | (K << 24);
+        it.run_begin = chunks[c].run_begin;
+        it.n_runs = chunks[c].n_runs;
+        it.n_src = chunks[c].n_src;
+        it.self_begin = chunks[c].self ? (int32_t)bA : -1;
+        it.self_n = chunks[c].self ? (int32_t)nA : 0;
+        it.out_off = (int32_t)(pbase + (int64_t)c * nA + g);
+        plan.items.push_back(it);
+      }
+    }
+    pbase += (int64_t)nch * nA;
+  }
+  plan.n_partials = pbase;
+}
+
+}  // namespace fmmlib

@@ -1,0 +1,347 @@
+"""Python binding of libfmm.so, the gfx950 dual-tree-traversal Laplace FMM.
+
+Argument marshalling only: every step of the method runs in the library
+(host C++ for the tree and the traversal, HIP kernels for the evaluation).
+torch supplies device memory and streams.  If the library is not built, every
+entry point raises; there is no fallback.
+
+    tree  = Tree(xyz_float64_numpy, ncrit)          # Morton octree (host)
+    lists = Lists(tree, theta)                       # dual tree traversal (host)
+    phi, grad = evaluate(tree, lists, q_cuda, p)     # one GPU evaluation
+    phi = potential(x_cuda, q_cuda, tree, lists, p)  # differentiable in q and x
+"""
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfmm.so")
+
+FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ESTATE = 0, -1, -2, -3, -4
+FMM_MIXED, FMM_FP64 = 0, 1
+FMM_MAC_FIRST, FMM_LEAF_FIRST = 0, 1
+FMM_P2P, FMM_M2L = 0, 1
+FMM_EVAL_TIMING, FMM_EVAL_KEEP_STAGES = 1, 2
+PHASES = ("gather", "p2p", "p2m", "m2m", "m2l", "l2l", "l2p", "total")
+
+_STATUS = {FMM_EINVAL: "EINVAL", FMM_ENOMEM: "ENOMEM", FMM_EDEVICE: "EDEVICE",
+           FMM_ESTATE: "ESTATE"}
+
+
+class FMMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_STATUS.get(code, code), msg))
+        self.code = code
+
+
+class _EvalOpts(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("precision", ctypes.c_int),
+                ("fp64_top_levels", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+class _TreeView(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_cells", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
+                ("max_level", ctypes.c_int32), ("fp32_exact", ctypes.c_int32),
+                ("perm", ctypes.c_void_p), ("keys", ctypes.c_void_p), ("level", ctypes.c_void_p),
+                ("parent", ctypes.c_void_p), ("child_begin", ctypes.c_void_p),
+                ("n_child", ctypes.c_void_p), ("body_begin", ctypes.c_void_p),
+                ("n_body", ctypes.c_void_p), ("center", ctypes.c_void_p),
+                ("radius", ctypes.c_void_p)]
+
+
+class _ListStats(ctypes.Structure):
+    _fields_ = [("p2p_entries", ctypes.c_int64), ("m2l_entries", ctypes.c_int64),
+                ("p2p_pairs", ctypes.c_int64), ("p2p_work_items", ctypes.c_int64),
+                ("p2p_max_row_sources", ctypes.c_int64)]
+
+
+EXPORTS = ("fmm_tree_build", "fmm_tree_set_positions", "fmm_tree_view", "fmm_tree_free",
+           "fmm_traverse", "fmm_lists_view", "fmm_lists_stats", "fmm_lists_free",
+           "fmm_evaluate", "fmm_evaluate_backward", "fmm_direct", "fmm_last_timings",
+           "fmm_last_error", "fmm_num_terms", "fmm_copy_expansions", "fmm_term_exponents")
+
+_lib = None
+
+
+def lib():
+    """Load libfmm.so (after torch, so both use one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libfmm.so is not built (%s); run paper_1209_3516_amd/build_lib.py"
+                           % LIB_PATH)
+    import torch  # noqa: F401  (its HIP runtime must be the one libfmm binds to)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u32, dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint,
+                              ctypes.c_double)
+    sig = {
+        "fmm_tree_build": ([vp, i64, i32, ctypes.POINTER(vp)], i32),
+        "fmm_tree_set_positions": ([vp, vp], i32),
+        "fmm_tree_view": ([vp, ctypes.POINTER(_TreeView)], i32),
+        "fmm_tree_free": ([vp], None),
+        "fmm_traverse": ([vp, dbl, u32, ctypes.POINTER(vp)], i32),
+        "fmm_lists_view": ([vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                            ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
+        "fmm_lists_stats": ([vp, ctypes.POINTER(_ListStats)], i32),
+        "fmm_lists_free": ([vp], None),
+        "fmm_evaluate": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp], i32),
+        "fmm_evaluate_backward": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp, vp, vp],
+                                  i32),
+        "fmm_direct": ([vp, vp, i64, vp, i64, vp, vp, vp], i32),
+        "fmm_last_timings": ([vp, ctypes.POINTER(dbl)], i32),
+        "fmm_last_error": ([], ctypes.c_char_p),
+        "fmm_num_terms": ([i32], i32),
+        "fmm_copy_expansions": ([vp, i32, vp], i32),
+        "fmm_term_exponents": ([i32, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != FMM_OK:
+        raise FMMError(rc, lib().fmm_last_error().decode())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _t_ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def num_terms(p):
+    return lib().fmm_num_terms(int(p))
+
+
+def term_exponents(p):
+    e = np.zeros((num_terms(p), 3), np.int32)
+    _check(lib().fmm_term_exponents(int(p), _np_ptr(e)))
+    return e
+
+
+class Tree:
+    """Morton octree with at most ncrit bodies per leaf, built on the host."""
+
+    def __init__(self, xyz, ncrit):
+        xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+        self.n = xyz.shape[0]
+        self.ncrit = int(ncrit)
+        h = ctypes.c_void_p()
+        _check(lib().fmm_tree_build(_np_ptr(xyz), self.n, self.ncrit, ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.fmm_tree_free(self._h)
+            self._h = None
+
+    def _view(self):
+        v = _TreeView()
+        _check(lib().fmm_tree_view(self._h, ctypes.byref(v)))
+        return v
+
+    @property
+    def n_cells(self):
+        return self._view().n_cells
+
+    @property
+    def max_level(self):
+        return self._view().max_level
+
+    def view(self):
+        """Copies of the tree arrays as numpy arrays."""
+        v = self._view()
+        n, nc = v.n, v.n_cells
+
+        def arr(ptr, dtype, count, shape=None):
+            if count == 0:
+                return np.zeros(shape or (0,), dtype)
+            buf = (ctypes.c_byte * (count * np.dtype(dtype).itemsize)).from_address(ptr)
+            a = np.frombuffer(buf, dtype=dtype, count=count).copy()
+            return a.reshape(shape) if shape else a
+
+        return dict(n=n, n_cells=nc, n_leaves=v.n_leaves, max_level=v.max_level,
+                    fp32_exact=bool(v.fp32_exact),
+                    perm=arr(v.perm, np.int32, n), keys=arr(v.keys, np.uint64, n),
+                    level=arr(v.level, np.int32, nc), parent=arr(v.parent, np.int32, nc),
+                    child_begin=arr(v.child_begin, np.int32, nc),
+                    n_child=arr(v.n_child, np.int32, nc),
+                    body_begin=arr(v.body_begin, np.int64, nc),
+                    n_body=arr(v.n_body, np.int64, nc),
+                    center=arr(v.center, np.float64, 3 * nc, (nc, 3)),
+                    radius=arr(v.radius, np.float64, nc))
+
+    def set_positions(self, xyz):
+        xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+        if xyz.shape[0] != self.n:
+            raise ValueError("set_positions: wrong number of bodies")
+        _check(lib().fmm_tree_set_positions(self._h, _np_ptr(xyz)))
+
+
+class Lists:
+    """P2P and M2L interaction lists from the dual tree traversal (host)."""
+
+    def __init__(self, tree, theta, leaf_first=False):
+        h = ctypes.c_void_p()
+        flags = FMM_LEAF_FIRST if leaf_first else FMM_MAC_FIRST
+        _check(lib().fmm_traverse(tree._h, float(theta), flags, ctypes.byref(h)))
+        self._h = h
+        self.tree = tree
+        self.theta = float(theta)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.fmm_lists_free(self._h)
+            self._h = None
+
+    def csr(self, kind):
+        ptr, col = ctypes.c_void_p(), ctypes.c_void_p()
+        nrows, nnz = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().fmm_lists_view(self._h, int(kind), ctypes.byref(ptr), ctypes.byref(col),
+                                    ctypes.byref(nrows), ctypes.byref(nnz)))
+        p = np.frombuffer((ctypes.c_int64 * (nrows.value + 1)).from_address(ptr.value),
+                          dtype=np.int64).copy()
+        c = (np.frombuffer((ctypes.c_int32 * nnz.value).from_address(col.value),
+                           dtype=np.int32).copy() if nnz.value else np.zeros(0, np.int32))
+        return p, c
+
+    def stats(self):
+        s = _ListStats()
+        _check(lib().fmm_lists_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _ListStats._fields_}
+
+
+def _opts(p, precision, flags=0, fp64_top_levels=-1):
+    prec = {"mixed": FMM_MIXED, "fp64": FMM_FP64}[precision]
+    return _EvalOpts(int(p), prec, int(fp64_top_levels), int(flags))
+
+
+def _dtype(precision):
+    import torch
+    return torch.float64 if precision == "fp64" else torch.float32
+
+
+def _check_tensor(t, n, dtype, name, cols=None):
+    shape = (n,) if cols is None else (n, cols)
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+        raise ValueError("%s must be a contiguous %s CUDA tensor of shape %s" % (name, dtype, shape))
+
+
+def evaluate(tree, lists, q, p, precision="mixed", grad=True, timing=False, keep_stages=False,
+             fp64_top_levels=-1, out=None):
+    """One FMM evaluation.  q: CUDA tensor [n] (float32 for "mixed", float64 for
+    "fp64"), user order.  Returns (phi [n], grad [n,3] or None)."""
+    import torch
+    dt = _dtype(precision)
+    _check_tensor(q, tree.n, dt, "q")
+    if out is None:
+        phi = torch.empty(tree.n, dtype=dt, device=q.device)
+        g = torch.empty(tree.n, 3, dtype=dt, device=q.device) if grad else None
+    else:
+        phi, g = out
+    flags = (FMM_EVAL_TIMING if timing else 0) | (FMM_EVAL_KEEP_STAGES if keep_stages else 0)
+    o = _opts(p, precision, flags, fp64_top_levels)
+    _check(lib().fmm_evaluate(tree._h, lists._h, ctypes.byref(o), _t_ptr(q), _t_ptr(phi),
+                              _t_ptr(g), _stream()))
+    return phi, g
+
+
+def evaluate_backward(tree, lists, q, grad_q, w, p, precision="mixed", need_dq=True,
+                      need_dx=True, fp64_top_levels=-1):
+    """Backward of L = sum_i w_i phi_i: returns (dL/dq [n], dL/dx [n,3])."""
+    import torch
+    dt = _dtype(precision)
+    _check_tensor(w, tree.n, dt, "w")
+    dq = torch.empty(tree.n, dtype=dt, device=w.device) if need_dq else None
+    dx = torch.empty(tree.n, 3, dtype=dt, device=w.device) if need_dx else None
+    o = _opts(p, precision, 0, fp64_top_levels)
+    _check(lib().fmm_evaluate_backward(tree._h, lists._h, ctypes.byref(o), _t_ptr(q),
+                                       _t_ptr(grad_q), _t_ptr(w), _t_ptr(dq), _t_ptr(dx),
+                                       _stream()))
+    return dq, dx
+
+
+def direct(xyz, q, targets):
+    """FP64 direct sum on the GPU at the given target indices (int64 CUDA tensor)."""
+    import torch
+    n = xyz.shape[0]
+    _check_tensor(xyz, n, torch.float64, "xyz", 3)
+    _check_tensor(q, n, torch.float64, "q")
+    m = targets.shape[0]
+    phi = torch.empty(m, dtype=torch.float64, device=xyz.device)
+    g = torch.empty(m, 3, dtype=torch.float64, device=xyz.device)
+    _check(lib().fmm_direct(_t_ptr(xyz), _t_ptr(q), n, _t_ptr(targets), m, _t_ptr(phi),
+                            _t_ptr(g), _stream()))
+    return phi, g
+
+
+def last_timings(lists):
+    """Per-phase device times (ms) of the last evaluation run with timing=True."""
+    ms = (ctypes.c_double * len(PHASES))()
+    _check(lib().fmm_last_timings(lists._h, ms))
+    return dict(zip(PHASES, list(ms)))
+
+
+def copy_expansions(lists, kind, p):
+    """Expansions of the last evaluation (order p) as (n_cells, T) float64, in the
+    library's term order (term_exponents(p)): kind 0 multipoles, 1 locals after
+    M2L (needs keep_stages=True), 2 locals after L2L."""
+    T = num_terms(p)
+    out = np.zeros((lists.tree.n_cells, T), np.float64)
+    _check(lib().fmm_copy_expansions(lists._h, int(kind), _np_ptr(out)))
+    return out
+
+
+def _make_autograd():
+    import torch
+
+    class FMMPotential(torch.autograd.Function):
+        """phi = FMM(x, q) with the tree and lists held fixed.  Backward of
+        L = sum_i w_i phi_i: dL/dq = phi[w] (one more evaluation with charges w),
+        dL/dx = w * grad[q] + q * grad[w], both from the library."""
+
+        @staticmethod
+        def forward(ctx, x, q, tree, lists, p, precision, fp64_top_levels):
+            phi, g = evaluate(tree, lists, q.detach().contiguous(), p, precision, grad=True,
+                              fp64_top_levels=fp64_top_levels)
+            ctx.save_for_backward(q, g)
+            ctx.cfg = (tree, lists, p, precision, fp64_top_levels)
+            ctx.mark_non_differentiable(g)
+            return phi
+
+        @staticmethod
+        def backward(ctx, w):
+            q, g = ctx.saved_tensors
+            tree, lists, p, precision, top = ctx.cfg
+            need_dx, need_dq = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            dq, dx = evaluate_backward(tree, lists, q.detach().contiguous(), g,
+                                       w.contiguous(), p, precision, need_dq=need_dq,
+                                       need_dx=need_dx, fp64_top_levels=top)
+            return dx, dq, None, None, None, None, None
+
+    return FMMPotential
+
+
+_autograd_fn = None
+
+
+def potential(x, q, tree, lists, p, precision="mixed", fp64_top_levels=-1):
+    """Differentiable FMM potential.  x: CUDA tensor [n,3] - the positions the
+    tree was built from (the tree holds its own copy; x carries the gradient);
+    q: CUDA tensor [n].  Returns phi [n]."""
+    global _autograd_fn
+    if _autograd_fn is None:
+        _autograd_fn = _make_autograd()
+    return _autograd_fn.apply(x, q, tree, lists, p, precision, fp64_top_levels)

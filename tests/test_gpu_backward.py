@@ -1,0 +1,169 @@
+"""Differentiable FMM on the GPU: L = sum_i w_i phi_i.
+
+With the tree, lists, centres and radii held fixed the method is linear in q
+and its far-field operator is symmetric (symmetric lists), so
+  dL/dq = phi[w]  and  dL/dx = w * grad[q] + q * grad[w].
+Checked against: the oracle's evaluations with charges w, central finite
+differences of the GPU FP64 method with the tree frozen (h = 1e-6, N = 1000),
+and the exact direct-sum gradient.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1209_3516_amd import fmm  # noqa: E402
+from paper_1209_3516_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+def _setup(n, ncrit=64, theta=0.4, dist="uniform"):
+    x = W.positions(n, dist)
+    q = W.charges(n)
+    w = W.weights(n)
+    return x, q, w, fmm.Tree(x, ncrit)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_backward_matches_oracle(precision):
+    x, q, w, t = _setup(8000, ncrit=32)
+    lst = fmm.Lists(t, 0.4)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    qt = torch.tensor(q, dtype=dt, device=DEV)
+    wt = torch.tensor(w, dtype=dt, device=DEV)
+    _, gq = fmm.evaluate(t, lst, qt, 4, precision)
+    dq, dx = fmm.evaluate_backward(t, lst, qt, gq, wt, 4, precision)
+    torch.cuda.synchronize()
+    o = O.OracleFMM(x, 32, 0.4)
+    rq, rw = o.evaluate(q, 4), o.evaluate(w, 4)
+    want_dx = w[:, None] * rq["grad"] + q[:, None] * rw["grad"]
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    assert rel(dq.double().cpu().numpy(), rw["phi"]) <= tol
+    assert rel(dx.double().cpu().numpy(), want_dx) <= tol
+
+
+def test_finite_differences_frozen_tree():
+    n = 1000
+    x, q, w, t = _setup(n, ncrit=64)
+    lst = fmm.Lists(t, 0.4)
+    qt = torch.tensor(q, dtype=torch.float64, device=DEV)
+    wt = torch.tensor(w, dtype=torch.float64, device=DEV)
+    _, gq = fmm.evaluate(t, lst, qt, 4, "fp64")
+    dq, dx = fmm.evaluate_backward(t, lst, qt, gq, wt, 4, "fp64")
+    dq, dx = dq.cpu().numpy(), dx.cpu().numpy()
+
+    def loss(xx, qq):
+        t.set_positions(xx)
+        phi, _ = fmm.evaluate(t, lst, torch.tensor(qq, dtype=torch.float64, device=DEV), 4,
+                              "fp64", grad=False)
+        return float(np.dot(w, phi.cpu().numpy()))
+
+    rng = np.random.default_rng(30)
+    h = 1e-6
+    for _ in range(20):
+        i, d = int(rng.integers(n)), int(rng.integers(3))
+        xp, xm = x.copy(), x.copy()
+        xp[i, d] += h
+        xm[i, d] -= h
+        fd = (loss(xp, q) - loss(xm, q)) / (2 * h)
+        assert abs(fd - dx[i, d]) <= 1e-6 * max(1.0, abs(dx[i, d])), (i, d, fd, dx[i, d])
+    t.set_positions(x)
+    for _ in range(20):
+        j = int(rng.integers(n))
+        qp, qm = q.copy(), q.copy()
+        qp[j] += h
+        qm[j] -= h
+        fd = (loss(x, qp) - loss(x, qm)) / (2 * h)
+        assert abs(fd - dq[j]) <= 1e-6 * max(1.0, abs(dq[j]))
+
+
+def test_gradient_against_direct_sum():
+    n = 20_000
+    x, q, w, t = _setup(n, ncrit=64)
+    lst = fmm.Lists(t, 0.4)
+    qt = torch.tensor(q, dtype=torch.float32, device=DEV)
+    wt = torch.tensor(w, dtype=torch.float32, device=DEV)
+    phi, gq = fmm.evaluate(t, lst, qt, 4)
+    dq, dx = fmm.evaluate_backward(t, lst, qt, gq, wt, 4)
+    torch.cuda.synchronize()
+    pq, gq_d = O.direct(x, q)
+    pw, gw_d = O.direct(x, w)
+    e_fwd = max(rel(phi.double().cpu().numpy(), pq), rel(gq.double().cpu().numpy(), gq_d))
+    want_dx = w[:, None] * gq_d + q[:, None] * gw_d
+    assert rel(dq.double().cpu().numpy(), pw) <= 3 * e_fwd + 1e-5
+    assert rel(dx.double().cpu().numpy(), want_dx) <= 3 * e_fwd + 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autograd_function(precision):
+    x, q, w, t = _setup(5000, ncrit=32)
+    lst = fmm.Lists(t, 0.4)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    xt = torch.tensor(x, dtype=dt, device=DEV, requires_grad=True)
+    qt = torch.tensor(q, dtype=dt, device=DEV, requires_grad=True)
+    wt = torch.tensor(w, dtype=dt, device=DEV)
+    phi = fmm.potential(xt, qt, t, lst, 4, precision)
+    loss = (wt * phi).sum()
+    loss.backward()
+    _, gq = fmm.evaluate(t, lst, qt.detach(), 4, precision)
+    dq, dx = fmm.evaluate_backward(t, lst, qt.detach(), gq, wt, 4, precision)
+    assert torch.equal(qt.grad, dq)
+    assert torch.equal(xt.grad, dx)
+    # only q differentiable: dx is not computed
+    q2 = torch.tensor(q, dtype=dt, device=DEV, requires_grad=True)
+    (wt * fmm.potential(xt.detach(), q2, t, lst, 4, precision)).sum().backward()
+    assert torch.equal(q2.grad, dq)
+
+
+def test_fwd_bwd_time_ratio():
+    x, q, w, t = _setup(200_000, ncrit=64)
+    lst = fmm.Lists(t, 0.4)
+    xt = torch.tensor(x, dtype=torch.float32, device=DEV, requires_grad=True)
+    qt = torch.tensor(q, dtype=torch.float32, device=DEV, requires_grad=True)
+    wt = torch.tensor(w, dtype=torch.float32, device=DEV)
+
+    def fwd():
+        return fmm.potential(xt, qt, t, lst, 4)
+
+    for _ in range(2):
+        (wt * fwd()).sum().backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        fwd()
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(5):
+        (wt * fwd()).sum().backward()
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    print("fwd+bwd / fwd =", t_fb / t_f)
+    assert t_fb / t_f < 3.0
+
+
+def test_injected_device_fault_leaves_handles_usable():
+    x, q, w, t = _setup(3000, ncrit=32)
+    lst = fmm.Lists(t, 0.4)
+    qt = torch.tensor(q, dtype=torch.float32, device=DEV)
+    ref, _ = fmm.evaluate(t, lst, qt, 4)
+    os.environ["FMM_FAULT_INJECT"] = "launch:3"
+    try:
+        with pytest.raises(fmm.FMMError) as e:
+            fmm.evaluate(t, lst, qt, 4)
+        assert e.value.code == fmm.FMM_EDEVICE
+    finally:
+        del os.environ["FMM_FAULT_INJECT"]
+    again, _ = fmm.evaluate(t, lst, qt, 4)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, again)
