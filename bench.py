@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--config", default="uniform-1e6-p4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first, as a reference "
+                         "for hardware memory-traffic counters")
     return ap.parse_args()
 
 
@@ -64,6 +67,13 @@ def main():
     lists = fmm.Lists(tree, theta)
     t_trav = time.perf_counter() - t0
     print("tree %.3fs traverse %.3fs" % (t_tree, t_trav), file=sys.stderr, flush=True)
+
+    if args.copy_calibration_mib > 0:
+        src = torch.ones(args.copy_calibration_mib * 2 ** 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     qt = torch.tensor(q, dtype=torch.float32, device=dev)
     phi = torch.empty(n, dtype=torch.float32, device=dev)

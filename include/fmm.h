@@ -60,10 +60,13 @@ enum fmm_list_kind { FMM_P2P = 0, FMM_M2L = 1 };
 
 enum fmm_eval_flags {
   FMM_EVAL_TIMING = 1, /* record per-phase device times (fmm_last_timings) */
-  FMM_EVAL_KEEP_STAGES = 2 /* keep a copy of the locals after M2L (fmm_copy_expansions) */
+  FMM_EVAL_KEEP_STAGES = 2, /* keep a copy of the locals after M2L (fmm_copy_expansions) */
+  FMM_EVAL_SERIAL = 4 /* run P2P on the caller's stream instead of overlapping it with the
+                         upward pass, M2L and L2L on a second (library-owned) stream */
 };
 
-/* Phases reported by fmm_last_timings, in this order. */
+/* Phases reported by fmm_last_timings, in this order.  Without FMM_EVAL_SERIAL
+ * the P2P phase overlaps P2M..L2L, so the phases then sum to more than the total. */
 enum fmm_phase {
   FMM_PHASE_GATHER = 0, /* charges into Morton order */
   FMM_PHASE_P2P = 1,    /* near field */
@@ -171,7 +174,10 @@ void fmm_lists_free(fmm_lists *l);
  * l must come from fmm_traverse(t, ...) (else FMM_ESTATE).  The first call on a
  * (tree, lists, p, precision) uploads the tree, lists and work plan and
  * allocates device scratch (hipMalloc); later calls reuse them.  No float
- * atomics: repeated calls give bitwise identical results.
+ * atomics: repeated calls give bitwise identical results.  Unless
+ * FMM_EVAL_SERIAL is set, the near field (P2P) runs on a second stream owned
+ * by the lists handle, forked from and joined back into `stream` with events,
+ * so it overlaps the far field; all outputs are complete when `stream` is.
  */
 int fmm_evaluate(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o, const void *q_dev,
                  void *phi_dev, void *grad_dev, void *stream);

@@ -74,9 +74,12 @@ struct DevLists {
   void *part_s = nullptr, *part_c = nullptr;
   void *tmp_phi = nullptr, *tmp_grad = nullptr;
   bool stage_valid = false;
-  // timing
-  hipEvent_t ev[FMM_NUM_PHASES] = {};
-  bool have_events = false, timing_valid = false;
+  // near-field stream (forked from / joined into the caller's stream)
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  // timing: 8 marks on the caller's stream, 2 around P2P
+  hipEvent_t ev[FMM_NUM_PHASES + 2] = {};
+  bool have_events = false, timing_valid = false, timed_serial = false;
   void release_scratch() {
     void *ptrs[] = {M, L, Lstage, M64, L64, L64stage, part_s, part_c, tmp_phi, tmp_grad};
     for (void *p2 : ptrs)
@@ -96,6 +99,9 @@ struct DevLists {
       if (p2) (void)hipFree(p2);
     if (have_events)
       for (auto &e : ev) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
     *this = DevLists();
   }
 };
@@ -289,7 +295,7 @@ int check_opts(const fmm_eval_opts *o) {
     set_error("fp64_top_levels must be -2, -1 or 0..21");
     return FMM_EINVAL;
   }
-  if (o->flags & ~(FMM_EVAL_TIMING | FMM_EVAL_KEEP_STAGES)) {
+  if (o->flags & ~(FMM_EVAL_TIMING | FMM_EVAL_KEEP_STAGES | FMM_EVAL_SERIAL)) {
     set_error("unknown evaluation flags");
     return FMM_EINVAL;
   }
@@ -321,14 +327,21 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   DevTree &dt = t->dev;
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool timing = (o->flags & FMM_EVAL_TIMING) != 0;
+  const bool overlap = (o->flags & FMM_EVAL_SERIAL) == 0;
   if (timing && !dv.have_events) {
-    for (int k = 0; k < FMM_NUM_PHASES; ++k) HIP_TRY(hipEventCreate(&dv.ev[k]));
+    for (auto &e : dv.ev) HIP_TRY(hipEventCreate(&e));
     dv.have_events = true;
+  }
+  if (overlap && !dv.side) {
+    // default priority, non-blocking with respect to the null stream
+    HIP_TRY(hipStreamCreateWithFlags(&dv.side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&dv.fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&dv.join, hipEventDisableTiming));
   }
   dv.timing_valid = false;
   g_launch_counter = 0;
-  auto mark = [&](int k) -> int {
-    if (timing) HIP_TRY(hipEventRecord(dv.ev[k], s));
+  auto mark = [&](int k, hipStream_t st) -> int {
+    if (timing) HIP_TRY(hipEventRecord(dv.ev[k], st));
     return FMM_OK;
   };
   const int p = o->p;
@@ -339,20 +352,31 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   const int max_level = td.max_level;
   const double *geo = dt.geo;
   const size_t real = fp64 ? 8 : 4;
-
-  if (int rc = mark(0)) return rc;
-  LAUNCH_TRY(D::gather_charges(fp64, td.n, dt.perm, q, bodies, stream));
-  if (int rc = mark(1)) return rc;
   // Bodies of different leaves never coincide for a tree built from these
   // positions (equal positions share a key, hence a leaf), nor in FP32 when
   // every position is FP32-representable; otherwise test every pair.
   const bool mask_all = td.moved || (!fp64 && !td.fp32_exact);
-  LAUNCH_TRY(D::p2p(fp64, mask_all, (int64_t)pl.items.size(), dv.items,
-                    dv.run_body, dv.run_prefix, bodies, dv.part_s, dv.part_c, stream));
-  if (int rc = mark(2)) return rc;
+
+  if (int rc = mark(0, s)) return rc;
+  LAUNCH_TRY(D::gather_charges(fp64, td.n, dt.perm, q, bodies, stream));
+  if (int rc = mark(1, s)) return rc;
+
+  // Near field: independent of the far field until the final combine.
+  const hipStream_t ns = overlap ? dv.side : s;
+  if (overlap) {
+    HIP_TRY(hipEventRecord(dv.fork, s));
+    HIP_TRY(hipStreamWaitEvent(ns, dv.fork, 0));
+  }
+  if (int rc = mark(8, ns)) return rc;
+  LAUNCH_TRY(D::p2p(fp64, mask_all, (int64_t)pl.items.size(), dv.items, dv.run_body,
+                    dv.run_prefix, bodies, dv.part_s, dv.part_c, ns));
+  if (int rc = mark(9, ns)) return rc;
+  if (overlap) HIP_TRY(hipEventRecord(dv.join, ns));
+
+  // Far field on the caller's stream.
   LAUNCH_TRY(D::p2m(p, fp64, (int64_t)pl.leaf_cell.size(), dv.leaf_cell, dt.body_begin, dt.n_body,
                     geo, bodies, dv.M, dv.M64, n_top, stream));
-  if (int rc = mark(3)) return rc;
+  if (int rc = mark(2, s)) return rc;
   for (int lev = max_level - 1; lev >= 0; --lev) {
     const int64_t c0 = td.level_begin[lev], c1 = td.level_begin[lev + 1];
     const bool out64 = c1 <= n_top;        // this level is kept in FP64
@@ -360,7 +384,7 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
     LAUNCH_TRY(D::m2m(p, fp64, c0, c1, dt.child_begin, dt.n_child, geo, dv.M, dv.M64, child64,
                       out64, stream));
   }
-  if (int rc = mark(4)) return rc;
+  if (int rc = mark(3, s)) return rc;
   LAUNCH_TRY(D::zero(dv.L, (int64_t)td.n_cells() * S * real, stream));
   if (n_top > 0) LAUNCH_TRY(D::zero(dv.L64, n_top * S * 8, stream));
   {
@@ -383,7 +407,7 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   } else {
     dv.stage_valid = false;
   }
-  if (int rc = mark(5)) return rc;
+  if (int rc = mark(4, s)) return rc;
   for (int lev = 1; lev <= max_level; ++lev) {
     const int64_t c0 = td.level_begin[lev], c1 = td.level_begin[lev + 1];
     const bool parent64 = td.level_begin[lev] <= n_top && n_top > 0;
@@ -391,11 +415,14 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
     LAUNCH_TRY(D::l2l(p, fp64, c0, c1, dt.parent, geo, dv.L, dv.L64, parent64, child64, stream));
   }
   if (n_top > 0) LAUNCH_TRY(D::copy_top_locals(p, n_top, dv.L64, (float *)dv.L, stream));
-  if (int rc = mark(6)) return rc;
+  if (int rc = mark(5, s)) return rc;
+  if (overlap) HIP_TRY(hipStreamWaitEvent(s, dv.join, 0));
+  if (int rc = mark(6, s)) return rc;
   LAUNCH_TRY(D::l2p_combine(p, fp64, td.n, dv.body_leaf, dv.leaf_cell, dv.leaf_pbase,
                             dv.leaf_nchunk, dt.body_begin, dt.n_body, geo, dv.L, bodies,
                             dv.part_s, dv.part_c, dt.perm, phi, grad, stream));
-  if (int rc = mark(7)) return rc;
+  if (int rc = mark(7, s)) return rc;
+  dv.timed_serial = !overlap;
   dv.timing_valid = timing;
   return FMM_OK;
 }
@@ -646,14 +673,20 @@ int fmm_last_timings(const fmm_lists *l, double *ms) {
     return FMM_ESTATE;
   }
   HIP_TRY(hipEventSynchronize(dv.ev[7]));
-  for (int k = 0; k < 7; ++k) {
+  HIP_TRY(hipEventSynchronize(dv.ev[9]));
+  auto span = [&](int a, int b, double *out) -> int {
     float f = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&f, dv.ev[k], dv.ev[k + 1]));
-    ms[k] = f;
-  }
-  float tot = 0.0f;
-  HIP_TRY(hipEventElapsedTime(&tot, dv.ev[0], dv.ev[7]));
-  ms[FMM_PHASE_TOTAL] = tot;
+    HIP_TRY(hipEventElapsedTime(&f, dv.ev[a], dv.ev[b]));
+    *out = f;
+    return FMM_OK;
+  };
+  // marks: 0 start, 1 after gather, 8/9 around P2P, 2 after P2M, 3 after M2M,
+  // 4 after M2L, 5 after L2L, 6 after the join, 7 end.
+  const int p2m_from = dv.timed_serial ? 9 : 1;
+  const int pairs[FMM_NUM_PHASES][2] = {{0, 1}, {8, 9}, {p2m_from, 2}, {2, 3},
+                                        {3, 4}, {4, 5}, {6, 7}, {0, 7}};
+  for (int k = 0; k < FMM_NUM_PHASES; ++k)
+    if (int rc = span(pairs[k][0], pairs[k][1], &ms[k])) return rc;
   return FMM_OK;
 }
 

@@ -534,17 +534,49 @@ __global__ __launch_bounds__(64) void m2l_kernel(int64_t r0, const int32_t *__re
   Acc acc[T];
   static_for<T>([&](auto I) { acc[decltype(I)::value] = Acc(0); });
   const int64_t e1 = ptr[A + 1];
-  for (int64_t e = ptr[A] + lane; e < e1; e += 64) {
-    const int B = col[e];
-    const double4 gb = geo[B];
-    Real D[T];
-    derivatives<P, Real>(Real(ga.x - gb.x), Real(ga.y - gb.y), Real(ga.z - gb.z), D);
-    Real mb[T];
-    load_row<T>(M + (int64_t)B * S, mb);
-    static_for<kM2L<P>.N>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      acc[kM2L<P>.k[i]] += Acc(mb[kM2L<P>.n[i]] * D[kM2L<P>.s[i]]);
-    });
+  if constexpr (T <= 56) {
+    // Software pipeline: the centre and multipole of the lane's next entry
+    // are loaded while the current entry is computed.
+    int64_t e = ptr[A] + lane;
+    double4 gb_next = ga;
+    Real mb_next[T];
+    static_for<T>([&](auto I) { mb_next[decltype(I)::value] = Real(0); });
+    if (e < e1) {
+      const int B = col[e];
+      gb_next = geo[B];
+      load_row<T>(M + (int64_t)B * S, mb_next);
+    }
+    int B2 = (e + 64 < e1) ? col[e + 64] : 0;
+    for (; e < e1; e += 64) {
+      const double4 gb = gb_next;
+      Real mb[T];
+      static_for<T>([&](auto I) { mb[decltype(I)::value] = mb_next[decltype(I)::value]; });
+      if (e + 64 < e1) {
+        gb_next = geo[B2];
+        load_row<T>(M + (int64_t)B2 * S, mb_next);
+        B2 = (e + 128 < e1) ? col[e + 128] : 0;
+      }
+      Real D[T];
+      derivatives<P, Real>(Real(ga.x - gb.x), Real(ga.y - gb.y), Real(ga.z - gb.z), D);
+      static_for<kM2L<P>.N>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        acc[kM2L<P>.k[i]] += Acc(mb[kM2L<P>.n[i]] * D[kM2L<P>.s[i]]);
+      });
+    }
+  } else {
+    // High orders: registers are the limit, so no prefetch.
+    for (int64_t e = ptr[A] + lane; e < e1; e += 64) {
+      const int B = col[e];
+      const double4 gb = geo[B];
+      Real D[T];
+      derivatives<P, Real>(Real(ga.x - gb.x), Real(ga.y - gb.y), Real(ga.z - gb.z), D);
+      Real mb[T];
+      load_row<T>(M + (int64_t)B * S, mb);
+      static_for<kM2L<P>.N>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        acc[kM2L<P>.k[i]] += Acc(mb[kM2L<P>.n[i]] * D[kM2L<P>.s[i]]);
+      });
+    }
   }
   static_for<T>([&](auto I) { red[lane * (T + 1) + decltype(I)::value] = acc[decltype(I)::value]; });
   __syncthreads();

@@ -21,7 +21,7 @@ FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ESTATE = 0, -1, -2, -3, -4
 FMM_MIXED, FMM_FP64 = 0, 1
 FMM_MAC_FIRST, FMM_LEAF_FIRST = 0, 1
 FMM_P2P, FMM_M2L = 0, 1
-FMM_EVAL_TIMING, FMM_EVAL_KEEP_STAGES = 1, 2
+FMM_EVAL_TIMING, FMM_EVAL_KEEP_STAGES, FMM_EVAL_SERIAL = 1, 2, 4
 PHASES = ("gather", "p2p", "p2m", "m2m", "m2l", "l2l", "l2p", "total")
 
 _STATUS = {FMM_EINVAL: "EINVAL", FMM_ENOMEM: "ENOMEM", FMM_EDEVICE: "EDEVICE",
@@ -240,9 +240,10 @@ def _check_tensor(t, n, dtype, name, cols=None):
 
 
 def evaluate(tree, lists, q, p, precision="mixed", grad=True, timing=False, keep_stages=False,
-             fp64_top_levels=-1, out=None):
+             fp64_top_levels=-1, out=None, serial=False):
     """One FMM evaluation.  q: CUDA tensor [n] (float32 for "mixed", float64 for
-    "fp64"), user order.  Returns (phi [n], grad [n,3] or None)."""
+    "fp64"), user order.  Returns (phi [n], grad [n,3] or None).  serial=True
+    keeps the near field on the caller's stream (no overlap with the far field)."""
     import torch
     dt = _dtype(precision)
     _check_tensor(q, tree.n, dt, "q")
@@ -251,7 +252,8 @@ def evaluate(tree, lists, q, p, precision="mixed", grad=True, timing=False, keep
         g = torch.empty(tree.n, 3, dtype=dt, device=q.device) if grad else None
     else:
         phi, g = out
-    flags = (FMM_EVAL_TIMING if timing else 0) | (FMM_EVAL_KEEP_STAGES if keep_stages else 0)
+    flags = ((FMM_EVAL_TIMING if timing else 0) | (FMM_EVAL_KEEP_STAGES if keep_stages else 0)
+             | (FMM_EVAL_SERIAL if serial else 0))
     o = _opts(p, precision, flags, fp64_top_levels)
     _check(lib().fmm_evaluate(tree._h, lists._h, ctypes.byref(o), _t_ptr(q), _t_ptr(phi),
                               _t_ptr(g), _stream()))

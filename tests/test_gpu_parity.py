@@ -206,7 +206,23 @@ def test_timings_are_reported():
     t = fmm.Tree(x, 64)
     lst = fmm.Lists(t, 0.4)
     qt = torch.tensor(W.charges(20_000), dtype=torch.float32, device=DEV)
-    fmm.evaluate(t, lst, qt, 4, timing=True)
+    fmm.evaluate(t, lst, qt, 4, timing=True, serial=True)
     ms = fmm.last_timings(lst)
     assert ms["total"] > 0 and ms["p2p"] > 0
-    assert abs(sum(ms[k] for k in fmm.PHASES[:-1]) - ms["total"]) <= 1e-3 + 1e-3 * ms["total"]
+    # serial: the phases tile the total up to the cost of the event records
+    covered = sum(ms[k] for k in fmm.PHASES[:-1])
+    assert covered <= ms["total"] + 1e-3 and covered >= ms["total"] - 0.02
+    fmm.evaluate(t, lst, qt, 4, timing=True)  # overlapped: phases overlap the total
+    ms = fmm.last_timings(lst)
+    assert 0 < ms["p2p"] <= ms["total"] and ms["m2l"] > 0
+
+
+def test_serial_and_overlapped_agree_bitwise():
+    x = W.uniform_cube(50_000, seed=31)
+    t = fmm.Tree(x, 64)
+    lst = fmm.Lists(t, 0.4)
+    qt = torch.tensor(W.charges(50_000), dtype=torch.float32, device=DEV)
+    a = fmm.evaluate(t, lst, qt, 4, serial=True)
+    b = fmm.evaluate(t, lst, qt, 4)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
