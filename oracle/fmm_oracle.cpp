@@ -390,6 +390,34 @@ void traverse(const Tree &tr, double theta, bool leaf_first, Lists &ls) {
   to_csr(tv.m2l, ls.n_rows, ls.m2l_ptr, ls.m2l_col);
 }
 
+// Upward pass: P2M on every leaf, then M2M from the deepest level upwards.
+void upward_pass(const Tree &tr, const Terms &T, const std::vector<double> &qs,
+                 std::vector<double> &M) {
+  const int64_t nc = (int64_t)tr.cells.size();
+  const int nt = T.count();
+  M.assign(nc * nt, 0.0);
+  int max_level = 0;
+  for (const auto &c : tr.cells) max_level = std::max(max_level, c.level);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t c = 0; c < nc; ++c) {
+    const Cell &C = tr.cells[c];
+    if (C.n_child != 0) continue;
+    int64_t b = C.body_begin;
+    p2m(T, C.X, &tr.xs[b], &tr.ys[b], &tr.zs[b], &qs[b], C.n_body, &M[c * nt]);
+  }
+  for (int lev = max_level - 1; lev >= 0; --lev) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t c = 0; c < nc; ++c) {
+      const Cell &C = tr.cells[c];
+      if (C.level != lev || C.n_child == 0) continue;
+      for (int k = 0; k < C.n_child; ++k) {
+        int ch = C.child_begin + k;
+        m2m(T, C.X, tr.cells[ch].X, &M[ch * nt], &M[c * nt]);
+      }
+    }
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -479,28 +507,10 @@ int oracle_evaluate(const oracle_fmm *o, int p, const double *q, double *phi, do
   for (int64_t i = 0; i < n; ++i) qs[i] = q[tr.perm[i]];
 
   // Upward pass: P2M on leaves, then M2M from the deepest level upwards.
-  std::vector<double> M(nc * nt, 0.0);
+  std::vector<double> M;
+  upward_pass(tr, T, qs, M);
   int max_level = 0;
   for (const auto &c : tr.cells) max_level = std::max(max_level, c.level);
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t c = 0; c < nc; ++c) {
-    const Cell &C = tr.cells[c];
-    if (C.n_child != 0) continue;
-    int64_t b = C.body_begin;
-    p2m(T, C.X, &tr.xs[b], &tr.ys[b], &tr.zs[b], &qs[b], C.n_body, &M[c * nt]);
-  }
-  for (int lev = max_level - 1; lev >= 0; --lev) {
-#pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t c = 0; c < nc; ++c) {
-      const Cell &C = tr.cells[c];
-      if (C.level != lev || C.n_child == 0) continue;
-      for (int k = 0; k < C.n_child; ++k) {
-        int ch = C.child_begin + k;
-        m2m(T, C.X, tr.cells[ch].X, &M[ch * nt], &M[c * nt]);
-      }
-    }
-  }
-
   // M2L over the M2L list, one target row at a time.
   std::vector<double> L(nc * nt, 0.0);
 #pragma omp parallel for schedule(dynamic, 16)
@@ -609,6 +619,67 @@ void oracle_op_l2p(int p, const double *XA, const double *L, const double *y, in
     grad[3 * i] = grad[3 * i + 1] = grad[3 * i + 2] = 0.0;
     l2p(T, XA, L, &y[3 * i], &phi[i], &grad[3 * i]);
   }
+}
+
+// The same evaluation restricted to the bodies of the given leaves, for
+// checks at sizes where the full evaluation is too slow: the upward pass over
+// the whole tree, then for each leaf the M2L rows and L2L translations along
+// its chain of ancestors, L2P, and its P2P row, in the same order as
+// oracle_evaluate (so the results are identical).  Outputs, for the bodies of
+// the leaves in the given order (sorted order within a leaf): user index,
+// phi, grad[3].  Returns the number of bodies written, or -1.
+int64_t oracle_evaluate_leaves(const oracle_fmm *o, int p, const double *q, const int32_t *leaves,
+                               int64_t n_leaves, int64_t *user_index, double *phi,
+                               double *grad) {
+  if (p < 1 || p > 16) return -1;
+  const Tree &tr = o->tree;
+  const Lists &ls = o->lists;
+  const int64_t n = tr.n;
+  Terms T(p);
+  const int nt = T.count();
+  std::vector<double> qs(n);
+  for (int64_t i = 0; i < n; ++i) qs[i] = q[tr.perm[i]];
+  std::vector<double> M;
+  upward_pass(tr, T, qs, M);
+  std::vector<int64_t> offset(n_leaves + 1, 0);
+  for (int64_t k = 0; k < n_leaves; ++k) {
+    const Cell &A = tr.cells[leaves[k]];
+    if (A.n_child != 0) return -1;
+    offset[k + 1] = offset[k] + A.n_body;
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < n_leaves; ++k) {
+    const int a = leaves[k];
+    std::vector<int> chain;
+    for (int c = a; c >= 0; c = tr.cells[c].parent) chain.push_back(c);
+    std::vector<double> Lp, Lc(nt, 0.0);
+    for (int idx = (int)chain.size() - 1; idx >= 0; --idx) {
+      const int c = chain[idx];
+      std::fill(Lc.begin(), Lc.end(), 0.0);
+      for (int64_t e = ls.m2l_ptr[c]; e < ls.m2l_ptr[c + 1]; ++e) {
+        const int b = ls.m2l_col[e];
+        m2l(T, tr.cells[c].X, tr.cells[b].X, &M[b * nt], Lc.data());
+      }
+      if (!Lp.empty()) l2l(T, tr.cells[tr.cells[c].parent].X, tr.cells[c].X, Lp.data(), Lc.data());
+      Lp = Lc;
+    }
+    const Cell &A = tr.cells[a];
+    for (int64_t i = A.body_begin; i < A.body_begin + A.n_body; ++i) {
+      const double xi[3] = {tr.xs[i], tr.ys[i], tr.zs[i]};
+      double fphi = 0.0, fg[3] = {0.0, 0.0, 0.0}, nphi = 0.0, ng[3] = {0.0, 0.0, 0.0};
+      l2p(T, A.X, Lp.data(), xi, &fphi, fg);
+      for (int64_t e = ls.p2p_ptr[a]; e < ls.p2p_ptr[a + 1]; ++e) {
+        const Cell &B = tr.cells[ls.p2p_col[e]];
+        int64_t b = B.body_begin;
+        p2p_point(xi, &tr.xs[b], &tr.ys[b], &tr.zs[b], &qs[b], B.n_body, &nphi, ng);
+      }
+      const int64_t out = offset[k] + (i - A.body_begin);
+      user_index[out] = tr.perm[i];
+      phi[out] = nphi + fphi;
+      for (int d = 0; d < 3; ++d) grad[3 * out + d] = ng[d] + fg[d];
+    }
+  }
+  return offset[n_leaves];
 }
 
 }  // extern "C"

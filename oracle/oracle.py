@@ -44,6 +44,8 @@ def _load():
     lib.oracle_term_exponents.restype = None
     lib.oracle_evaluate.argtypes = [vp, i32] + [vp] * 10
     lib.oracle_evaluate.restype = i32
+    lib.oracle_evaluate_leaves.argtypes = [vp, i32, vp, vp, i64, vp, vp, vp]
+    lib.oracle_evaluate_leaves.restype = i64
     lib.oracle_direct.argtypes = [vp, vp, i64, vp, i64, vp, vp]
     lib.oracle_direct.restype = None
     lib.oracle_op_derivatives.argtypes = [i32, vp, vp]
@@ -143,6 +145,24 @@ class OracleFMM:
         if rc != 0:
             raise ValueError("oracle_evaluate failed")
         return out
+
+
+def evaluate_leaves(o, q, p, leaves):
+    """The full evaluation restricted to the bodies of the given leaf cells (same
+    arithmetic in the same order).  Returns (user_index, phi, grad)."""
+    lib = _load()
+    q = _f64(q, (-1,))
+    leaves = np.ascontiguousarray(leaves, dtype=np.int32)
+    t = o.tree()
+    nb = int(t["n_body"][leaves].sum())
+    idx = np.zeros(nb, np.int64)
+    phi = np.zeros(nb)
+    grad = np.zeros((nb, 3))
+    got = lib.oracle_evaluate_leaves(o._h, int(p), _p(q), _p(leaves), leaves.shape[0], _p(idx),
+                                     _p(phi), _p(grad))
+    if got != nb:
+        raise ValueError("oracle_evaluate_leaves failed")
+    return idx, phi, grad
 
 
 def direct(xyz, q, targets=None):

@@ -289,3 +289,18 @@ def test_all_coincident_is_single_leaf():
     assert o.num_cells == 1
     r = o.evaluate(q, 4)
     assert np.all(r["phi"] == 0) and np.all(r["grad"] == 0)
+
+
+@pytest.mark.parametrize("dist,ncrit,theta,p", [("uniform", 64, 0.4, 4), ("plummer", 16, 0.35, 6)])
+def test_per_leaf_evaluation_equals_full_evaluation(dist, ncrit, theta, p):
+    """The per-leaf oracle (used for checks at full size) is the full evaluation."""
+    x = W.positions(6000, dist)
+    q = W.charges(6000)
+    o = O.OracleFMM(x, ncrit, theta)
+    full = o.evaluate(q, p)
+    t = o.tree()
+    leaves = np.nonzero(t["n_child"] == 0)[0][::3]
+    idx, phi, grad = O.evaluate_leaves(o, q, p, leaves)
+    assert len(set(idx.tolist())) == len(idx)
+    np.testing.assert_array_equal(phi, full["phi"][idx])
+    np.testing.assert_array_equal(grad, full["grad"][idx])
