@@ -26,6 +26,38 @@ sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X, 256 CUs at 2.4 GHz
 FLOP_PER_PAIR = 20               # potential + gradient per body pair (section 3.4, Table 6)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_p2p_uniform_N1e6_p4.txt")
+
+
+def p2p_source_digest():
+    """Identity of the P2P kernel as built: its sources and the device flags."""
+    import hashlib
+
+    from paper_1209_3516_amd import build_lib
+
+    h = hashlib.sha256()
+    for name in ("p2p.hip", "device_common.h", "fmm_internal.h"):
+        with open(os.path.join(build_lib.CSRC, name), "rb") as f:
+            h.update(f.read())
+    h.update(" ".join(build_lib.DEVICE_FLAGS[:-2]).encode())
+    return h.hexdigest()
+
+
+def measured_traffic(config_name):
+    """HBM bytes per P2P launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None if the
+    summary is missing, is for another workload, or the P2P kernel changed."""
+    if config_name != "uniform-1e6-p4" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("p2p_source_sha256") != p2p_source_digest():
+        return None
+    return float(vals["p2p_traffic_bytes_per_launch"])
 
 
 def parse():
@@ -161,7 +193,8 @@ def main():
             "outputs": "potential+gradient", "precision": "fp32 P2P/M2L, Kahan P2P sums"},
         "roofline": {"bound": "alu", "kernel": "p2p", "achieved": achieved,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic(args.config),
                      "work": "%d pairs x %d flop" % (pairs, FLOP_PER_PAIR),
                      "p2p_ms": phase_ms["p2p"]},
         "p2p_gpairs_per_s": pairs / p2p_s / 1e9,

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libfmm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["tree.cpp", "traverse.cpp", "plan.cpp", "api.cpp"]
-DEVICE_SOURCES = ["kernels.hip"]
+DEVICE_SOURCES = ["p2p.hip", "far.hip", "misc.hip"]
 
 HOST_FLAGS = ["-std=c++17", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
               "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),

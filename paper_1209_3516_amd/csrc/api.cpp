@@ -220,8 +220,10 @@ int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
   const fmmlib::TreeData &td = t->data;
   const fmmlib::ListData &ld = l->data;
   fmmlib::build_p2p_plan(td, ld, dv.plan);
-  for (int64_t a = 0; a < ld.n_rows; ++a)
-    if (ld.m2l_ptr[a + 1] > ld.m2l_ptr[a]) dv.m2l_rows_host.push_back((int32_t)a);
+  // M2L runs over every cell: a row without entries writes zeros, so L needs
+  // no separate clearing before M2L.
+  dv.m2l_rows_host.resize(ld.n_rows);
+  for (int64_t a = 0; a < ld.n_rows; ++a) dv.m2l_rows_host[a] = (int32_t)a;
   const auto &pl = dv.plan;
   if (int rc = dev_upload(&dv.m2l_ptr, ld.m2l_ptr.data(), ld.m2l_ptr.size())) return rc;
   if (int rc = dev_upload(&dv.m2l_col, ld.m2l_col.data(), ld.m2l_col.size())) return rc;
@@ -385,8 +387,6 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
                       out64, stream));
   }
   if (int rc = mark(3, s)) return rc;
-  LAUNCH_TRY(D::zero(dv.L, (int64_t)td.n_cells() * S * real, stream));
-  if (n_top > 0) LAUNCH_TRY(D::zero(dv.L64, n_top * S * 8, stream));
   {
     const auto &rows = dv.m2l_rows_host;
     const int64_t split =

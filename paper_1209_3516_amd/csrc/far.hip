@@ -1,0 +1,392 @@
+// Far-field kernels (P2M, M2M, M2L, L2L, L2P + combine) of the gfx950 FMM.
+//
+// Expansions are Cartesian Taylor (section 3.1, Table 2) of total degree
+// 0..p-1.  Multipoles about a cell centre X_B, locals about X_A:
+//   P2M  M_n(B)  = sum_j q_j (X_B - x_j)^n / n!
+//   M2M  M_n(P) += sum_{m <= n} M_m(c) (X_P - X_c)^(n-m) / (n-m)!
+//   M2L  L_k(A) += sum_{|n|+|k| <= p-1} M_n(B) D^(n+k) G(X_A - X_B),   G = 1/|r|
+//   L2L  L_k(c) += sum_{m >= k} L_m(P) (X_c - X_P)^(m-k) / (m-k)!
+//   L2P  phi(y)  = sum_k L_k (y - X_A)^k / k!, gradient by differentiating in y
+//   P2P  phi_i  += q_j / r,  grad_i += q_j (x_j - x_i) / r^3   (r > 0)
+// The derivatives D^m G come from the recurrence for a_m = D^m G / m!:
+//   |m| r^2 a_m = -(2|m|-1) sum_d R_d a_{m-e_d} - (|m|-1) sum_d a_{m-2e_d}.
+// Translations are computed on the fly per pair rather than loaded as
+// precomputed matrices (section 3.1: bytes per flop keep falling).
+//
+// All index arithmetic over multi-indices is resolved at compile time: the
+// kernels are templated on p and every loop over coefficients is unrolled
+// through constexpr tables, so coefficients live in registers.
+//
+// No floating-point atomics anywhere: each output value is produced by one
+// thread or one wave in a fixed order, so results are bitwise reproducible.
+#include "device_common.h"
+
+namespace fmmlib {
+namespace dev {
+namespace {
+
+// ----------------------------------------------------------------------------
+// P2M: one thread per leaf.
+// ----------------------------------------------------------------------------
+template <int P, typename Real>
+__global__ __launch_bounds__(64) void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
+                           const int32_t *__restrict__ body_begin,
+                           const int32_t *__restrict__ n_body, const double4 *__restrict__ geo,
+                           const typename Vec<Real>::V4 *__restrict__ bodies, Real *__restrict__ M,
+                           double *__restrict__ M64, int64_t n_top) {
+  constexpr int T = nterms(P), S = pad4(T);
+  const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= n_leaves) return;
+  const int c = leaf_cell[li];
+  const double4 g = geo[c];
+  Real acc[T];
+  static_for<T>([&](auto I) { acc[decltype(I)::value] = Real(0); });
+  const int b0 = body_begin[c], nb = n_body[c];
+  for (int j = 0; j < nb; ++j) {
+    const typename Vec<Real>::V4 b = bodies[b0 + j];
+    Real mono[T];
+    monomials<P, Real>(Real(g.x - (double)b.x), Real(g.y - (double)b.y), Real(g.z - (double)b.z),
+                       mono);
+    static_for<T>([&](auto I) { acc[decltype(I)::value] += b.w * mono[decltype(I)::value]; });
+  }
+  static_for<T>([&](auto I) { M[(int64_t)c * S + decltype(I)::value] = acc[decltype(I)::value]; });
+  if (c < n_top)
+    static_for<T>(
+        [&](auto I) { M64[(int64_t)c * S + decltype(I)::value] = (double)acc[decltype(I)::value]; });
+}
+
+// ----------------------------------------------------------------------------
+// M2M: one thread per parent cell of one level; the parent gathers from its
+// contiguous children (no atomics).
+// ----------------------------------------------------------------------------
+template <int P, typename CT, typename AT>
+__global__ __launch_bounds__(64) void m2m_kernel(int64_t c0, int64_t c1, const int32_t *__restrict__ child_begin,
+                           const int32_t *__restrict__ n_child, const double4 *__restrict__ geo,
+                           const CT *__restrict__ Mchild, AT *__restrict__ Mout,
+                           float *__restrict__ Mcopy) {
+  constexpr int T = nterms(P), S = pad4(T);
+  const int64_t c = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= c1) return;
+  const int nch = n_child[c];
+  if (nch == 0) return;
+  const double4 gp = geo[c];
+  AT acc[T];
+  static_for<T>([&](auto I) { acc[decltype(I)::value] = AT(0); });
+  for (int k = 0; k < nch; ++k) {
+    const int ch = child_begin[c] + k;
+    const double4 gc = geo[ch];
+    AT mono[T];
+    monomials<P, AT>(AT(gp.x - gc.x), AT(gp.y - gc.y), AT(gp.z - gc.z), mono);
+    CT mc[T];
+    load_row<T>(Mchild + (int64_t)ch * S, mc);
+    static_for<kShift<P>.N>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      acc[kShift<P>.hi[i]] += AT(mc[kShift<P>.lo[i]]) * mono[kShift<P>.diff[i]];
+    });
+  }
+  static_for<T>([&](auto I) { Mout[c * S + decltype(I)::value] = acc[decltype(I)::value]; });
+  if (Mcopy)
+    static_for<T>([&](auto I) { Mcopy[c * S + decltype(I)::value] = (float)acc[decltype(I)::value]; });
+}
+
+// ----------------------------------------------------------------------------
+// M2L: one 64-lane wave per target cell with M2L entries; lane l takes the
+// entries l, l+64, ... of the row, computes D^m G(X_A - X_B) with the
+// recurrence and contracts it with the source multipole.  The 64 lane
+// partials are summed in LDS in a fixed order.
+// ----------------------------------------------------------------------------
+template <int P, typename Real, typename Acc>
+__global__ __launch_bounds__(64) void m2l_kernel(int64_t r0, const int32_t *__restrict__ rows,
+                                                 const int64_t *__restrict__ ptr,
+                                                 const int32_t *__restrict__ col,
+                                                 const double4 *__restrict__ geo,
+                                                 const Real *__restrict__ M, Acc *__restrict__ Lout) {
+  constexpr int T = nterms(P), S = pad4(T);
+  __shared__ Acc red[64 * (T + 1)];
+  const int lane = threadIdx.x;
+  const int A = rows[r0 + xcd_remap(blockIdx.x, gridDim.x)];
+  const double4 ga = geo[A];
+  Acc acc[T];
+  static_for<T>([&](auto I) { acc[decltype(I)::value] = Acc(0); });
+  const int64_t e1 = ptr[A + 1];
+  if constexpr (T <= 56) {
+    // Software pipeline with two register buffers: the centre and multipole
+    // of the lane's next entry load while the current entry is computed.
+    auto contract = [&](const double4 &gb, const Real (&mb)[T]) {
+      Real D[T];
+      derivatives<P, Real>(Real(ga.x - gb.x), Real(ga.y - gb.y), Real(ga.z - gb.z), D);
+      static_for<kM2L<P>.N>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        acc[kM2L<P>.k[i]] += Acc(mb[kM2L<P>.n[i]] * D[kM2L<P>.s[i]]);
+      });
+    };
+    int64_t e = ptr[A] + lane;
+    double4 g0 = ga, g1 = ga;
+    Real m0[T], m1[T];
+    if (e < e1) {
+      const int B = col[e];
+      g0 = geo[B];
+      load_row<T>(M + (int64_t)B * S, m0);
+    }
+    int Bn = (e + 64 < e1) ? col[e + 64] : 0;
+    while (e < e1) {
+      if (e + 64 < e1) {
+        g1 = geo[Bn];
+        load_row<T>(M + (int64_t)Bn * S, m1);
+        Bn = (e + 128 < e1) ? col[e + 128] : 0;
+      }
+      contract(g0, m0);
+      e += 64;
+      if (e >= e1) break;
+      if (e + 64 < e1) {
+        g0 = geo[Bn];
+        load_row<T>(M + (int64_t)Bn * S, m0);
+        Bn = (e + 128 < e1) ? col[e + 128] : 0;
+      }
+      contract(g1, m1);
+      e += 64;
+    }
+  } else {
+    // High orders: registers are the limit, so no prefetch.
+    for (int64_t e = ptr[A] + lane; e < e1; e += 64) {
+      const int B = col[e];
+      const double4 gb = geo[B];
+      Real D[T];
+      derivatives<P, Real>(Real(ga.x - gb.x), Real(ga.y - gb.y), Real(ga.z - gb.z), D);
+      Real mb[T];
+      load_row<T>(M + (int64_t)B * S, mb);
+      static_for<kM2L<P>.N>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        acc[kM2L<P>.k[i]] += Acc(mb[kM2L<P>.n[i]] * D[kM2L<P>.s[i]]);
+      });
+    }
+  }
+  static_for<T>([&](auto I) { red[lane * (T + 1) + decltype(I)::value] = acc[decltype(I)::value]; });
+  __syncthreads();
+  for (int t = lane; t < T; t += 64) {
+    Acc sum = Acc(0);
+    for (int l = 0; l < 64; ++l) sum += red[l * (T + 1) + t];
+    Lout[(int64_t)A * S + t] = sum;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// L2L: one thread per child cell of one level; the child pulls from its
+// parent.  PT: parent's storage type, AT: arithmetic type, CT: child's.
+// ----------------------------------------------------------------------------
+template <int P, typename PT, typename AT, typename CT>
+__global__ __launch_bounds__(64) void l2l_kernel(int64_t c0, int64_t c1, const int32_t *__restrict__ parent,
+                           const double4 *__restrict__ geo, const PT *__restrict__ Lpar,
+                           CT *__restrict__ Lchild) {
+  constexpr int T = nterms(P), S = pad4(T);
+  const int64_t c = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= c1) return;
+  const int pc = parent[c];
+  const double4 gc = geo[c], gp = geo[pc];
+  AT mono[T];
+  monomials<P, AT>(AT(gc.x - gp.x), AT(gc.y - gp.y), AT(gc.z - gp.z), mono);
+  PT lp[T];
+  load_row<T>(Lpar + (int64_t)pc * S, lp);
+  AT add[T];
+  static_for<T>([&](auto I) { add[decltype(I)::value] = AT(0); });
+  static_for<kShift<P>.N>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    add[kShift<P>.lo[i]] += AT(lp[kShift<P>.hi[i]]) * mono[kShift<P>.diff[i]];
+  });
+  static_for<T>([&](auto I) {
+    constexpr int t = decltype(I)::value;
+    Lchild[c * S + t] = CT(AT(Lchild[c * S + t]) + add[t]);
+  });
+}
+
+__global__ void copy_top_kernel(int64_t n, const double *__restrict__ src, float *__restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
+// ----------------------------------------------------------------------------
+// L2P + near/far combine + scatter to user order: one thread per body.
+// ----------------------------------------------------------------------------
+template <int P, typename Real, bool KAHAN>
+__global__ __launch_bounds__(256) void l2p_combine_kernel(
+    int64_t n, const int32_t *__restrict__ body_leaf, const int32_t *__restrict__ leaf_cell,
+    const int32_t *__restrict__ leaf_pbase, const int32_t *__restrict__ leaf_nchunk,
+    const int32_t *__restrict__ cell_body_begin, const int32_t *__restrict__ cell_n_body,
+    const double4 *__restrict__ geo, const Real *__restrict__ L,
+    const typename Vec<Real>::V4 *__restrict__ bodies,
+    const typename Vec<Real>::V4 *__restrict__ part_s,
+    const typename Vec<Real>::V4 *__restrict__ part_c, const int32_t *__restrict__ perm,
+    Real *__restrict__ phi_out, Real *__restrict__ grad_out) {
+  using V4 = typename Vec<Real>::V4;
+  constexpr int T = nterms(P), S = pad4(T);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a = body_leaf[i];
+  const int c = leaf_cell[a];
+  const V4 b = bodies[i];
+  const double4 g = geo[c];
+  Real mono[T];
+  monomials<P, Real>(Real((double)b.x - g.x), Real((double)b.y - g.y), Real((double)b.z - g.z),
+                     mono);
+  Real lc[T];
+  load_row<T>(L + (int64_t)c * S, lc);
+  Real f = Real(0), gx = Real(0), gy = Real(0), gz = Real(0);
+  static_for<T>([&](auto I) {
+    constexpr int t = decltype(I)::value;
+    f += lc[t] * mono[t];
+    if constexpr (kBasis<P>.lo[t][0] >= 0) gx += lc[t] * mono[kBasis<P>.lo[t][0]];
+    if constexpr (kBasis<P>.lo[t][1] >= 0) gy += lc[t] * mono[kBasis<P>.lo[t][1]];
+    if constexpr (kBasis<P>.lo[t][2] >= 0) gz += lc[t] * mono[kBasis<P>.lo[t][2]];
+  });
+  Real s4[4] = {0, 0, 0, 0}, c4[4] = {0, 0, 0, 0};
+  const int nA = cell_n_body[c];
+  const int64_t slot0 = (int64_t)leaf_pbase[a] + (i - cell_body_begin[c]);
+  const int nch = leaf_nchunk[a];
+  for (int ch = 0; ch < nch; ++ch) {
+    const V4 ps = part_s[slot0 + (int64_t)ch * nA];
+    const Real vs[4] = {ps.x, ps.y, ps.z, ps.w};
+    if constexpr (KAHAN) {
+      const V4 pc = part_c[slot0 + (int64_t)ch * nA];
+      const Real vc[4] = {pc.x, pc.y, pc.z, pc.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const Real y = (vs[k] - vc[k]) - c4[k];
+        const Real t = s4[k] + y;
+        c4[k] = (t - s4[k]) - y;
+        s4[k] = t;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s4[k] += vs[k];
+    }
+  }
+  const int64_t u = perm[i];
+  phi_out[u] = (s4[0] - c4[0]) + f;
+  if (grad_out) {
+    grad_out[3 * u + 0] = (s4[1] - c4[1]) + gx;
+    grad_out[3 * u + 1] = (s4[2] - c4[2]) + gy;
+    grad_out[3 * u + 2] = (s4[3] - c4[3]) + gz;
+  }
+}
+
+}  // namespace
+
+#define FMM_LAUNCH_CHECK() return (int)hipGetLastError()
+
+int p2m(int p, bool fp64, int64_t n_leaves, const int32_t *leaf_cell, const int32_t *cell_body_begin,
+        const int32_t *cell_n_body, const double *geo, const void *bodies, void *M, double *M64,
+        int64_t n_top, void *stream) {
+  if (n_leaves == 0) return 0;
+  const unsigned nb = blocks_for(n_leaves, 64);
+  return with_p(p, [&](auto PC) {
+    constexpr int PP = decltype(PC)::value;
+    if (fp64)
+      p2m_kernel<PP, double><<<nb, 64, 0, S_(stream)>>>(n_leaves, leaf_cell, cell_body_begin,
+                                                        cell_n_body, (const double4 *)geo,
+                                                        (const double4 *)bodies, (double *)M,
+                                                        M64, 0);
+    else
+      p2m_kernel<PP, float><<<nb, 64, 0, S_(stream)>>>(n_leaves, leaf_cell, cell_body_begin,
+                                                       cell_n_body, (const double4 *)geo,
+                                                       (const float4 *)bodies, (float *)M, M64,
+                                                       n_top);
+  });
+}
+
+int m2m(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *child_begin,
+        const int32_t *n_child, const double *geo, void *M, double *M64, bool child_fp64,
+        bool out_fp64, void *stream) {
+  if (c1 <= c0) return 0;
+  const unsigned nb = blocks_for(c1 - c0, 64);
+  const double4 *g = (const double4 *)geo;
+  return with_p(p, [&](auto PC) {
+    constexpr int PP = decltype(PC)::value;
+    if (fp64)
+      m2m_kernel<PP, double, double><<<nb, 64, 0, S_(stream)>>>(
+          c0, c1, child_begin, n_child, g, (const double *)M, (double *)M, nullptr);
+    else if (out_fp64 && child_fp64)
+      m2m_kernel<PP, double, double><<<nb, 64, 0, S_(stream)>>>(c0, c1, child_begin, n_child, g,
+                                                                M64, M64, (float *)M);
+    else if (out_fp64)
+      m2m_kernel<PP, float, double><<<nb, 64, 0, S_(stream)>>>(
+          c0, c1, child_begin, n_child, g, (const float *)M, M64, (float *)M);
+    else
+      m2m_kernel<PP, float, float><<<nb, 64, 0, S_(stream)>>>(
+          c0, c1, child_begin, n_child, g, (const float *)M, (float *)M, nullptr);
+  });
+}
+
+int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int32_t *rows, const int64_t *ptr,
+        const int32_t *col, const double *geo, const void *M, void *L, double *L64,
+        bool acc_fp64, void *stream) {
+  if (r1 <= r0) return 0;
+  const unsigned G = (unsigned)(r1 - r0);
+  const double4 *g = (const double4 *)geo;
+  return with_p(p, [&](auto PC) {
+    constexpr int PP = decltype(PC)::value;
+    if (fp64)
+      m2l_kernel<PP, double, double><<<G, 64, 0, S_(stream)>>>(r0, rows, ptr, col, g,
+                                                               (const double *)M, (double *)L);
+    else if (acc_fp64)
+      m2l_kernel<PP, float, double><<<G, 64, 0, S_(stream)>>>(r0, rows, ptr, col, g,
+                                                              (const float *)M, L64);
+    else
+      m2l_kernel<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, rows, ptr, col, g,
+                                                             (const float *)M, (float *)L);
+  });
+}
+
+int l2l(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *parent, const double *geo,
+        void *L, double *L64, bool parent_fp64, bool child_fp64, void *stream) {
+  if (c1 <= c0) return 0;
+  const unsigned nb = blocks_for(c1 - c0, 64);
+  const double4 *g = (const double4 *)geo;
+  return with_p(p, [&](auto PC) {
+    constexpr int PP = decltype(PC)::value;
+    if (fp64)
+      l2l_kernel<PP, double, double, double><<<nb, 64, 0, S_(stream)>>>(
+          c0, c1, parent, g, (const double *)L, (double *)L);
+    else if (parent_fp64 && child_fp64)
+      l2l_kernel<PP, double, double, double><<<nb, 64, 0, S_(stream)>>>(c0, c1, parent, g, L64,
+                                                                        L64);
+    else if (parent_fp64)
+      l2l_kernel<PP, double, double, float><<<nb, 64, 0, S_(stream)>>>(c0, c1, parent, g, L64,
+                                                                       (float *)L);
+    else
+      l2l_kernel<PP, float, float, float><<<nb, 64, 0, S_(stream)>>>(
+          c0, c1, parent, g, (const float *)L, (float *)L);
+  });
+}
+
+int copy_top_locals(int p, int64_t n_top, const double *L64, float *L, void *stream) {
+  const int64_t n = n_top * stride(p);
+  if (n == 0) return 0;
+  copy_top_kernel<<<blocks_for(n, 256), 256, 0, S_(stream)>>>(n, L64, L);
+  FMM_LAUNCH_CHECK();
+}
+
+int l2p_combine(int p, bool fp64, int64_t n, const int32_t *body_leaf, const int32_t *leaf_cell,
+                const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
+                const int32_t *cell_body_begin, const int32_t *cell_n_body, const double *geo,
+                const void *L, const void *bodies, const void *part_s, const void *part_c,
+                const int32_t *perm, void *phi, void *grad, void *stream) {
+  if (n == 0) return 0;
+  const unsigned nb = blocks_for(n, 256);
+  const double4 *g = (const double4 *)geo;
+  return with_p(p, [&](auto PC) {
+    constexpr int PP = decltype(PC)::value;
+    if (fp64)
+      l2p_combine_kernel<PP, double, false><<<nb, 256, 0, S_(stream)>>>(
+          n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk, cell_body_begin, cell_n_body, g,
+          (const double *)L, (const double4 *)bodies, (const double4 *)part_s, nullptr, perm,
+          (double *)phi, (double *)grad);
+    else
+      l2p_combine_kernel<PP, float, true><<<nb, 256, 0, S_(stream)>>>(
+          n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk, cell_body_begin, cell_n_body, g,
+          (const float *)L, (const float4 *)bodies, (const float4 *)part_s,
+          (const float4 *)part_c, perm, (float *)phi, (float *)grad);
+  });
+}
+
+}  // namespace dev
+}  // namespace fmmlib

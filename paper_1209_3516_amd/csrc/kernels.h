@@ -1,4 +1,5 @@
-// Host-side launchers of the gfx950 kernels (implemented in kernels.hip).
+// Host-side launchers of the gfx950 kernels (implemented in p2p.hip, far.hip
+// and misc.hip).
 // Plain pointers and sizes only; every launcher enqueues on `stream`
 // (a hipStream_t) and returns the hipError_t of the launch as an int.
 #pragma once
@@ -54,8 +55,6 @@ int l2p_combine(int p, bool fp64, int64_t n, const int32_t *body_leaf, const int
 
 int backward_combine(bool fp64, int64_t n, const void *q, const void *w, const void *grad_q,
                      const void *grad_w, void *dx, void *stream);
-
-int zero(void *ptr, int64_t bytes, void *stream);
 
 int direct_sum(const double *xyz, const double *q, int64_t n, const int64_t *targets, int64_t m,
                double *phi, double *grad, void *stream);
