@@ -184,6 +184,71 @@ void p2p_point(const double xi[3], const double *x, const double *y, const doubl
   }
 }
 
+// Sources that also carry a dipole moment s (used by the backward of a loss
+// on the gradient).  A dipole s at x_j has the potential s . grad_y G(y - x_j)
+// = s . (x_j - y) / |y - x_j|^3; in the multipole expansion about X_B it
+// contributes M_n += sum_d s_d (X_B - x_j)^(n - e_d) / (n - e_d)!.
+void p2m_dipole(const Terms &T, const double X[3], const double *x, const double *y,
+                const double *z, const double *s, int64_t nb, double *M) {
+  for (int64_t j = 0; j < nb; ++j) {
+    const double d[3] = {X[0] - x[j], X[1] - y[j], X[2] - z[j]};
+    for (int t = 0; t < T.count(); ++t)
+      for (int a = 0; a < 3; ++a) {
+        int e[3] = {T.ex[t], T.ey[t], T.ez[t]};
+        e[a] -= 1;
+        const int l = T.index(e[0], e[1], e[2]);
+        if (l >= 0) M[t] += s[3 * j + a] * scaled_monomial(T, l, d);
+      }
+  }
+}
+
+// Hessian of the local expansion at y, applied to the vector v:
+// (H v)_a = sum_b v_b sum_{k >= e_a + e_b} L_k (y - X_A)^(k - e_a - e_b) / (k - e_a - e_b)!
+void l2p_hessian(const Terms &T, const double XA[3], const double *L, const double y[3],
+                 const double v[3], double hv[3]) {
+  const double d[3] = {y[0] - XA[0], y[1] - XA[1], y[2] - XA[2]};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double h = 0.0;
+      for (int k = 0; k < T.count(); ++k) {
+        int e[3] = {T.ex[k], T.ey[k], T.ez[k]};
+        e[a] -= 1;
+        e[b] -= 1;
+        const int l = T.index(e[0], e[1], e[2]);
+        if (l >= 0) h += L[k] * scaled_monomial(T, l, d);
+      }
+      hv[a] += h * v[b];
+    }
+}
+
+// Direct interaction of sources (charges q, optional dipoles s) with one
+// target: potential, gradient, and optionally the Hessian of the charge
+// field applied to v (Hessian of 1/|r| is (3 r r^T - r^2 I) / r^5).
+void p2p_general_point(const double xi[3], const double *x, const double *y, const double *z,
+                       const double *q, const double *s, int64_t nb, const double *v,
+                       double *phi, double g[3], double hv[3]) {
+  for (int64_t j = 0; j < nb; ++j) {
+    const double d[3] = {x[j] - xi[0], y[j] - xi[1], z[j] - xi[2]};
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 == 0.0) continue;
+    const double r = std::sqrt(r2);
+    const double inv3 = 1.0 / (r2 * r);
+    const double inv5 = inv3 / r2;
+    *phi += q[j] / r;
+    for (int a = 0; a < 3; ++a) g[a] += q[j] * d[a] * inv3;
+    if (s) {
+      const double *sj = &s[3 * j];
+      const double sd = sj[0] * d[0] + sj[1] * d[1] + sj[2] * d[2];
+      *phi += sd * inv3;
+      for (int a = 0; a < 3; ++a) g[a] += -sj[a] * inv3 + 3.0 * sd * d[a] * inv5;
+    }
+    if (v && hv) {
+      const double dv = d[0] * v[0] + d[1] * v[1] + d[2] * v[2];
+      for (int a = 0; a < 3; ++a) hv[a] += q[j] * (3.0 * dv * d[a] - r2 * v[a]) * inv5;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Tree: bounding cube, 21-bit-per-axis Morton keys, stable sort, split every
 // cell holding more than ncrit bodies (section 3.3 and Table 3: Morton keys,
@@ -680,6 +745,161 @@ int64_t oracle_evaluate_leaves(const oracle_fmm *o, int p, const double *q, cons
     }
   }
   return offset[n_leaves];
+}
+
+// Replace the positions (user order) keeping the tree structure, centres,
+// radii and lists: the method with its tree frozen, for finite differences.
+void oracle_set_positions(oracle_fmm *o, const double *xyz) {
+  Tree &t = o->tree;
+  for (int64_t i = 0; i < t.n; ++i) {
+    t.xs[i] = xyz[3 * (int64_t)t.perm[i] + 0];
+    t.ys[i] = xyz[3 * (int64_t)t.perm[i] + 1];
+    t.zs[i] = xyz[3 * (int64_t)t.perm[i] + 2];
+  }
+}
+
+// Evaluation with sources that carry charges q and optionally dipoles s
+// ([n][3]), and optionally, at every body i, the Hessian of the charge field
+// applied to v_i ([n][3]; needs s == NULL).  Outputs in user order; any may be
+// NULL.  The far field uses the same expansions: dipoles enter through P2M,
+// the Hessian through second derivatives of the local expansion.
+int oracle_evaluate_general(const oracle_fmm *o, int p, const double *q, const double *s,
+                            const double *v, double *phi, double *grad, double *hv) {
+  if (p < 1 || p > 16 || (s && v)) return -1;
+  const Tree &tr = o->tree;
+  const Lists &ls = o->lists;
+  const int64_t n = tr.n;
+  const int64_t nc = (int64_t)tr.cells.size();
+  if (n == 0) return 0;
+  Terms T(p);
+  const int nt = T.count();
+  std::vector<double> qs(n), ss(s ? 3 * n : 0), vs(v ? 3 * n : 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t u = tr.perm[i];
+    qs[i] = q[u];
+    for (int a = 0; a < 3; ++a) {
+      if (s) ss[3 * i + a] = s[3 * u + a];
+      if (v) vs[3 * i + a] = v[3 * u + a];
+    }
+  }
+  std::vector<double> M;
+  upward_pass(tr, T, qs, M);
+  if (s) {
+    // dipole moments of the leaves, then shifted upwards like the charges
+    std::vector<double> Md(nc * nt, 0.0);
+    int max_level = 0;
+    for (const auto &c : tr.cells) max_level = std::max(max_level, c.level);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t c = 0; c < nc; ++c) {
+      const Cell &C = tr.cells[c];
+      if (C.n_child != 0) continue;
+      int64_t b = C.body_begin;
+      p2m_dipole(T, C.X, &tr.xs[b], &tr.ys[b], &tr.zs[b], &ss[3 * b], C.n_body, &Md[c * nt]);
+    }
+    for (int lev = max_level - 1; lev >= 0; --lev) {
+#pragma omp parallel for schedule(dynamic, 16)
+      for (int64_t c = 0; c < nc; ++c) {
+        const Cell &C = tr.cells[c];
+        if (C.level != lev || C.n_child == 0) continue;
+        for (int k = 0; k < C.n_child; ++k) {
+          int ch = C.child_begin + k;
+          m2m(T, C.X, tr.cells[ch].X, &Md[ch * nt], &Md[c * nt]);
+        }
+      }
+    }
+    for (int64_t k = 0; k < nc * nt; ++k) M[k] += Md[k];
+  }
+  std::vector<double> L(nc * nt, 0.0);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t a = 0; a < nc; ++a)
+    for (int64_t e = ls.m2l_ptr[a]; e < ls.m2l_ptr[a + 1]; ++e) {
+      int b = ls.m2l_col[e];
+      m2l(T, tr.cells[a].X, tr.cells[b].X, &M[b * nt], &L[a * nt]);
+    }
+  int max_level = 0;
+  for (const auto &c : tr.cells) max_level = std::max(max_level, c.level);
+  for (int lev = 1; lev <= max_level; ++lev) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t c = 0; c < nc; ++c) {
+      const Cell &C = tr.cells[c];
+      if (C.level != lev) continue;
+      l2l(T, tr.cells[C.parent].X, C.X, &L[C.parent * nt], &L[c * nt]);
+    }
+  }
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t a = 0; a < nc; ++a) {
+    const Cell &A = tr.cells[a];
+    if (A.n_child != 0) continue;
+    for (int64_t i = A.body_begin; i < A.body_begin + A.n_body; ++i) {
+      const double xi[3] = {tr.xs[i], tr.ys[i], tr.zs[i]};
+      const double *vi = v ? &vs[3 * i] : nullptr;
+      double f = 0.0, g[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+      l2p(T, A.X, &L[a * nt], xi, &f, g);
+      if (vi) l2p_hessian(T, A.X, &L[a * nt], xi, vi, h);
+      double nf = 0.0, ng[3] = {0, 0, 0}, nh[3] = {0, 0, 0};
+      for (int64_t e = ls.p2p_ptr[a]; e < ls.p2p_ptr[a + 1]; ++e) {
+        const Cell &B = tr.cells[ls.p2p_col[e]];
+        int64_t b = B.body_begin;
+        p2p_general_point(xi, &tr.xs[b], &tr.ys[b], &tr.zs[b], &qs[b], s ? &ss[3 * b] : nullptr,
+                          B.n_body, vi, &nf, ng, nh);
+      }
+      const int64_t u = tr.perm[i];
+      if (phi) phi[u] = nf + f;
+      for (int d = 0; d < 3; ++d) {
+        if (grad) grad[3 * u + d] = ng[d] + g[d];
+        if (hv) hv[3 * u + d] = nh[d] + h[d];
+      }
+    }
+  }
+  return 0;
+}
+
+// Direct sum with charges q and optional dipoles s at the given targets, and
+// optionally the Hessian of the charge field applied to v[target].
+void oracle_direct_general(const double *xyz, const double *q, const double *s, int64_t n,
+                           const int64_t *targets, int64_t m, const double *v, double *phi,
+                           double *grad, double *hv) {
+  std::vector<double> x(n), y(n), z(n);
+  for (int64_t j = 0; j < n; ++j) {
+    x[j] = xyz[3 * j];
+    y[j] = xyz[3 * j + 1];
+    z[j] = xyz[3 * j + 2];
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t t = 0; t < m; ++t) {
+    const int64_t i = targets[t];
+    const double xi[3] = {x[i], y[i], z[i]};
+    double f = 0.0, g[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+    p2p_general_point(xi, x.data(), y.data(), z.data(), q, s, n, v ? &v[3 * t] : nullptr, &f,
+                      g, h);
+    phi[t] = f;
+    for (int d = 0; d < 3; ++d) {
+      grad[3 * t + d] = g[d];
+      if (hv) hv[3 * t + d] = h[d];
+    }
+  }
+}
+
+void oracle_op_p2m_dipole(int p, const double *X, const double *xyz, const double *s, int64_t nb,
+                          double *M) {
+  Terms T(p);
+  std::vector<double> x(nb), y(nb), z(nb);
+  for (int64_t j = 0; j < nb; ++j) {
+    x[j] = xyz[3 * j];
+    y[j] = xyz[3 * j + 1];
+    z[j] = xyz[3 * j + 2];
+  }
+  for (int t = 0; t < T.count(); ++t) M[t] = 0.0;
+  p2m_dipole(T, X, x.data(), y.data(), z.data(), s, nb, M);
+}
+
+void oracle_op_l2p_hessian(int p, const double *XA, const double *L, const double *y,
+                           const double *v, int64_t m, double *hv) {
+  Terms T(p);
+  for (int64_t i = 0; i < m; ++i) {
+    hv[3 * i] = hv[3 * i + 1] = hv[3 * i + 2] = 0.0;
+    l2p_hessian(T, XA, L, &y[3 * i], &v[3 * i], &hv[3 * i]);
+  }
 }
 
 }  // extern "C"

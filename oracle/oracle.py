@@ -46,6 +46,16 @@ def _load():
     lib.oracle_evaluate.restype = i32
     lib.oracle_evaluate_leaves.argtypes = [vp, i32, vp, vp, i64, vp, vp, vp]
     lib.oracle_evaluate_leaves.restype = i64
+    lib.oracle_set_positions.argtypes = [vp, vp]
+    lib.oracle_set_positions.restype = None
+    lib.oracle_evaluate_general.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.oracle_evaluate_general.restype = i32
+    lib.oracle_direct_general.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, vp, vp]
+    lib.oracle_direct_general.restype = None
+    lib.oracle_op_p2m_dipole.argtypes = [i32, vp, vp, vp, i64, vp]
+    lib.oracle_op_p2m_dipole.restype = None
+    lib.oracle_op_l2p_hessian.argtypes = [i32, vp, vp, vp, vp, i64, vp]
+    lib.oracle_op_l2p_hessian.restype = None
     lib.oracle_direct.argtypes = [vp, vp, i64, vp, i64, vp, vp]
     lib.oracle_direct.restype = None
     lib.oracle_op_derivatives.argtypes = [i32, vp, vp]
@@ -145,6 +155,63 @@ class OracleFMM:
         if rc != 0:
             raise ValueError("oracle_evaluate failed")
         return out
+
+
+def set_positions(o, xyz):
+    """Move the bodies (user order) with the tree, centres, radii and lists frozen."""
+    _load().oracle_set_positions(o._h, _p(_f64(xyz, (-1, 3))))
+
+
+def evaluate_general(o, p, q, s=None, v=None):
+    """Charges q and optional dipoles s [n,3] as sources; optional per-body
+    vectors v [n,3] for the Hessian of the charge field applied to v.
+    Returns (phi, grad, hv) in user order (hv None without v)."""
+    lib = _load()
+    n = o.n
+    q = _f64(q, (-1,))
+    s = None if s is None else _f64(s, (-1, 3))
+    v = None if v is None else _f64(v, (-1, 3))
+    phi, grad = np.zeros(n), np.zeros((n, 3))
+    hv = None if v is None else np.zeros((n, 3))
+    rc = lib.oracle_evaluate_general(o._h, int(p), _p(q), _p(s), _p(v), _p(phi), _p(grad), _p(hv))
+    if rc != 0:
+        raise ValueError("oracle_evaluate_general failed")
+    return phi, grad, hv
+
+
+def direct_general(xyz, q, s=None, targets=None, v=None):
+    """Direct sum with charges q and optional dipoles s; optional vectors v
+    (one per target) for the Hessian of the charge field.  Returns (phi, grad, hv)."""
+    lib = _load()
+    xyz = _f64(xyz, (-1, 3))
+    n = xyz.shape[0]
+    q = _f64(q, (-1,))
+    s = None if s is None else _f64(s, (-1, 3))
+    targets = np.arange(n, dtype=np.int64) if targets is None else np.ascontiguousarray(
+        targets, dtype=np.int64)
+    m = targets.shape[0]
+    v = None if v is None else _f64(v, (-1, 3))
+    phi, grad = np.zeros(m), np.zeros((m, 3))
+    hv = None if v is None else np.zeros((m, 3))
+    lib.oracle_direct_general(_p(xyz), _p(q), _p(s), n, _p(targets), m, _p(v), _p(phi), _p(grad),
+                              _p(hv))
+    return phi, grad, hv
+
+
+def p2m_dipole(p, X, xyz, s):
+    xyz = _f64(xyz, (-1, 3))
+    M = np.zeros(num_terms(p))
+    _load().oracle_op_p2m_dipole(p, _p(_f64(X, (3,))), _p(xyz), _p(_f64(s, (-1, 3))),
+                                 xyz.shape[0], _p(M))
+    return M
+
+
+def l2p_hessian(p, XA, L, y, v):
+    y = _f64(y, (-1, 3))
+    hv = np.zeros((y.shape[0], 3))
+    _load().oracle_op_l2p_hessian(p, _p(_f64(XA, (3,))), _p(_f64(L)), _p(y), _p(_f64(v, (-1, 3))),
+                                  y.shape[0], _p(hv))
+    return hv
 
 
 def evaluate_leaves(o, q, p, leaves):
