@@ -183,18 +183,27 @@ int fmm_evaluate(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o, 
                  void *phi_dev, void *grad_dev, void *stream);
 
 /*
- * Backward of L = sum_i w_i phi_i for the forward above, with the tree, lists,
- * centres and radii held fixed (the method is linear in q and its far-field
- * operator is symmetric when the lists are):
- *   dq_dev[i]    = dL/dq_i = phi_i[w]                       (an evaluation with charges w)
- *   dx_dev[i][d] = dL/dx_i = w_i grad_i[q] + q_i grad_i[w]
- *   grad_q_dev   device [n][3]: grad[q] from the forward (required when dx_dev != NULL)
- *   w_dev        device [n]: upstream gradient dL/dphi
- * Same dtype/stream rules as fmm_evaluate; dq_dev or dx_dev may be NULL.
+ * Backward of L = sum_i w_i phi_i + sum_i v_i . grad_i for the forward above,
+ * with the tree, lists, centres and radii held fixed.  The method is linear in
+ * q and its far-field operator is symmetric (the lists are symmetric), so
+ *   dL/dq_j = Phi_j           Phi: potential of charges w plus dipoles -v
+ *                             (a dipole s at x_j has potential s.(x_j - y)/|x_j - y|^3)
+ *   dL/dx_i = w_i grad_i[q] + q_i grad Phi_i + H_i[q] v_i
+ * where H[q] is the Hessian of the charge field (second derivatives of the
+ * local expansion plus the near-field Hessian of 1/r).  With v = NULL (a loss
+ * on the potential only) this is one evaluation with charges w plus an
+ * elementwise combine; with v it is two evaluations (charges w + dipoles -v,
+ * and charges q with Hessian-vector outputs) plus the combine.
+ *   q_dev       device [n]: the forward's charges (required when dx_dev != NULL)
+ *   grad_q_dev  device [n][3]: grad[q] from the forward (required when dx_dev != NULL)
+ *   w_dev       device [n]: dL/dphi (required; zeros for a loss on the gradient only)
+ *   v_dev       device [n][3]: dL/dgrad, or NULL
+ *   dq_dev      device [n] out, or NULL;  dx_dev device [n][3] out, or NULL
+ * Same dtype/stream rules as fmm_evaluate.
  */
 int fmm_evaluate_backward(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o,
                           const void *q_dev, const void *grad_q_dev, const void *w_dev,
-                          void *dq_dev, void *dx_dev, void *stream);
+                          const void *v_dev, void *dq_dev, void *dx_dev, void *stream);
 
 /*
  * Direct O(N) sum per target in FP64 on the GPU (zero-distance pairs skipped),

@@ -73,6 +73,7 @@ struct DevLists {
   double *M64 = nullptr, *L64 = nullptr, *L64stage = nullptr;
   void *part_s = nullptr, *part_c = nullptr;
   void *tmp_phi = nullptr, *tmp_grad = nullptr;
+  void *vec4 = nullptr, *tmp_hv = nullptr;  // backward with a gradient upstream
   bool stage_valid = false;
   // near-field stream (forked from / joined into the caller's stream)
   hipStream_t side = nullptr;
@@ -81,10 +82,11 @@ struct DevLists {
   hipEvent_t ev[FMM_NUM_PHASES + 2] = {};
   bool have_events = false, timing_valid = false, timed_serial = false;
   void release_scratch() {
-    void *ptrs[] = {M, L, Lstage, M64, L64, L64stage, part_s, part_c, tmp_phi, tmp_grad};
+    void *ptrs[] = {M, L, Lstage, M64, L64, L64stage, part_s, part_c, tmp_phi, tmp_grad,
+                    vec4, tmp_hv};
     for (void *p2 : ptrs)
       if (p2) (void)hipFree(p2);
-    M = L = Lstage = part_s = part_c = tmp_phi = tmp_grad = nullptr;
+    M = L = Lstage = part_s = part_c = tmp_phi = tmp_grad = vec4 = tmp_hv = nullptr;
     M64 = L64 = L64stage = nullptr;
     p = 0;
     prec = -1;
@@ -274,6 +276,8 @@ int ensure_scratch(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o) {
   if (!fp64) HIP_TRY(hipMalloc(&dv.part_c, np * 4 * real));
   HIP_TRY(hipMalloc(&dv.tmp_phi, std::max<int64_t>(1, n) * real));
   HIP_TRY(hipMalloc(&dv.tmp_grad, std::max<int64_t>(1, n) * 3 * real));
+  HIP_TRY(hipMalloc(&dv.vec4, std::max<int64_t>(1, n) * 4 * real));
+  HIP_TRY(hipMalloc(&dv.tmp_hv, std::max<int64_t>(1, n) * 3 * real));
   dv.p = o->p;
   dv.prec = o->precision;
   dv.n_top = n_top;
@@ -316,9 +320,12 @@ int check_pair(const fmm_tree *t, const fmm_lists *l) {
   return FMM_OK;
 }
 
-// Enqueue one forward evaluation; outputs in user order.
+// Enqueue one evaluation; outputs in user order.  mode kCharges: charges q ->
+// (phi, grad).  kDipoles: charges q plus dipoles -v_user (v_user [n][3]) ->
+// (phi, grad).  kHessVec: charges q; grad receives H[q] v_user.
 int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void *q, void *phi,
-                  void *grad, void *stream) {
+                  void *grad, void *stream, int mode = fmmlib::dev::kCharges,
+                  const void *v_user = nullptr) {
   namespace D = fmmlib::dev;
   const fmmlib::TreeData &td = t->data;
   const bool fp64 = o->precision == FMM_FP64;
@@ -361,6 +368,12 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
 
   if (int rc = mark(0, s)) return rc;
   LAUNCH_TRY(D::gather_charges(fp64, td.n, dt.perm, q, bodies, stream));
+  const void *vec = nullptr;
+  if (mode != D::kCharges) {
+    LAUNCH_TRY(D::gather_vectors(fp64, td.n, dt.perm, v_user, mode == D::kDipoles ? -1.0 : 1.0,
+                                 dv.vec4, stream));
+    vec = dv.vec4;
+  }
   if (int rc = mark(1, s)) return rc;
 
   // Near field: independent of the far field until the final combine.
@@ -370,14 +383,15 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
     HIP_TRY(hipStreamWaitEvent(ns, dv.fork, 0));
   }
   if (int rc = mark(8, ns)) return rc;
-  LAUNCH_TRY(D::p2p(fp64, mask_all, (int64_t)pl.items.size(), dv.items, dv.run_body,
-                    dv.run_prefix, bodies, dv.part_s, dv.part_c, ns));
+  LAUNCH_TRY(D::p2p(fp64, mode, mask_all, (int64_t)pl.items.size(), dv.items, dv.run_body,
+                    dv.run_prefix, bodies, vec, dv.part_s, dv.part_c, ns));
   if (int rc = mark(9, ns)) return rc;
   if (overlap) HIP_TRY(hipEventRecord(dv.join, ns));
 
   // Far field on the caller's stream.
   LAUNCH_TRY(D::p2m(p, fp64, (int64_t)pl.leaf_cell.size(), dv.leaf_cell, dt.body_begin, dt.n_body,
-                    geo, bodies, dv.M, dv.M64, n_top, stream));
+                    geo, bodies, mode == D::kDipoles ? vec : nullptr, dv.M, dv.M64, n_top,
+                    stream));
   if (int rc = mark(2, s)) return rc;
   for (int lev = max_level - 1; lev >= 0; --lev) {
     const int64_t c0 = td.level_begin[lev], c1 = td.level_begin[lev + 1];
@@ -418,8 +432,8 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   if (int rc = mark(5, s)) return rc;
   if (overlap) HIP_TRY(hipStreamWaitEvent(s, dv.join, 0));
   if (int rc = mark(6, s)) return rc;
-  LAUNCH_TRY(D::l2p_combine(p, fp64, td.n, dv.body_leaf, dv.leaf_cell, dv.leaf_pbase,
-                            dv.leaf_nchunk, dt.body_begin, dt.n_body, geo, dv.L, bodies,
+  LAUNCH_TRY(D::l2p_combine(p, fp64, mode, td.n, dv.body_leaf, dv.leaf_cell, dv.leaf_pbase,
+                            dv.leaf_nchunk, dt.body_begin, dt.n_body, geo, dv.L, bodies, vec,
                             dv.part_s, dv.part_c, dt.perm, phi, grad, stream));
   if (int rc = mark(7, s)) return rc;
   dv.timed_serial = !overlap;
@@ -617,28 +631,44 @@ int fmm_evaluate(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o, 
 
 int fmm_evaluate_backward(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o,
                           const void *q_dev, const void *grad_q_dev, const void *w_dev,
-                          void *dq_dev, void *dx_dev, void *stream) {
+                          const void *v_dev, void *dq_dev, void *dx_dev, void *stream) {
   if (int rc = check_pair(t, l)) return rc;
   if (int rc = check_opts(o)) return rc;
   if (t->data.n == 0) return FMM_OK;
-  if (!w_dev || (dx_dev && (!q_dev || !grad_q_dev))) {
-    set_error("fmm_evaluate_backward: w is required; dx needs q and grad_q");
+  if ((!w_dev && !v_dev) || (dx_dev && (!q_dev || !grad_q_dev))) {
+    set_error("fmm_evaluate_backward: w or v is required; dx needs q and grad_q");
+    return FMM_EINVAL;
+  }
+  if (!w_dev) {
+    set_error("fmm_evaluate_backward: w is required (pass zeros for a loss on grad only)");
     return FMM_EINVAL;
   }
   if (!dq_dev && !dx_dev) return FMM_OK;
   fmm_tree *tt = const_cast<fmm_tree *>(t);
   fmm_lists *ll = const_cast<fmm_lists *>(l);
+  namespace D = fmmlib::dev;
   try {
     const bool fp64 = o->precision == FMM_FP64;
     if (int rc = ensure_tree_device(tt, fp64)) return rc;
     if (int rc = ensure_lists_device(tt, ll)) return rc;
     if (int rc = ensure_scratch(tt, ll, o)) return rc;
-    void *phi_w = dq_dev ? dq_dev : ll->dev.tmp_phi;
-    void *grad_w = dx_dev ? ll->dev.tmp_grad : nullptr;
-    if (int rc = evaluate_impl(tt, ll, o, w_dev, phi_w, grad_w, stream)) return rc;
+    DevLists &dv = ll->dev;
+    void *phi_w = dq_dev ? dq_dev : dv.tmp_phi;
+    void *grad_w = dx_dev ? dv.tmp_grad : nullptr;
+    const void *hv = nullptr;
+    if (v_dev && dx_dev) {
+      // H[q] v at every body (charges q, per-target vectors v)
+      if (int rc = evaluate_impl(tt, ll, o, q_dev, nullptr, dv.tmp_hv, stream, D::kHessVec, v_dev))
+        return rc;
+      hv = dv.tmp_hv;
+    }
+    // Phi: charges w plus dipoles -v (or charges w alone)
+    if (int rc = evaluate_impl(tt, ll, o, w_dev, phi_w, grad_w, stream,
+                               v_dev ? D::kDipoles : D::kCharges, v_dev))
+      return rc;
     if (dx_dev)
-      LAUNCH_TRY(fmmlib::dev::backward_combine(fp64, t->data.n, q_dev, w_dev, grad_q_dev, grad_w,
-                                               dx_dev, stream));
+      LAUNCH_TRY(D::backward_combine(fp64, t->data.n, q_dev, w_dev, grad_q_dev, grad_w, hv, dx_dev,
+                                     stream));
     return FMM_OK;
   } catch (const std::bad_alloc &) {
     set_error("fmm_evaluate_backward: out of host memory");

@@ -26,13 +26,15 @@ namespace dev {
 namespace {
 
 // ----------------------------------------------------------------------------
-// P2M: one thread per leaf.
+// P2M: one thread per leaf.  With dipoles (DIP), a body's dipole s adds
+// sum_d s_d (X - x)^(n - e_d) / (n - e_d)! to M_n.
 // ----------------------------------------------------------------------------
-template <int P, typename Real>
+template <int P, typename Real, bool DIP>
 __global__ __launch_bounds__(64) void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
                            const int32_t *__restrict__ body_begin,
                            const int32_t *__restrict__ n_body, const double4 *__restrict__ geo,
-                           const typename Vec<Real>::V4 *__restrict__ bodies, Real *__restrict__ M,
+                           const typename Vec<Real>::V4 *__restrict__ bodies,
+                           const typename Vec<Real>::V4 *__restrict__ dip, Real *__restrict__ M,
                            double *__restrict__ M64, int64_t n_top) {
   constexpr int T = nterms(P), S = pad4(T);
   const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -48,6 +50,15 @@ __global__ __launch_bounds__(64) void p2m_kernel(int64_t n_leaves, const int32_t
     monomials<P, Real>(Real(g.x - (double)b.x), Real(g.y - (double)b.y), Real(g.z - (double)b.z),
                        mono);
     static_for<T>([&](auto I) { acc[decltype(I)::value] += b.w * mono[decltype(I)::value]; });
+    if constexpr (DIP) {
+      const typename Vec<Real>::V4 sd = dip[b0 + j];
+      static_for<T>([&](auto I) {
+        constexpr int t = decltype(I)::value;
+        if constexpr (kBasis<P>.lo[t][0] >= 0) acc[t] += sd.x * mono[kBasis<P>.lo[t][0]];
+        if constexpr (kBasis<P>.lo[t][1] >= 0) acc[t] += sd.y * mono[kBasis<P>.lo[t][1]];
+        if constexpr (kBasis<P>.lo[t][2] >= 0) acc[t] += sd.z * mono[kBasis<P>.lo[t][2]];
+      });
+    }
   }
   static_for<T>([&](auto I) { M[(int64_t)c * S + decltype(I)::value] = acc[decltype(I)::value]; });
   if (c < n_top)
@@ -206,14 +217,18 @@ __global__ void copy_top_kernel(int64_t n, const double *__restrict__ src, float
 
 // ----------------------------------------------------------------------------
 // L2P + near/far combine + scatter to user order: one thread per body.
+// HESS: the Hessian of the local expansion applied to the body's vector v,
+// (H v)_a = sum_b v_b sum_{k >= e_a + e_b} L_k (y - X)^(k-e_a-e_b) / (k-e_a-e_b)!,
+// is combined with the P2P Hessian-vector partials and written to grad_out.
 // ----------------------------------------------------------------------------
-template <int P, typename Real, bool KAHAN>
+template <int P, typename Real, bool KAHAN, bool HESS>
 __global__ __launch_bounds__(256) void l2p_combine_kernel(
     int64_t n, const int32_t *__restrict__ body_leaf, const int32_t *__restrict__ leaf_cell,
     const int32_t *__restrict__ leaf_pbase, const int32_t *__restrict__ leaf_nchunk,
     const int32_t *__restrict__ cell_body_begin, const int32_t *__restrict__ cell_n_body,
     const double4 *__restrict__ geo, const Real *__restrict__ L,
     const typename Vec<Real>::V4 *__restrict__ bodies,
+    const typename Vec<Real>::V4 *__restrict__ tvec,
     const typename Vec<Real>::V4 *__restrict__ part_s,
     const typename Vec<Real>::V4 *__restrict__ part_c, const int32_t *__restrict__ perm,
     Real *__restrict__ phi_out, Real *__restrict__ grad_out) {
@@ -231,13 +246,35 @@ __global__ __launch_bounds__(256) void l2p_combine_kernel(
   Real lc[T];
   load_row<T>(L + (int64_t)c * S, lc);
   Real f = Real(0), gx = Real(0), gy = Real(0), gz = Real(0);
-  static_for<T>([&](auto I) {
-    constexpr int t = decltype(I)::value;
-    f += lc[t] * mono[t];
-    if constexpr (kBasis<P>.lo[t][0] >= 0) gx += lc[t] * mono[kBasis<P>.lo[t][0]];
-    if constexpr (kBasis<P>.lo[t][1] >= 0) gy += lc[t] * mono[kBasis<P>.lo[t][1]];
-    if constexpr (kBasis<P>.lo[t][2] >= 0) gz += lc[t] * mono[kBasis<P>.lo[t][2]];
-  });
+  if constexpr (!HESS) {
+    static_for<T>([&](auto I) {
+      constexpr int t = decltype(I)::value;
+      f += lc[t] * mono[t];
+      if constexpr (kBasis<P>.lo[t][0] >= 0) gx += lc[t] * mono[kBasis<P>.lo[t][0]];
+      if constexpr (kBasis<P>.lo[t][1] >= 0) gy += lc[t] * mono[kBasis<P>.lo[t][1]];
+      if constexpr (kBasis<P>.lo[t][2] >= 0) gz += lc[t] * mono[kBasis<P>.lo[t][2]];
+    });
+  } else {
+    // six distinct second derivatives, then H v
+    Real h[3][3] = {};
+    static_for<T>([&](auto I) {
+      constexpr int t = decltype(I)::value;
+      static_for<3>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        if constexpr (kBasis<P>.lo[t][a] >= 0) {
+          static_for<3>([&](auto Bb) {
+            constexpr int b2 = decltype(Bb)::value;
+            if constexpr (b2 >= a && kBasis<P>.lo[kBasis<P>.lo[t][a]][b2] >= 0)
+              h[a][b2] += lc[t] * mono[kBasis<P>.lo[kBasis<P>.lo[t][a]][b2]];
+          });
+        }
+      });
+    });
+    const typename Vec<Real>::V4 v = tvec[i];
+    gx = h[0][0] * v.x + h[0][1] * v.y + h[0][2] * v.z;
+    gy = h[0][1] * v.x + h[1][1] * v.y + h[1][2] * v.z;
+    gz = h[0][2] * v.x + h[1][2] * v.y + h[2][2] * v.z;
+  }
   Real s4[4] = {0, 0, 0, 0}, c4[4] = {0, 0, 0, 0};
   const int nA = cell_n_body[c];
   const int64_t slot0 = (int64_t)leaf_pbase[a] + (i - cell_body_begin[c]);
@@ -261,7 +298,7 @@ __global__ __launch_bounds__(256) void l2p_combine_kernel(
     }
   }
   const int64_t u = perm[i];
-  phi_out[u] = (s4[0] - c4[0]) + f;
+  if (phi_out) phi_out[u] = (s4[0] - c4[0]) + f;
   if (grad_out) {
     grad_out[3 * u + 0] = (s4[1] - c4[1]) + gx;
     grad_out[3 * u + 1] = (s4[2] - c4[2]) + gy;
@@ -274,22 +311,30 @@ __global__ __launch_bounds__(256) void l2p_combine_kernel(
 #define FMM_LAUNCH_CHECK() return (int)hipGetLastError()
 
 int p2m(int p, bool fp64, int64_t n_leaves, const int32_t *leaf_cell, const int32_t *cell_body_begin,
-        const int32_t *cell_n_body, const double *geo, const void *bodies, void *M, double *M64,
-        int64_t n_top, void *stream) {
+        const int32_t *cell_n_body, const double *geo, const void *bodies, const void *dipoles,
+        void *M, double *M64, int64_t n_top, void *stream) {
   if (n_leaves == 0) return 0;
   const unsigned nb = blocks_for(n_leaves, 64);
+  const double4 *g = (const double4 *)geo;
   return with_p(p, [&](auto PC) {
     constexpr int PP = decltype(PC)::value;
-    if (fp64)
-      p2m_kernel<PP, double><<<nb, 64, 0, S_(stream)>>>(n_leaves, leaf_cell, cell_body_begin,
-                                                        cell_n_body, (const double4 *)geo,
-                                                        (const double4 *)bodies, (double *)M,
-                                                        M64, 0);
-    else
-      p2m_kernel<PP, float><<<nb, 64, 0, S_(stream)>>>(n_leaves, leaf_cell, cell_body_begin,
-                                                       cell_n_body, (const double4 *)geo,
-                                                       (const float4 *)bodies, (float *)M, M64,
-                                                       n_top);
+    if (fp64) {
+      const double4 *b = (const double4 *)bodies, *d = (const double4 *)dipoles;
+      if (dipoles)
+        p2m_kernel<PP, double, true><<<nb, 64, 0, S_(stream)>>>(
+            n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, (double *)M, M64, 0);
+      else
+        p2m_kernel<PP, double, false><<<nb, 64, 0, S_(stream)>>>(
+            n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, (double *)M, M64, 0);
+    } else {
+      const float4 *b = (const float4 *)bodies, *d = (const float4 *)dipoles;
+      if (dipoles)
+        p2m_kernel<PP, float, true><<<nb, 64, 0, S_(stream)>>>(
+            n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, (float *)M, M64, n_top);
+      else
+        p2m_kernel<PP, float, false><<<nb, 64, 0, S_(stream)>>>(
+            n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, (float *)M, M64, n_top);
+    }
   });
 }
 
@@ -365,26 +410,48 @@ int copy_top_locals(int p, int64_t n_top, const double *L64, float *L, void *str
   FMM_LAUNCH_CHECK();
 }
 
-int l2p_combine(int p, bool fp64, int64_t n, const int32_t *body_leaf, const int32_t *leaf_cell,
-                const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
+template <int PP, typename Real, bool HESS>
+void launch_l2p(unsigned nb, hipStream_t st, int64_t n, const int32_t *body_leaf,
+                const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
+                const int32_t *cell_body_begin, const int32_t *cell_n_body, const double4 *g,
+                const void *L, const void *bodies, const void *tvec, const void *part_s,
+                const void *part_c, const int32_t *perm, void *phi, void *grad) {
+  using V4 = typename Vec<Real>::V4;
+  constexpr bool kahan = std::is_same<Real, float>::value;
+  l2p_combine_kernel<PP, Real, kahan, HESS><<<nb, 256, 0, st>>>(
+      n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk, cell_body_begin, cell_n_body, g,
+      (const Real *)L, (const V4 *)bodies, (const V4 *)tvec, (const V4 *)part_s,
+      (const V4 *)part_c, perm, (Real *)phi, (Real *)grad);
+}
+
+int l2p_combine(int p, bool fp64, int mode, int64_t n, const int32_t *body_leaf,
+                const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
                 const int32_t *cell_body_begin, const int32_t *cell_n_body, const double *geo,
-                const void *L, const void *bodies, const void *part_s, const void *part_c,
-                const int32_t *perm, void *phi, void *grad, void *stream) {
+                const void *L, const void *bodies, const void *tvec, const void *part_s,
+                const void *part_c, const int32_t *perm, void *phi, void *grad, void *stream) {
   if (n == 0) return 0;
   const unsigned nb = blocks_for(n, 256);
   const double4 *g = (const double4 *)geo;
+  const hipStream_t st = S_(stream);
+  const bool hess = mode == kHessVec;
   return with_p(p, [&](auto PC) {
     constexpr int PP = decltype(PC)::value;
-    if (fp64)
-      l2p_combine_kernel<PP, double, false><<<nb, 256, 0, S_(stream)>>>(
-          n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk, cell_body_begin, cell_n_body, g,
-          (const double *)L, (const double4 *)bodies, (const double4 *)part_s, nullptr, perm,
-          (double *)phi, (double *)grad);
+    if (fp64 && hess)
+      launch_l2p<PP, double, true>(nb, st, n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
+                                   cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
+                                   nullptr, perm, nullptr, grad);
+    else if (fp64)
+      launch_l2p<PP, double, false>(nb, st, n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
+                                    cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
+                                    nullptr, perm, phi, grad);
+    else if (hess)
+      launch_l2p<PP, float, true>(nb, st, n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
+                                  cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
+                                  part_c, perm, nullptr, grad);
     else
-      l2p_combine_kernel<PP, float, true><<<nb, 256, 0, S_(stream)>>>(
-          n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk, cell_body_begin, cell_n_body, g,
-          (const float *)L, (const float4 *)bodies, (const float4 *)part_s,
-          (const float4 *)part_c, perm, (float *)phi, (float *)grad);
+      launch_l2p<PP, float, false>(nb, st, n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
+                                   cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
+                                   part_c, perm, phi, grad);
   });
 }
 

@@ -20,13 +20,26 @@ inline int stride(int p) { return (terms(p) + 3) & ~3; }
 int gather_charges(bool fp64, int64_t n, const int32_t *perm, const void *q_user, void *bodies,
                    void *stream);
 
-int p2p(bool fp64, bool mask_all, int64_t n_items, const P2PItem *items, const int32_t *run_body,
-        const int32_t *run_prefix, const void *bodies, void *part_s, void *part_c, void *stream);
+// What a P2P/L2P pass computes (see p2p.hip): charges -> (phi, grad);
+// charges + dipoles -> (phi, grad); charges with per-target vectors v ->
+// Hessian of the charge field applied to v.
+enum EvalMode { kCharges = 0, kDipoles = 1, kHessVec = 2 };
+
+// vec: [n] float4/double4 per-body dipoles (kDipoles) or per-target vectors
+// (kHessVec), Morton order; unused for kCharges.
+int p2p(bool fp64, int mode, bool mask_all, int64_t n_items, const P2PItem *items,
+        const int32_t *run_body, const int32_t *run_prefix, const void *bodies, const void *vec,
+        void *part_s, void *part_c, void *stream);
+
+// out[i] = sign * v[perm[i]] as a 4-vector (w = 0); v is user order [n][3].
+int gather_vectors(bool fp64, int64_t n, const int32_t *perm, const void *v_user, double sign,
+                   void *out, void *stream);
 
 // geo: [n_cells] double4 (centre x, y, z, radius).
+// dipoles: [n] 4-vectors in Morton order, or NULL for charges only.
 int p2m(int p, bool fp64, int64_t n_leaves, const int32_t *leaf_cell, const int32_t *cell_body_begin,
-        const int32_t *cell_n_body, const double *geo, const void *bodies, void *M, double *M64,
-        int64_t n_top, void *stream);
+        const int32_t *cell_n_body, const double *geo, const void *bodies, const void *dipoles,
+        void *M, double *M64, int64_t n_top, void *stream);
 
 // Parents are the cells [c0, c1) of one level; leaves among them are skipped.
 // child_fp64: children's multipoles are read from M64 (else from M).
@@ -47,14 +60,17 @@ int l2l(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *parent, const d
 
 int copy_top_locals(int p, int64_t n_top, const double *L64, float *L, void *stream);
 
-int l2p_combine(int p, bool fp64, int64_t n, const int32_t *body_leaf, const int32_t *leaf_cell,
-                const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
+// kHessVec: tvec holds the per-target vectors (Morton order) and grad receives
+// H v; phi is not written.
+int l2p_combine(int p, bool fp64, int mode, int64_t n, const int32_t *body_leaf,
+                const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
                 const int32_t *cell_body_begin, const int32_t *cell_n_body, const double *geo,
-                const void *L, const void *bodies, const void *part_s, const void *part_c,
-                const int32_t *perm, void *phi, void *grad, void *stream);
+                const void *L, const void *bodies, const void *tvec, const void *part_s,
+                const void *part_c, const int32_t *perm, void *phi, void *grad, void *stream);
 
+// dx = w * grad_q + q * grad_w (+ hv if not NULL), user order.
 int backward_combine(bool fp64, int64_t n, const void *q, const void *w, const void *grad_q,
-                     const void *grad_w, void *dx, void *stream);
+                     const void *grad_w, const void *hv, void *dx, void *stream);
 
 int direct_sum(const double *xyz, const double *q, int64_t n, const int64_t *targets, int64_t m,
                double *phi, double *grad, void *stream);

@@ -16,16 +16,37 @@ __global__ void gather_kernel(int64_t n, const int32_t *__restrict__ perm,
   if (i < n) bodies[i].w = q[perm[i]];
 }
 
-// dL/dx = w * grad[q] + q * grad[w], user order.
+// Per-body vectors into Morton order: out[i] = sign * v[perm[i]], w = 0.
+template <typename Real>
+__global__ void gather_vec_kernel(int64_t n, const int32_t *__restrict__ perm,
+                                  const Real *__restrict__ v, Real sign,
+                                  typename Vec<Real>::V4 *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t u = perm[i];
+  typename Vec<Real>::V4 o;
+  o.x = sign * v[3 * u];
+  o.y = sign * v[3 * u + 1];
+  o.z = sign * v[3 * u + 2];
+  o.w = Real(0);
+  out[i] = o;
+}
+
+// dL/dx = w * grad[q] + q * grad[w] (+ H[q] v), user order.
 template <typename Real>
 __global__ void backward_combine_kernel(int64_t n, const Real *__restrict__ q,
                                         const Real *__restrict__ w, const Real *__restrict__ gq,
-                                        const Real *__restrict__ gw, Real *__restrict__ dx) {
+                                        const Real *__restrict__ gw, const Real *__restrict__ hv,
+                                        Real *__restrict__ dx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const Real qi = q[i], wi = w[i];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) dx[3 * i + d] = wi * gq[3 * i + d] + qi * gw[3 * i + d];
+  for (int d = 0; d < 3; ++d) {
+    Real v = wi * gq[3 * i + d] + qi * gw[3 * i + d];
+    if (hv) v += hv[3 * i + d];
+    dx[3 * i + d] = v;
+  }
 }
 
 // FP64 direct sum: one 256-thread work-group per target, fixed-order reduction.
@@ -94,17 +115,29 @@ int gather_charges(bool fp64, int64_t n, const int32_t *perm, const void *q_user
   FMM_LAUNCH_CHECK();
 }
 
+int gather_vectors(bool fp64, int64_t n, const int32_t *perm, const void *v_user, double sign,
+                   void *out, void *stream) {
+  if (n == 0) return 0;
+  if (fp64)
+    gather_vec_kernel<double><<<blocks_for(n, 256), 256, 0, S_(stream)>>>(
+        n, perm, (const double *)v_user, sign, (double4 *)out);
+  else
+    gather_vec_kernel<float><<<blocks_for(n, 256), 256, 0, S_(stream)>>>(
+        n, perm, (const float *)v_user, (float)sign, (float4 *)out);
+  FMM_LAUNCH_CHECK();
+}
+
 int backward_combine(bool fp64, int64_t n, const void *q, const void *w, const void *grad_q,
-                     const void *grad_w, void *dx, void *stream) {
+                     const void *grad_w, const void *hv, void *dx, void *stream) {
   if (n == 0) return 0;
   if (fp64)
     backward_combine_kernel<double><<<blocks_for(n, 256), 256, 0, S_(stream)>>>(
         n, (const double *)q, (const double *)w, (const double *)grad_q, (const double *)grad_w,
-        (double *)dx);
+        (const double *)hv, (double *)dx);
   else
     backward_combine_kernel<float><<<blocks_for(n, 256), 256, 0, S_(stream)>>>(
         n, (const float *)q, (const float *)w, (const float *)grad_q, (const float *)grad_w,
-        (float *)dx);
+        (const float *)hv, (float *)dx);
   FMM_LAUNCH_CHECK();
 }
 

@@ -13,16 +13,29 @@ namespace {
 // of one stream).  Within a batch each lane sums in plain arithmetic; the
 // batch partial is then added with Kahan compensation (FP32), and the K
 // streams and the chunks of a row are merged with the same compensation.
+//
+// Modes (compile time):
+//   kCharges      sources are charges q: (phi, grad phi)
+//   kDipoles      sources carry charges q and dipoles s; a dipole s at x_j
+//                 has the potential s . (x_j - y) / |x_j - y|^3: (phi, grad phi)
+//   kHessVec      sources are charges; each target i carries a vector v_i and
+//                 gets the Hessian of the charge field applied to it,
+//                 sum_j q_j (3 (d.v) d - r^2 v) / r^5, d = x_j - x_i: (0, H v)
+// The per-target result is always a 4-vector, so the partial-sum layout and
+// the merge are shared.
 // ----------------------------------------------------------------------------
 constexpr int kNB = 512;
 static_assert(kP2PMaxRuns == 256, "LDS run table size");
 
-template <typename Real, int R, bool KAHAN, bool MASK, typename IndexFn>
+template <typename Real, int MODE, int R, bool KAHAN, bool MASK, typename IndexFn>
 __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
                                           const typename Vec<Real>::V4 *__restrict__ bodies,
-                                          typename Vec<Real>::V4 *src, int s, int K,
+                                          const typename Vec<Real>::V4 *__restrict__ dipoles,
+                                          typename Vec<Real>::V4 *src,
+                                          typename Vec<Real>::V4 *srcd, int s, int K,
                                           const Real (&xi)[R], const Real (&yi)[R],
-                                          const Real (&zi)[R], Real (&S)[R][4], Real (&C)[R][4]) {
+                                          const Real (&zi)[R], const Real (&vt)[R][3],
+                                          Real (&S)[R][4], Real (&C)[R][4]) {
   using V4 = typename Vec<Real>::V4;
   const int lane = threadIdx.x;
   const Real far = Vec<Real>::kFar;
@@ -31,16 +44,20 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
 #pragma unroll
     for (int q = 0; q <= kNB / 64; ++q) {
       const int pos = q * 64 + lane;
-      V4 v;
+      V4 v, dv;
       if (pos < nb) {
-        v = bodies[body_of(off + pos)];
+        const int b = body_of(off + pos);
+        v = bodies[b];
+        if constexpr (MODE == kDipoles) dv = dipoles[b];
       } else {
         v.x = far;
         v.y = far;
         v.z = far;
         v.w = Real(0);
+        if constexpr (MODE == kDipoles) dv.x = dv.y = dv.z = dv.w = Real(0);
       }
       src[pos] = v;
+      if constexpr (MODE == kDipoles) srcd[pos] = dv;
     }
     __syncthreads();
     const int iters = (nb + K - 1) / K;
@@ -50,18 +67,38 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
 #pragma unroll 2
     for (int j = 0; j < iters; ++j) {
       const V4 sj = src[s + K * j];
+      V4 dj;
+      if constexpr (MODE == kDipoles) dj = srcd[s + K * j];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const Real dx = sj.x - xi[r], dy = sj.y - yi[r], dz = sj.z - zi[r];
         const Real r2 = dx * dx + dy * dy + dz * dz;
         Real inv = rsqrt_(r2);
         if constexpr (MASK) inv = r2 > Real(0) ? inv : Real(0);
-        const Real qr = sj.w * inv;
-        const Real qr3 = qr * (inv * inv);
-        p[r][0] += qr;
-        p[r][1] += qr3 * dx;
-        p[r][2] += qr3 * dy;
-        p[r][3] += qr3 * dz;
+        if constexpr (MODE == kCharges) {
+          const Real qr = sj.w * inv;
+          const Real qr3 = qr * (inv * inv);
+          p[r][0] += qr;
+          p[r][1] += qr3 * dx;
+          p[r][2] += qr3 * dy;
+          p[r][3] += qr3 * dz;
+        } else if constexpr (MODE == kDipoles) {
+          const Real inv2 = inv * inv;
+          const Real inv3 = inv * inv2;
+          const Real sd3 = (dj.x * dx + dj.y * dy + dj.z * dz) * inv3;
+          const Real t = sj.w * inv3 + Real(3) * sd3 * inv2;
+          p[r][0] += sj.w * inv + sd3;
+          p[r][1] += t * dx - dj.x * inv3;
+          p[r][2] += t * dy - dj.y * inv3;
+          p[r][3] += t * dz - dj.z * inv3;
+        } else {
+          const Real inv2 = inv * inv;
+          const Real q5 = sj.w * (inv * inv2) * inv2;
+          const Real dv3 = Real(3) * (dx * vt[r][0] + dy * vt[r][1] + dz * vt[r][2]);
+          p[r][1] += q5 * (dv3 * dx - r2 * vt[r][0]);
+          p[r][2] += q5 * (dv3 * dy - r2 * vt[r][1]);
+          p[r][3] += q5 * (dv3 * dz - r2 * vt[r][2]);
+        }
       }
     }
 #pragma unroll
@@ -81,13 +118,15 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
   }
 }
 
-template <typename Real, int R, bool KAHAN, bool MASK_ALL>
+template <typename Real, int MODE, int R, bool KAHAN, bool MASK_ALL>
 __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__restrict__ run_body,
                                          const int32_t *__restrict__ run_prefix,
                                          const typename Vec<Real>::V4 *__restrict__ bodies,
+                                         const typename Vec<Real>::V4 *__restrict__ vec,
                                          typename Vec<Real>::V4 *__restrict__ out_s,
                                          typename Vec<Real>::V4 *__restrict__ out_c,
-                                         typename Vec<Real>::V4 *src, int32_t *rb, int32_t *rp) {
+                                         typename Vec<Real>::V4 *src,
+                                         typename Vec<Real>::V4 *srcd, int32_t *rb, int32_t *rp) {
   using V4 = typename Vec<Real>::V4;
   const int lane = threadIdx.x;
   const int nt = it.tgt_cfg & 0xff;
@@ -97,15 +136,22 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
   const int u = lane - s * L;
   if (s >= K) s = K - 1;  // spare lanes repeat the last stream; not merged
 
-  Real xi[R], yi[R], zi[R];
+  Real xi[R], yi[R], zi[R], vt[R][3];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int t = u + L * r;
+    vt[r][0] = vt[r][1] = vt[r][2] = Real(0);
     if (t < nt) {
       const V4 b = bodies[it.tgt_begin + t];
       xi[r] = b.x;
       yi[r] = b.y;
       zi[r] = b.z;
+      if constexpr (MODE == kHessVec) {
+        const V4 v = vec[it.tgt_begin + t];
+        vt[r][0] = v.x;
+        vt[r][1] = v.y;
+        vt[r][2] = v.z;
+      }
     } else {
       xi[r] = yi[r] = zi[r] = -Vec<Real>::kFar;
     }
@@ -118,8 +164,9 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
 
   if (it.self_n > 0) {
     const int b0 = it.self_begin;
-    p2p_phase<Real, R, KAHAN, true>(
-        it.self_n, [&](int c) { return b0 + c; }, bodies, src, s, K, xi, yi, zi, S, C);
+    p2p_phase<Real, MODE, R, KAHAN, true>(
+        it.self_n, [&](int c) { return b0 + c; }, bodies, vec, src, srcd, s, K, xi, yi, zi, vt, S,
+        C);
   }
   if (it.n_src > 0) {
     for (int r = lane; r < it.n_runs; r += 64) {
@@ -129,13 +176,13 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
     if (lane == 0) rp[it.n_runs] = it.n_src;
     __syncthreads();
     int ri = 0;
-    p2p_phase<Real, R, KAHAN, MASK_ALL>(
+    p2p_phase<Real, MODE, R, KAHAN, MASK_ALL>(
         it.n_src,
         [&](int c) {
           while (rp[ri + 1] <= c) ++ri;
           return rb[ri] + (c - rp[ri]);
         },
-        bodies, src, s, K, xi, yi, zi, S, C);
+        bodies, vec, src, srcd, s, K, xi, yi, zi, vt, S, C);
   }
 
   // Merge the K streams (lanes s*L + u) into the lanes of stream 0.
@@ -175,24 +222,27 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
   }
 }
 
-template <typename Real, bool KAHAN, bool MASK_ALL>
+// vec: per-body dipoles (kDipoles) or per-target vectors (kHessVec), Morton order.
+template <typename Real, int MODE, bool KAHAN, bool MASK_ALL>
 __global__ __launch_bounds__(64) void p2p_kernel(const P2PItem *__restrict__ items,
                                                  const int32_t *__restrict__ run_body,
                                                  const int32_t *__restrict__ run_prefix,
                                                  const typename Vec<Real>::V4 *__restrict__ bodies,
+                                                 const typename Vec<Real>::V4 *__restrict__ vec,
                                                  typename Vec<Real>::V4 *__restrict__ out_s,
                                                  typename Vec<Real>::V4 *__restrict__ out_c) {
   using V4 = typename Vec<Real>::V4;
   __shared__ V4 src[kNB + 64];
+  __shared__ V4 srcd[MODE == kDipoles ? kNB + 64 : 1];
   __shared__ int32_t rb[kP2PMaxRuns];
   __shared__ int32_t rp[kP2PMaxRuns + 1];
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const P2PItem it = items[w];
   switch ((it.tgt_cfg >> 8) & 0xff) {
-#define FMM_P2P_CASE(RR)                                                                          \
-  case RR:                                                                                        \
-    p2p_item<Real, RR, KAHAN, MASK_ALL>(it, run_body, run_prefix, bodies, out_s, out_c, src, rb, \
-                                        rp);                                                      \
+#define FMM_P2P_CASE(RR)                                                                  \
+  case RR:                                                                                \
+    p2p_item<Real, MODE, RR, KAHAN, MASK_ALL>(it, run_body, run_prefix, bodies, vec, out_s, \
+                                              out_c, src, srcd, rb, rp);                   \
     break;
     FMM_P2P_CASE(1)
     FMM_P2P_CASE(2)
@@ -208,30 +258,52 @@ __global__ __launch_bounds__(64) void p2p_kernel(const P2PItem *__restrict__ ite
   }
 }
 
+template <typename Real, int MODE>
+void launch_p2p(bool mask_all, unsigned G, hipStream_t st, const P2PItem *items,
+                const int32_t *run_body, const int32_t *run_prefix, const void *bodies,
+                const void *vec, void *part_s, void *part_c) {
+  using V4 = typename Vec<Real>::V4;
+  constexpr bool kahan = std::is_same<Real, float>::value;
+  const V4 *b = (const V4 *)bodies;
+  const V4 *v = (const V4 *)vec;
+  if (mask_all)
+    p2p_kernel<Real, MODE, kahan, true><<<G, 64, 0, st>>>(items, run_body, run_prefix, b, v,
+                                                          (V4 *)part_s, (V4 *)part_c);
+  else
+    p2p_kernel<Real, MODE, kahan, false><<<G, 64, 0, st>>>(items, run_body, run_prefix, b, v,
+                                                           (V4 *)part_s, (V4 *)part_c);
+}
+
 }  // namespace
 
-#define FMM_LAUNCH_CHECK() return (int)hipGetLastError()
-
-int p2p(bool fp64, bool mask_all, int64_t n_items, const P2PItem *items, const int32_t *run_body,
-        const int32_t *run_prefix, const void *bodies, void *part_s, void *part_c, void *stream) {
+int p2p(bool fp64, int mode, bool mask_all, int64_t n_items, const P2PItem *items,
+        const int32_t *run_body, const int32_t *run_prefix, const void *bodies, const void *vec,
+        void *part_s, void *part_c, void *stream) {
   if (n_items == 0) return 0;
   const unsigned G = (unsigned)n_items;
+  const hipStream_t st = S_(stream);
   if (fp64) {
-    if (mask_all)
-      p2p_kernel<double, false, true><<<G, 64, 0, S_(stream)>>>(
-          items, run_body, run_prefix, (const double4 *)bodies, (double4 *)part_s, nullptr);
+    if (mode == kCharges)
+      launch_p2p<double, kCharges>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
+                                   part_s, nullptr);
+    else if (mode == kDipoles)
+      launch_p2p<double, kDipoles>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
+                                   part_s, nullptr);
     else
-      p2p_kernel<double, false, false><<<G, 64, 0, S_(stream)>>>(
-          items, run_body, run_prefix, (const double4 *)bodies, (double4 *)part_s, nullptr);
+      launch_p2p<double, kHessVec>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
+                                   part_s, nullptr);
   } else {
-    if (mask_all)
-      p2p_kernel<float, true, true><<<G, 64, 0, S_(stream)>>>(
-          items, run_body, run_prefix, (const float4 *)bodies, (float4 *)part_s, (float4 *)part_c);
+    if (mode == kCharges)
+      launch_p2p<float, kCharges>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
+                                  part_s, part_c);
+    else if (mode == kDipoles)
+      launch_p2p<float, kDipoles>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
+                                  part_s, part_c);
     else
-      p2p_kernel<float, true, false><<<G, 64, 0, S_(stream)>>>(
-          items, run_body, run_prefix, (const float4 *)bodies, (float4 *)part_s, (float4 *)part_c);
+      launch_p2p<float, kHessVec>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
+                                  part_s, part_c);
   }
-  FMM_LAUNCH_CHECK();
+  return (int)hipGetLastError();
 }
 
 }  // namespace dev

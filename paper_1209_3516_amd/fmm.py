@@ -86,8 +86,8 @@ def lib():
         "fmm_lists_stats": ([vp, ctypes.POINTER(_ListStats)], i32),
         "fmm_lists_free": ([vp], None),
         "fmm_evaluate": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp], i32),
-        "fmm_evaluate_backward": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp, vp, vp],
-                                  i32),
+        "fmm_evaluate_backward": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp, vp, vp,
+                                   vp], i32),
         "fmm_direct": ([vp, vp, i64, vp, i64, vp, vp, vp], i32),
         "fmm_last_timings": ([vp, ctypes.POINTER(dbl)], i32),
         "fmm_last_error": ([], ctypes.c_char_p),
@@ -261,17 +261,20 @@ def evaluate(tree, lists, q, p, precision="mixed", grad=True, timing=False, keep
 
 
 def evaluate_backward(tree, lists, q, grad_q, w, p, precision="mixed", need_dq=True,
-                      need_dx=True, fp64_top_levels=-1):
-    """Backward of L = sum_i w_i phi_i: returns (dL/dq [n], dL/dx [n,3])."""
+                      need_dx=True, fp64_top_levels=-1, v=None):
+    """Backward of L = sum_i w_i phi_i + sum_i v_i . grad_i (v optional):
+    returns (dL/dq [n], dL/dx [n,3])."""
     import torch
     dt = _dtype(precision)
     _check_tensor(w, tree.n, dt, "w")
+    if v is not None:
+        _check_tensor(v, tree.n, dt, "v", 3)
     dq = torch.empty(tree.n, dtype=dt, device=w.device) if need_dq else None
     dx = torch.empty(tree.n, 3, dtype=dt, device=w.device) if need_dx else None
     o = _opts(p, precision, 0, fp64_top_levels)
     _check(lib().fmm_evaluate_backward(tree._h, lists._h, ctypes.byref(o), _t_ptr(q),
-                                       _t_ptr(grad_q), _t_ptr(w), _t_ptr(dq), _t_ptr(dx),
-                                       _stream()))
+                                       _t_ptr(grad_q), _t_ptr(w), _t_ptr(v), _t_ptr(dq),
+                                       _t_ptr(dx), _stream()))
     return dq, dx
 
 
@@ -333,7 +336,33 @@ def _make_autograd():
                                        need_dx=need_dx, fp64_top_levels=top)
             return dx, dq, None, None, None, None, None
 
-    return FMMPotential
+    class FMMField(torch.autograd.Function):
+        """(phi, grad phi) = FMM(x, q), both differentiable, tree and lists fixed.
+        Backward of L = sum w.phi + sum v.grad: dL/dq = Phi (charges w plus
+        dipoles -v), dL/dx = w grad[q] + q grad Phi + H[q] v."""
+
+        @staticmethod
+        def forward(ctx, x, q, tree, lists, p, precision, fp64_top_levels):
+            phi, g = evaluate(tree, lists, q.detach().contiguous(), p, precision, grad=True,
+                              fp64_top_levels=fp64_top_levels)
+            ctx.save_for_backward(q, g)
+            ctx.cfg = (tree, lists, p, precision, fp64_top_levels)
+            return phi, g
+
+        @staticmethod
+        def backward(ctx, w, v):
+            q, g = ctx.saved_tensors
+            tree, lists, p, precision, top = ctx.cfg
+            need_dx, need_dq = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            if w is None:
+                w = torch.zeros_like(q)
+            dq, dx = evaluate_backward(tree, lists, q.detach().contiguous(), g, w.contiguous(),
+                                       p, precision, need_dq=need_dq, need_dx=need_dx,
+                                       fp64_top_levels=top,
+                                       v=None if v is None else v.contiguous())
+            return dx, dq, None, None, None, None, None
+
+    return FMMPotential, FMMField
 
 
 _autograd_fn = None
@@ -346,4 +375,14 @@ def potential(x, q, tree, lists, p, precision="mixed", fp64_top_levels=-1):
     global _autograd_fn
     if _autograd_fn is None:
         _autograd_fn = _make_autograd()
-    return _autograd_fn.apply(x, q, tree, lists, p, precision, fp64_top_levels)
+    return _autograd_fn[0].apply(x, q, tree, lists, p, precision, fp64_top_levels)
+
+
+def field(x, q, tree, lists, p, precision="mixed", fp64_top_levels=-1):
+    """Differentiable potential and gradient: returns (phi [n], grad [n,3]); a
+    loss may depend on both (the backward then also uses dipole sources and
+    Hessian-vector products)."""
+    global _autograd_fn
+    if _autograd_fn is None:
+        _autograd_fn = _make_autograd()
+    return _autograd_fn[1].apply(x, q, tree, lists, p, precision, fp64_top_levels)

@@ -167,3 +167,110 @@ def test_injected_device_fault_leaves_handles_usable():
     again, _ = fmm.evaluate(t, lst, qt, 4)
     torch.cuda.synchronize()
     assert torch.equal(ref, again)
+
+
+# --- loss on the gradient output as well: L = sum w.phi + sum v.grad ----------
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_backward_with_gradient_upstream_matches_oracle(precision):
+    n = 6000
+    x, q, w, t = _setup(n, ncrit=32)
+    v = W.dipoles(n)
+    lst = fmm.Lists(t, 0.4)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    qt = torch.tensor(q, dtype=dt, device=DEV)
+    wt = torch.tensor(w, dtype=dt, device=DEV)
+    vt = torch.tensor(v, dtype=dt, device=DEV)
+    _, gq = fmm.evaluate(t, lst, qt, 4, precision)
+    dq, dx = fmm.evaluate_backward(t, lst, qt, gq, wt, 4, precision, v=vt)
+    torch.cuda.synchronize()
+    o = O.OracleFMM(x, 32, 0.4)
+    _, rgq, hv = O.evaluate_general(o, 4, q, v=v)
+    Phi, gPhi, _ = O.evaluate_general(o, 4, w, s=-v)
+    want_dx = w[:, None] * rgq + q[:, None] * gPhi + hv
+    tol = 1e-12 if precision == "fp64" else 3e-5
+    assert rel(dq.double().cpu().numpy(), Phi) <= tol
+    assert rel(dx.double().cpu().numpy(), want_dx) <= tol
+
+
+def test_gradient_upstream_finite_differences():
+    n = 800
+    x, q, w, t = _setup(n, ncrit=32)
+    v = W.dipoles(n)
+    lst = fmm.Lists(t, 0.45)
+    qt = torch.tensor(q, dtype=torch.float64, device=DEV)
+    wt = torch.tensor(w, dtype=torch.float64, device=DEV)
+    vt = torch.tensor(v, dtype=torch.float64, device=DEV)
+    _, gq = fmm.evaluate(t, lst, qt, 5, "fp64")
+    dq, dx = fmm.evaluate_backward(t, lst, qt, gq, wt, 5, "fp64", v=vt)
+    dq, dx = dq.cpu().numpy(), dx.cpu().numpy()
+
+    def loss(xx, qq):
+        t.set_positions(xx)
+        phi, g = fmm.evaluate(t, lst, torch.tensor(qq, dtype=torch.float64, device=DEV), 5, "fp64")
+        return float(np.dot(w, phi.cpu().numpy()) + np.sum(v * g.cpu().numpy()))
+
+    rng = np.random.default_rng(31)
+    h = 1e-6
+    rms = np.sqrt(np.mean(dx ** 2))
+    for _ in range(12):
+        i, d = int(rng.integers(n)), int(rng.integers(3))
+        xp, xm = x.copy(), x.copy()
+        xp[i, d] += h
+        xm[i, d] -= h
+        fd = (loss(xp, q) - loss(xm, q)) / (2 * h)
+        assert abs(fd - dx[i, d]) <= 1e-5 * max(1.0, abs(dx[i, d]), rms), (i, d, fd, dx[i, d])
+    t.set_positions(x)
+    for _ in range(12):
+        j = int(rng.integers(n))
+        qp, qm = q.copy(), q.copy()
+        qp[j] += h
+        qm[j] -= h
+        fd = (loss(x, qp) - loss(x, qm)) / (2 * h)
+        assert abs(fd - dq[j]) <= 1e-6 * max(1.0, abs(dq[j]))
+
+
+def test_gradient_upstream_against_direct_sum():
+    n = 20_000
+    x, q, w, t = _setup(n, ncrit=64)
+    v = W.dipoles(n)
+    lst = fmm.Lists(t, 0.4)
+    qt = torch.tensor(q, dtype=torch.float32, device=DEV)
+    wt = torch.tensor(w, dtype=torch.float32, device=DEV)
+    vt = torch.tensor(v, dtype=torch.float32, device=DEV)
+    phi, gq = fmm.evaluate(t, lst, qt, 6)
+    dq, dx = fmm.evaluate_backward(t, lst, qt, gq, wt, 6, v=vt)
+    torch.cuda.synchronize()
+    tg = W.sample_targets(n, 500)
+    _, gq_d, hv_d = O.direct_general(x, q, None, tg, v[tg])
+    Phi_d, gPhi_d, _ = O.direct_general(x, w, -v, tg)
+    want_dx = w[tg, None] * gq_d + q[tg, None] * gPhi_d + hv_d
+    e_fwd = rel(gq.double().cpu().numpy()[tg], gq_d)
+    assert rel(dq.double().cpu().numpy()[tg], Phi_d) <= 10 * e_fwd + 1e-5
+    assert rel(dx.double().cpu().numpy()[tg], want_dx) <= 10 * e_fwd + 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_field_autograd(precision):
+    n = 5000
+    x, q, w, t = _setup(n, ncrit=32)
+    v = W.dipoles(n)
+    lst = fmm.Lists(t, 0.4)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    xt = torch.tensor(x, dtype=dt, device=DEV, requires_grad=True)
+    qt = torch.tensor(q, dtype=dt, device=DEV, requires_grad=True)
+    wt = torch.tensor(w, dtype=dt, device=DEV)
+    vt = torch.tensor(v, dtype=dt, device=DEV)
+    phi, g = fmm.field(xt, qt, t, lst, 4, precision)
+    ((wt * phi).sum() + (vt * g).sum()).backward()
+    _, gq = fmm.evaluate(t, lst, qt.detach(), 4, precision)
+    dq, dx = fmm.evaluate_backward(t, lst, qt.detach(), gq, wt, 4, precision, v=vt)
+    assert torch.equal(qt.grad, dq)
+    assert torch.equal(xt.grad, dx)
+    # loss on the gradient only
+    q2 = torch.tensor(q, dtype=dt, device=DEV, requires_grad=True)
+    _, g2 = fmm.field(xt.detach(), q2, t, lst, 4, precision)
+    (vt * g2).sum().backward()
+    dq2, _ = fmm.evaluate_backward(t, lst, qt.detach(), gq, torch.zeros_like(wt), 4, precision,
+                                   v=vt, need_dx=False)
+    assert torch.equal(q2.grad, dq2)

@@ -141,8 +141,12 @@ def test_invalid_arguments_are_rejected_without_gpu():
     assert L.fmm_evaluate(t2._h, lst._h, ctypes.byref(o), dummy, dummy, None,
                           None) == fmm.FMM_ESTATE
     assert b"another tree" in L.fmm_last_error()
-    assert L.fmm_evaluate_backward(t._h, lst._h, ctypes.byref(o), dummy, None, dummy, None,
+    # dx without grad_q
+    assert L.fmm_evaluate_backward(t._h, lst._h, ctypes.byref(o), dummy, None, dummy, None, None,
                                    dummy, None) == fmm.FMM_EINVAL
+    # no w
+    assert L.fmm_evaluate_backward(t._h, lst._h, ctypes.byref(o), dummy, dummy, None, dummy,
+                                   dummy, dummy, None) == fmm.FMM_EINVAL
     assert L.fmm_last_timings(lst._h, (ctypes.c_double * 8)()) == fmm.FMM_ESTATE
     assert L.fmm_copy_expansions(lst._h, 0, dummy) == fmm.FMM_ESTATE
     assert L.fmm_num_terms(0) == -1 and L.fmm_num_terms(4) == 20 and L.fmm_num_terms(8) == 120
