@@ -28,6 +28,11 @@
  *  - Handles (fmm_tree, fmm_lists) own host memory and, once a device call
  *    has been made, device memory; a handle is used from one host thread and
  *    one stream at a time.
+ *  - Environment: FMM_LOG=1 prints tree and list statistics to stderr (host
+ *    calls only).  FMM_FAULT_INJECT=alloc:K makes the K-th allocation
+ *    checkpoint of a tree build or traversal fail (FMM_ENOMEM, nothing
+ *    leaked); FMM_FAULT_INJECT=launch:K makes the K-th kernel launch of each
+ *    evaluation report FMM_EDEVICE instead of launching.  For tests.
  */
 #ifndef PAPER_1209_3516_AMD_FMM_H
 #define PAPER_1209_3516_AMD_FMM_H

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -37,6 +38,7 @@ int fault_launch_target() {
   return std::atoi(s + 7);
 }
 thread_local int g_launch_counter = 0;
+thread_local int g_alloc_counter = 0;
 
 struct DevTree {
   int device = -1;
@@ -119,6 +121,15 @@ struct fmm_lists {
   fmmlib::ListData data;
   DevLists dev;
 };
+
+namespace fmmlib {
+void reset_alloc_checkpoints() { g_alloc_counter = 0; }
+void alloc_checkpoint() {
+  const char *s = std::getenv("FMM_FAULT_INJECT");
+  if (!s || std::strncmp(s, "alloc:", 6) != 0) return;
+  if (++g_alloc_counter == std::atoi(s + 6)) throw std::bad_alloc();
+}
+}  // namespace fmmlib
 
 namespace {
 
@@ -482,6 +493,7 @@ int fmm_tree_build(const double *xyz, int64_t n, int ncrit, fmm_tree **out) {
   }
   *out = nullptr;
   fmm_tree *t = nullptr;
+  fmmlib::reset_alloc_checkpoints();
   try {
     t = new fmm_tree();
     std::string err;
@@ -497,6 +509,10 @@ int fmm_tree_build(const double *xyz, int64_t n, int ncrit, fmm_tree **out) {
     return FMM_ENOMEM;
   }
   t->data.id = g_next_tree_id++;
+  if (std::getenv("FMM_LOG"))
+    std::fprintf(stderr, "[fmm] tree: n=%lld ncrit=%d cells=%lld leaves=%lld depth=%d fp32_exact=%d\n",
+                 (long long)n, ncrit, (long long)t->data.n_cells(), (long long)t->data.n_leaves,
+                 t->data.max_level, (int)t->data.fp32_exact);
   *out = t;
   return FMM_OK;
 }
@@ -566,6 +582,7 @@ int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **ou
   }
   *out = nullptr;
   fmm_lists *l = nullptr;
+  fmmlib::reset_alloc_checkpoints();
   try {
     l = new fmm_lists();
     fmmlib::dual_traverse(t->data, theta, (flags & FMM_LEAF_FIRST) != 0, l->data);
@@ -574,6 +591,11 @@ int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **ou
     set_error("fmm_traverse: out of host memory");
     return FMM_ENOMEM;
   }
+  if (std::getenv("FMM_LOG"))
+    std::fprintf(stderr, "[fmm] lists: theta=%g %s p2p=%lld m2l=%lld pairs=%lld\n", theta,
+                 (flags & FMM_LEAF_FIRST) ? "leaf-first" : "mac-first",
+                 (long long)l->data.p2p_col.size(), (long long)l->data.m2l_col.size(),
+                 (long long)l->data.p2p_pairs);
   *out = l;
   return FMM_OK;
 }

@@ -77,6 +77,12 @@ struct P2PPlan {
 void p2p_lane_layout(int nt, int *R, int *L, int *K);
 
 constexpr int kP2PMaxRuns = 256;
+
+// Fault injection for failure-handling tests: with FMM_FAULT_INJECT=alloc:K
+// the K-th checkpoint of a tree build or traversal (counted from 1 within
+// that call) throws std::bad_alloc, as a failed host allocation would.
+void alloc_checkpoint();
+void reset_alloc_checkpoints();
 constexpr int kP2PChunkSources = 8192;
 
 int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string &err);

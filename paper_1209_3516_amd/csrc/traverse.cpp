@@ -117,6 +117,7 @@ void dual_traverse(const TreeData &t, double theta, bool leaf_first, ListData &l
 #ifdef _OPENMP
   nthreads = omp_get_max_threads();
 #endif
+  alloc_checkpoint();
   std::vector<PairBuf> bufs(nthreads + 1);
   if (l.n_rows > 0) {
     // Breadth-first expansion until there is enough independent work.
@@ -149,7 +150,9 @@ void dual_traverse(const TreeData &t, double theta, bool leaf_first, ListData &l
       }
     }
   }
+  alloc_checkpoint();
   to_csr(bufs, false, l.n_rows, l.p2p_ptr, l.p2p_col);
+  alloc_checkpoint();
   to_csr(bufs, true, l.n_rows, l.m2l_ptr, l.m2l_col);
 
   int64_t pairs = 0, max_src = 0;

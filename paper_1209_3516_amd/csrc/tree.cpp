@@ -94,6 +94,7 @@ int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string
   }
   t.root_half = h;
 
+  alloc_checkpoint();
   std::vector<uint64_t> key(n, 0);
   std::vector<int32_t> idx(n);
   const double base[3] = {t.root_center[0] - h, t.root_center[1] - h, t.root_center[2] - h};
@@ -110,6 +111,7 @@ int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string
     }
     key[i] = k;
   }
+  alloc_checkpoint();
   radix_sort_pairs(key, idx);
   t.perm = idx;
   t.keys = key;
@@ -117,6 +119,7 @@ int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string
   for (int64_t i = 0; i < n; ++i)
     for (int d = 0; d < 3; ++d) t.pos[3 * i + d] = xyz[3 * (int64_t)idx[i] + d];
 
+  alloc_checkpoint();
   // Level by level: the children of the level-L cells, in parent order,
   // form level L+1.  Within a cell the keys are sorted, so the bodies of one
   // octant are a contiguous range found by binary search on the octant digit.
@@ -170,6 +173,7 @@ int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string
 
   // Geometry, deepest level first: a leaf takes the bounding box of its
   // bodies, a parent the union of its children's boxes (min/max are exact).
+  alloc_checkpoint();
   std::vector<double> blo(3 * nc), bhi(3 * nc);
   for (int L = t.max_level; L >= 0; --L) {
 #pragma omp parallel for schedule(dynamic, 64)

@@ -174,3 +174,36 @@ def test_lane_layout_table():
         best = max(((nt * (64 // -(-nt // r))) / (64.0 * r), r) for r in range(1, 9)
                    if -(-nt // r) <= 64)
         assert best[0] >= 0.5 or nt > 32
+
+
+def test_injected_allocation_failures_return_enomem(monkeypatch):
+    x = W.uniform_cube(3000, seed=71)
+    ok = fmm.Tree(x, 8)
+    tree_fail = lists_fail = 0
+    for k in range(1, 8):
+        monkeypatch.setenv("FMM_FAULT_INJECT", "alloc:%d" % k)
+        try:
+            fmm.Tree(x, 8)
+        except fmm.FMMError as e:
+            assert e.code == fmm.FMM_ENOMEM
+            assert b"host memory" in fmm.lib().fmm_last_error()
+            tree_fail += 1
+        try:
+            fmm.Lists(ok, 0.4)
+        except fmm.FMMError as e:
+            assert e.code == fmm.FMM_ENOMEM
+            lists_fail += 1
+    monkeypatch.delenv("FMM_FAULT_INJECT")
+    assert tree_fail == 4 and lists_fail == 3
+    # the library still works afterwards, and gives the same lists
+    a, b = fmm.Lists(ok, 0.4), fmm.Lists(fmm.Tree(x, 8), 0.4)
+    for kind in (fmm.FMM_P2P, fmm.FMM_M2L):
+        np.testing.assert_array_equal(a.csr(kind)[1], b.csr(kind)[1])
+
+
+def test_log_output(capfd, monkeypatch):
+    monkeypatch.setenv("FMM_LOG", "1")
+    t = fmm.Tree(W.uniform_cube(500), 16)
+    fmm.Lists(t, 0.4)
+    err = capfd.readouterr().err
+    assert "[fmm] tree: n=500" in err and "[fmm] lists: theta=0.4" in err
