@@ -1,0 +1,99 @@
+"""Accuracy-driven choice of the opening angle theta (section 3.2, Table 4).
+
+For a given order p the paper searches for the largest theta whose FMM result
+meets a target relative L2 error of the force against a direct sum.  The same
+search here: the FMM runs on the GPU (mixed precision by default), the
+reference is the library's FP64 direct sum on the GPU, the error is taken over
+a set of target bodies, and the search is a coarse scan of theta followed by
+bisection inside the bracketing step.
+
+Errors (R12 of the design notes): e_phi, e_grad, and the paper's force error
+e_F with F_i = -q_i grad_i.
+"""
+import time
+
+import numpy as np
+
+from . import fmm
+
+
+def errors(phi, grad, ref_phi, ref_grad, q_t):
+    f = -q_t[:, None] * grad
+    fr = -q_t[:, None] * ref_grad
+    return dict(e_phi=float(np.linalg.norm(phi - ref_phi) / np.linalg.norm(ref_phi)),
+                e_grad=float(np.linalg.norm(grad - ref_grad) / np.linalg.norm(ref_grad)),
+                e_force=float(np.linalg.norm(f - fr) / np.linalg.norm(fr)))
+
+
+class Problem:
+    """Bodies, charges and the FP64 direct-sum reference at the target bodies."""
+
+    def __init__(self, x, q, targets=None, device="cuda:0"):
+        import torch
+
+        self.x = np.ascontiguousarray(x, dtype=np.float64)
+        self.q = np.ascontiguousarray(q, dtype=np.float64)
+        n = self.x.shape[0]
+        self.targets = np.arange(n, dtype=np.int64) if targets is None else np.asarray(
+            targets, dtype=np.int64)
+        self.device = device
+        ph, g = fmm.direct(torch.tensor(self.x, device=device), torch.tensor(self.q, device=device),
+                           torch.tensor(self.targets, device=device))
+        torch.cuda.synchronize()
+        self.ref_phi = ph.cpu().numpy()
+        self.ref_grad = g.cpu().numpy()
+
+    def run(self, p, theta, ncrit, precision="mixed", tree=None, timed=True):
+        """One FMM at (p, theta): errors and times (host tree/traversal, GPU phases)."""
+        import torch
+
+        t0 = time.perf_counter()
+        if tree is None:
+            tree = fmm.Tree(self.x, ncrit)
+        t1 = time.perf_counter()
+        lists = fmm.Lists(tree, theta)
+        t2 = time.perf_counter()
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        qt = torch.tensor(self.q, dtype=dt, device=self.device)
+        fmm.evaluate(tree, lists, qt, p, precision)  # first call uploads the lists
+        torch.cuda.synchronize()
+        phi, g = fmm.evaluate(tree, lists, qt, p, precision, timing=timed, serial=True)
+        ms = fmm.last_timings(lists) if timed else {}
+        torch.cuda.synchronize()
+        out = errors(phi.double().cpu().numpy()[self.targets],
+                     g.double().cpu().numpy()[self.targets], self.ref_phi, self.ref_grad,
+                     self.q[self.targets])
+        out.update(p=p, theta=theta, ncrit=ncrit, tree_s=t1 - t0, traverse_s=t2 - t1,
+                   phase_ms=ms, stats=lists.stats())
+        return out
+
+
+def largest_theta(problem, p, target, ncrit, metric="e_force", lo=0.02, hi=0.98, step=0.04,
+                  refine=7, precision="mixed"):
+    """Largest theta in [lo, hi] whose error metric is <= target: scan from
+    large theta downwards in `step`, then bisect inside the bracketing step.
+    Returns (theta, run) or (None, None) if even `lo` misses the target."""
+    tree = fmm.Tree(problem.x, ncrit)
+    grid = np.arange(hi, lo - 1e-12, -step)
+    good = None
+    bad = None
+    for th in grid:
+        r = problem.run(p, float(th), ncrit, precision, tree=tree, timed=False)
+        if r[metric] <= target:
+            good = (float(th), r)
+            break
+        bad = float(th)
+    if good is None:
+        return None, None
+    if bad is None:
+        return good
+    a, b = good[0], bad
+    best = good
+    for _ in range(refine):
+        mid = 0.5 * (a + b)
+        r = problem.run(p, mid, ncrit, precision, tree=tree, timed=False)
+        if r[metric] <= target:
+            a, best = mid, (mid, r)
+        else:
+            b = mid
+    return best
