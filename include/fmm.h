@@ -163,6 +163,17 @@ void fmm_tree_free(fmm_tree *t);
  */
 int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out);
 
+/*
+ * The same traversal on the GPU (level-synchronous frontier of cell pairs,
+ * same FP64 MAC without FMA contraction, canonical order by a 64-bit radix
+ * sort): the lists are identical bit for bit to fmm_traverse's.  Uses the
+ * current device and `stream` (hipStream_t or NULL) and synchronises it; the
+ * M2L list stays on the device for fmm_evaluate, and both lists are copied to
+ * the host for fmm_lists_view.  Errors as fmm_traverse, plus FMM_EDEVICE.
+ */
+int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out,
+                     void *stream);
+
 /* CSR view of one list (library-owned host arrays, valid until fmm_lists_free).
  * nrows = number of cells; row_ptr[nrows+1] int64; col[nnz] int32. */
 int fmm_lists_view(const fmm_lists *l, int kind, const int64_t **row_ptr, const int32_t **col,

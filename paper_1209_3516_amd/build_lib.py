@@ -17,7 +17,9 @@ LIB = os.path.join(HERE, "libfmm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["tree.cpp", "traverse.cpp", "plan.cpp", "api.cpp"]
-DEVICE_SOURCES = ["p2p.hip", "far.hip", "misc.hip"]
+DEVICE_SOURCES = ["p2p.hip", "far.hip", "misc.hip", "tree_gpu.hip"]
+# Sources whose FP64 arithmetic must match the host bit for bit (no FMA contraction).
+EXACT_SOURCES = {"tree_gpu.hip"}
 
 HOST_FLAGS = ["-std=c++17", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
               "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
@@ -44,7 +46,8 @@ def build(verbose=False, jobs=8):
         objs.append(obj)
     for src in DEVICE_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        cmd = [os.path.join(ROCM, "bin", "hipcc")] + DEVICE_FLAGS + [
+        extra = ["-ffp-contract=off"] if src in EXACT_SOURCES else []
+        cmd = [os.path.join(ROCM, "bin", "hipcc")] + DEVICE_FLAGS + extra + [
             "-c", os.path.join(CSRC, src), "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)

@@ -61,6 +61,7 @@ struct DevTree {
 struct DevLists {
   int device = -1;
   bool uploaded = false;
+  bool m2l_on_device = false;  // M2L CSR already on the device (GPU traversal)
   fmmlib::P2PPlan plan;
   std::vector<int32_t> m2l_rows_host;
   int64_t *m2l_ptr = nullptr;
@@ -238,8 +239,10 @@ int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
   dv.m2l_rows_host.resize(ld.n_rows);
   for (int64_t a = 0; a < ld.n_rows; ++a) dv.m2l_rows_host[a] = (int32_t)a;
   const auto &pl = dv.plan;
-  if (int rc = dev_upload(&dv.m2l_ptr, ld.m2l_ptr.data(), ld.m2l_ptr.size())) return rc;
-  if (int rc = dev_upload(&dv.m2l_col, ld.m2l_col.data(), ld.m2l_col.size())) return rc;
+  if (!dv.m2l_on_device) {
+    if (int rc = dev_upload(&dv.m2l_ptr, ld.m2l_ptr.data(), ld.m2l_ptr.size())) return rc;
+    if (int rc = dev_upload(&dv.m2l_col, ld.m2l_col.data(), ld.m2l_col.size())) return rc;
+  }
   if (int rc = dev_upload(&dv.m2l_rows, dv.m2l_rows_host.data(), dv.m2l_rows_host.size()))
     return rc;
   if (int rc = dev_upload(&dv.items, pl.items.data(), pl.items.size())) return rc;
@@ -596,6 +599,92 @@ int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **ou
                  (flags & FMM_LEAF_FIRST) ? "leaf-first" : "mac-first",
                  (long long)l->data.p2p_col.size(), (long long)l->data.m2l_col.size(),
                  (long long)l->data.p2p_pairs);
+  *out = l;
+  return FMM_OK;
+}
+
+int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out,
+                     void *stream) {
+  if (!t || !out) {
+    set_error("fmm_traverse_gpu: NULL argument");
+    return FMM_EINVAL;
+  }
+  if (!(theta > 0.0 && theta < 1.0)) {
+    set_error("fmm_traverse_gpu: theta must be in (0, 1)");
+    return FMM_EINVAL;
+  }
+  if (flags & ~(unsigned)FMM_LEAF_FIRST) {
+    set_error("fmm_traverse_gpu: unknown flags");
+    return FMM_EINVAL;
+  }
+  *out = nullptr;
+  fmm_tree *tt = const_cast<fmm_tree *>(t);
+  fmm_lists *l = nullptr;
+  fmmlib::dev::DeviceLists dl;
+  auto free_dl = [&]() {
+    void *ptrs[] = {dl.p2p_ptr, dl.p2p_col, dl.m2l_ptr, dl.m2l_col};
+    for (void *p : ptrs)
+      if (p) (void)hipFree(p);
+  };
+  try {
+    l = new fmm_lists();
+    fmmlib::ListData &ld = l->data;
+    const fmmlib::TreeData &td = t->data;
+    ld.tree_id = td.id;
+    ld.theta = theta;
+    ld.flags = flags;
+    ld.n_rows = td.n_cells();
+    if (td.n_cells() > 0) {
+      if (int rc = ensure_tree_device(tt, false)) {
+        delete l;
+        return rc;
+      }
+      const int rc = fmmlib::dev::dual_traverse_gpu(td.n_cells(), tt->dev.geo, tt->dev.child_begin,
+                                                    tt->dev.n_child, theta,
+                                                    (flags & FMM_LEAF_FIRST) != 0, stream, dl);
+      if (rc != 0) {
+        free_dl();
+        delete l;
+        return hip_fail((hipError_t)rc, "dual_traverse_gpu");
+      }
+    }
+    const int64_t nr = ld.n_rows;
+    ld.p2p_ptr.resize(nr + 1);
+    ld.m2l_ptr.resize(nr + 1);
+    ld.p2p_col.resize(dl.p2p_nnz);
+    ld.m2l_col.resize(dl.m2l_nnz);
+    hipError_t e = hipSuccess;
+    if (nr > 0) {
+      const std::pair<void *, const void *> cp[4] = {{ld.p2p_ptr.data(), dl.p2p_ptr},
+                                                     {ld.m2l_ptr.data(), dl.m2l_ptr},
+                                                     {ld.p2p_col.data(), dl.p2p_col},
+                                                     {ld.m2l_col.data(), dl.m2l_col}};
+      const size_t sz[4] = {(size_t)(nr + 1) * 8, (size_t)(nr + 1) * 8, (size_t)dl.p2p_nnz * 4,
+                            (size_t)dl.m2l_nnz * 4};
+      for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        if (sz[k]) e = hipMemcpy(cp[k].first, cp[k].second, sz[k], hipMemcpyDeviceToHost);
+    } else {
+      ld.p2p_ptr.assign(1, 0);
+      ld.m2l_ptr.assign(1, 0);
+    }
+    if (e != hipSuccess) {
+      free_dl();
+      delete l;
+      return hip_fail(e, "fmm_traverse_gpu: copy to host");
+    }
+    fmmlib::list_statistics(td, ld);
+    // keep the M2L list on the device for the evaluation
+    if (dl.p2p_ptr) (void)hipFree(dl.p2p_ptr);
+    if (dl.p2p_col) (void)hipFree(dl.p2p_col);
+    l->dev.m2l_ptr = dl.m2l_ptr;
+    l->dev.m2l_col = dl.m2l_col;
+    l->dev.m2l_on_device = nr > 0;
+  } catch (const std::bad_alloc &) {
+    free_dl();
+    delete l;
+    set_error("fmm_traverse_gpu: out of host memory");
+    return FMM_ENOMEM;
+  }
   *out = l;
   return FMM_OK;
 }

@@ -87,6 +87,8 @@ constexpr int kP2PChunkSources = 8192;
 
 int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string &err);
 void dual_traverse(const TreeData &t, double theta, bool leaf_first, ListData &l);
+// p2p_pairs and max_row_sources of finished lists.
+void list_statistics(const TreeData &t, ListData &l);
 void build_p2p_plan(const TreeData &t, const ListData &l, P2PPlan &plan);
 
 }  // namespace fmmlib

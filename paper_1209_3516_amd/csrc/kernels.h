@@ -72,6 +72,20 @@ int l2p_combine(int p, bool fp64, int mode, int64_t n, const int32_t *body_leaf,
 int backward_combine(bool fp64, int64_t n, const void *q, const void *w, const void *grad_q,
                      const void *grad_w, const void *hv, void *dx, void *stream);
 
+// Interaction lists on the device (CSR, rows = target cells, sources
+// ascending).  Pointers are hipMalloc'd by dual_traverse_gpu; the caller frees.
+struct DeviceLists {
+  int64_t n_rows = 0, p2p_nnz = 0, m2l_nnz = 0;
+  int64_t *p2p_ptr = nullptr, *m2l_ptr = nullptr;
+  int32_t *p2p_col = nullptr, *m2l_col = nullptr;
+};
+
+// Dual tree traversal on the GPU with the rules of the host traversal.
+// geo: [n_cells] double4 (centre, radius); synchronises `stream`.
+int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_begin,
+                      const int32_t *n_child, double theta, bool leaf_first, void *stream,
+                      DeviceLists &out);
+
 int direct_sum(const double *xyz, const double *q, int64_t n, const int64_t *targets, int64_t m,
                double *phi, double *grad, void *stream);
 

@@ -154,7 +154,10 @@ void dual_traverse(const TreeData &t, double theta, bool leaf_first, ListData &l
   to_csr(bufs, false, l.n_rows, l.p2p_ptr, l.p2p_col);
   alloc_checkpoint();
   to_csr(bufs, true, l.n_rows, l.m2l_ptr, l.m2l_col);
+  list_statistics(t, l);
+}
 
+void list_statistics(const TreeData &t, ListData &l) {
   int64_t pairs = 0, max_src = 0;
   for (int64_t a = 0; a < l.n_rows; ++a) {
     int64_t src = 0;

@@ -58,7 +58,8 @@ class _ListStats(ctypes.Structure):
 EXPORTS = ("fmm_tree_build", "fmm_tree_set_positions", "fmm_tree_view", "fmm_tree_free",
            "fmm_traverse", "fmm_lists_view", "fmm_lists_stats", "fmm_lists_free",
            "fmm_evaluate", "fmm_evaluate_backward", "fmm_direct", "fmm_last_timings",
-           "fmm_last_error", "fmm_num_terms", "fmm_copy_expansions", "fmm_term_exponents")
+           "fmm_last_error", "fmm_num_terms", "fmm_copy_expansions", "fmm_term_exponents",
+           "fmm_traverse_gpu")
 
 _lib = None
 
@@ -81,6 +82,7 @@ def lib():
         "fmm_tree_view": ([vp, ctypes.POINTER(_TreeView)], i32),
         "fmm_tree_free": ([vp], None),
         "fmm_traverse": ([vp, dbl, u32, ctypes.POINTER(vp)], i32),
+        "fmm_traverse_gpu": ([vp, dbl, u32, ctypes.POINTER(vp), vp], i32),
         "fmm_lists_view": ([vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                             ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
         "fmm_lists_stats": ([vp, ctypes.POINTER(_ListStats)], i32),
@@ -191,12 +193,17 @@ class Tree:
 
 
 class Lists:
-    """P2P and M2L interaction lists from the dual tree traversal (host)."""
+    """P2P and M2L interaction lists from the dual tree traversal, on the host
+    or (device=True) on the GPU; both give identical lists."""
 
-    def __init__(self, tree, theta, leaf_first=False):
+    def __init__(self, tree, theta, leaf_first=False, device=False):
         h = ctypes.c_void_p()
         flags = FMM_LEAF_FIRST if leaf_first else FMM_MAC_FIRST
-        _check(lib().fmm_traverse(tree._h, float(theta), flags, ctypes.byref(h)))
+        if device:
+            _check(lib().fmm_traverse_gpu(tree._h, float(theta), flags, ctypes.byref(h),
+                                          _stream()))
+        else:
+            _check(lib().fmm_traverse(tree._h, float(theta), flags, ctypes.byref(h)))
         self._h = h
         self.tree = tree
         self.theta = float(theta)
