@@ -139,6 +139,18 @@ typedef struct fmm_lists_stats_t {
 int fmm_tree_build(const double *xyz, int64_t n, int ncrit, fmm_tree **out);
 
 /*
+ * The same tree built on the GPU (bounding-box reduction, Morton keys with
+ * the same FP64 expression and no FMA contraction, stable radix sort of
+ * (key, index), level-by-level octant split, per-cell bounding box and
+ * radius): identical bit for bit to fmm_tree_build's.
+ *   xyz_dev device, n x 3 row-major FP64 positions in user order.
+ * Uses the current device and `stream` (synchronised).  The tree keeps its
+ * device arrays for the evaluation and a host copy for views and the host
+ * traversal.  FMM_EINVAL for non-finite positions, else as fmm_tree_build.
+ */
+int fmm_tree_build_gpu(const void *xyz_dev, int64_t n, int ncrit, fmm_tree **out, void *stream);
+
+/*
  * Replace the positions (host, n x 3, user order) while keeping the structure
  * (keys, cells, centres, radii) frozen - used for finite-difference checks of
  * the gradient, which differentiate the method with its tree held fixed.

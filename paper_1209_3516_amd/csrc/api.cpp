@@ -520,6 +520,69 @@ int fmm_tree_build(const double *xyz, int64_t n, int ncrit, fmm_tree **out) {
   return FMM_OK;
 }
 
+int fmm_tree_build_gpu(const void *xyz_dev, int64_t n, int ncrit, fmm_tree **out, void *stream) {
+  if (!out || n < 0 || ncrit < 1 || (n > 0 && !xyz_dev)) {
+    set_error("fmm_tree_build_gpu: need out != NULL, n >= 0, ncrit >= 1, xyz != NULL");
+    return FMM_EINVAL;
+  }
+  if (n > (int64_t)INT32_MAX - 1) {
+    set_error("fmm_tree_build_gpu: n must be below 2^31 - 1");
+    return FMM_EINVAL;
+  }
+  *out = nullptr;
+  fmm_tree *t = nullptr;
+  fmmlib::dev::DeviceTree dtree;
+  auto free_dev = [&]() {
+    void *ptrs[] = {dtree.perm, dtree.body_begin, dtree.n_body, dtree.child_begin,
+                    dtree.n_child, dtree.parent, dtree.geo, dtree.pos};
+    for (void *p : ptrs)
+      if (p) (void)hipFree(p);
+  };
+  try {
+    t = new fmm_tree();
+    int dev;
+    if (int rc = current_device(&dev)) {
+      delete t;
+      return rc;
+    }
+    std::string err;
+    const int rc = fmmlib::dev::build_tree_gpu((const double *)xyz_dev, n, ncrit, stream, dtree,
+                                               t->data, err);
+    if (rc != 0) {
+      free_dev();
+      delete t;
+      if (rc == -1) {
+        set_error(err);
+        return FMM_EINVAL;
+      }
+      return hip_fail((hipError_t)rc, "build_tree_gpu");
+    }
+    if (n > 0) {
+      // the device arrays serve the evaluation directly
+      DevTree &dv = t->dev;
+      dv.device = dev;
+      dv.n = n;
+      dv.n_cells = dtree.n_cells;
+      dv.perm = dtree.perm;
+      dv.geo = dtree.geo;
+      dv.body_begin = dtree.body_begin;
+      dv.n_body = dtree.n_body;
+      dv.child_begin = dtree.child_begin;
+      dv.n_child = dtree.n_child;
+      dv.parent = dtree.parent;
+      (void)hipFree(dtree.pos);
+    }
+  } catch (const std::bad_alloc &) {
+    free_dev();
+    delete t;
+    set_error("fmm_tree_build_gpu: out of host memory");
+    return FMM_ENOMEM;
+  }
+  t->data.id = g_next_tree_id++;
+  *out = t;
+  return FMM_OK;
+}
+
 int fmm_tree_set_positions(fmm_tree *t, const double *xyz) {
   if (!t || (t->data.n > 0 && !xyz)) {
     set_error("fmm_tree_set_positions: bad argument");

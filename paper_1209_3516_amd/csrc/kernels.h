@@ -5,6 +5,7 @@
 #pragma once
 
 #include <cstdint>
+#include <string>
 
 #include "fmm_internal.h"
 
@@ -85,6 +86,21 @@ struct DeviceLists {
 int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_begin,
                       const int32_t *n_child, double theta, bool leaf_first, void *stream,
                       DeviceLists &out);
+
+// A tree built on the device: arrays hipMalloc'd by build_tree_gpu (caller
+// frees); geo [n_cells] double4 (centre, radius); pos [n][3] Morton order.
+struct DeviceTree {
+  int64_t n = 0, n_cells = 0;
+  int32_t *perm = nullptr, *body_begin = nullptr, *n_body = nullptr, *child_begin = nullptr,
+          *n_child = nullptr, *parent = nullptr;
+  double *geo = nullptr, *pos = nullptr;
+};
+
+// Tree build on the GPU with the rules of build_tree; fills `t` (host copy)
+// and `out` (device arrays).  xyz: device [n][3] FP64, user order.  Returns 0,
+// a hipError_t, or -1 with `err` set for non-finite positions.
+int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, DeviceTree &out,
+                   TreeData &t, std::string &err);
 
 int direct_sum(const double *xyz, const double *q, int64_t n, const int64_t *targets, int64_t m,
                double *phi, double *grad, void *stream);

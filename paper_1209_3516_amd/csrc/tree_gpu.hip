@@ -14,7 +14,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <algorithm>
 #include <hipcub/hipcub.hpp>
+#include <string>
 #include <vector>
 
 #include "kernels.h"
@@ -178,6 +180,230 @@ int sort_to_csr(uint64_t *keys, int64_t nnz, int64_t n_rows, hipStream_t st, Buf
   return (int)hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Tree build on the GPU (section 3.3; same rules as tree.cpp, same FP64
+// expressions, no FMA contraction):
+//   bounding box -> Morton keys -> stable radix sort of (key, index) ->
+//   level-by-level split of cells with more than ncrit bodies into their
+//   non-empty octants (breadth-first numbering) -> per-cell bounding box
+//   centre and radius.
+// ---------------------------------------------------------------------------
+struct Box {
+  double lo[3], hi[3];
+  int finite, exact;
+};
+
+__global__ void bbox_partial(int64_t n, const double *__restrict__ xyz, Box *__restrict__ out) {
+  __shared__ double slo[3][256], shi[3][256];
+  __shared__ int sf[256], se[256];
+  double lo[3], hi[3];
+  int fin = 1, ex = 1;
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = __builtin_inf();
+    hi[d] = -__builtin_inf();
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    for (int d = 0; d < 3; ++d) {
+      const double v = xyz[3 * i + d];
+      if (!__builtin_isfinite(v)) fin = 0;
+      if ((double)(float)v != v) ex = 0;
+      lo[d] = v < lo[d] ? v : lo[d];
+      hi[d] = v > hi[d] ? v : hi[d];
+    }
+  const int t = threadIdx.x;
+  for (int d = 0; d < 3; ++d) {
+    slo[d][t] = lo[d];
+    shi[d][t] = hi[d];
+  }
+  sf[t] = fin;
+  se[t] = ex;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      for (int d = 0; d < 3; ++d) {
+        slo[d][t] = slo[d][t + h] < slo[d][t] ? slo[d][t + h] : slo[d][t];
+        shi[d][t] = shi[d][t + h] > shi[d][t] ? shi[d][t + h] : shi[d][t];
+      }
+      sf[t] &= sf[t + h];
+      se[t] &= se[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    Box b;
+    for (int d = 0; d < 3; ++d) {
+      b.lo[d] = slo[d][0];
+      b.hi[d] = shi[d][0];
+    }
+    b.finite = sf[0];
+    b.exact = se[0];
+    out[blockIdx.x] = b;
+  }
+}
+
+__device__ __forceinline__ uint64_t dilate3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x001f00000000ffffull;
+  v = (v | (v << 16)) & 0x001f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+__global__ void morton_keys(int64_t n, const double *__restrict__ xyz, double bx, double by,
+                            double bz, double width, int degenerate, uint64_t *__restrict__ key,
+                            int32_t *__restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  idx[i] = (int32_t)i;
+  if (degenerate) {
+    key[i] = 0;
+    return;
+  }
+  const double base[3] = {bx, by, bz};
+  uint64_t k = 0;
+  for (int d = 0; d < 3; ++d) {
+    double s = floor((xyz[3 * i + d] - base[d]) / width * 2097152.0);
+    s = s < 0.0 ? 0.0 : (s > 2097151.0 ? 2097151.0 : s);
+    k |= dilate3((uint64_t)s) << d;
+  }
+  key[i] = k;
+}
+
+__global__ void gather_positions(int64_t n, const double *__restrict__ xyz,
+                                 const int32_t *__restrict__ perm, double *__restrict__ pos) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t u = perm[i];
+  for (int d = 0; d < 3; ++d) pos[3 * i + d] = xyz[3 * u + d];
+}
+
+// Octant boundaries of cell c at level L: bodies [b0, b1) have sorted keys,
+// so each octant digit is a contiguous range, found by binary search.
+__device__ __forceinline__ int64_t digit_bound(const uint64_t *__restrict__ keys, int64_t lo,
+                                               int64_t hi, int shift, int oct) {
+  while (lo < hi) {  // first position whose digit > oct
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int)((keys[mid] >> shift) & 7u) <= oct)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ void count_children(int64_t c0, int64_t c1, int level, int ncrit, int splittable,
+                               const uint64_t *__restrict__ keys,
+                               const int64_t *__restrict__ body_begin,
+                               const int64_t *__restrict__ n_body, int32_t *__restrict__ nch) {
+  const int64_t c = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= c1) return;
+  int count = 0;
+  if (splittable && n_body[c] > ncrit && level < 21) {
+    const int shift = 3 * (20 - level);
+    int64_t prev = body_begin[c];
+    const int64_t end = prev + n_body[c];
+    for (int oct = 0; oct < 8; ++oct) {
+      const int64_t b = digit_bound(keys, prev, end, shift, oct);
+      count += b > prev;
+      prev = b;
+    }
+  }
+  nch[c - c0] = count;
+}
+
+__global__ void write_children(int64_t c0, int64_t c1, int level, const uint64_t *__restrict__ keys,
+                               const int32_t *__restrict__ nch, const int32_t *__restrict__ off,
+                               int64_t next_base, int64_t *__restrict__ body_begin,
+                               int64_t *__restrict__ n_body, int32_t *__restrict__ lev,
+                               int32_t *__restrict__ parent, int32_t *__restrict__ child_begin,
+                               int32_t *__restrict__ n_child) {
+  const int64_t c = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= c1) return;
+  const int k = nch[c - c0];
+  n_child[c] = k;
+  child_begin[c] = k ? (int32_t)(next_base + off[c - c0]) : 0;
+  if (!k) return;
+  const int shift = 3 * (20 - level);
+  int64_t prev = body_begin[c];
+  const int64_t end = prev + n_body[c];
+  int64_t out = next_base + off[c - c0];
+  for (int oct = 0; oct < 8; ++oct) {
+    const int64_t b = digit_bound(keys, prev, end, shift, oct);
+    if (b > prev) {
+      body_begin[out] = prev;
+      n_body[out] = b - prev;
+      lev[out] = level + 1;
+      parent[out] = (int32_t)c;
+      ++out;
+    }
+    prev = b;
+  }
+}
+
+// One 256-thread work-group per cell: tight bounding box of its bodies, its
+// middle as the centre, and the largest centre-to-body distance.
+__global__ __launch_bounds__(256) void cell_geometry(const double *__restrict__ pos,
+                                                     const int64_t *__restrict__ body_begin,
+                                                     const int64_t *__restrict__ n_body,
+                                                     double4 *__restrict__ geo) {
+  __shared__ double red[3][256];
+  __shared__ double X[3];
+  const int64_t c = blockIdx.x;
+  const int64_t b0 = body_begin[c], nb = n_body[c];
+  const int t = threadIdx.x;
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = __builtin_inf();
+    hi[d] = -__builtin_inf();
+  }
+  for (int64_t j = t; j < nb; j += 256)
+    for (int d = 0; d < 3; ++d) {
+      const double v = pos[3 * (b0 + j) + d];
+      lo[d] = v < lo[d] ? v : lo[d];
+      hi[d] = v > hi[d] ? v : hi[d];
+    }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int d = 0; d < 3; ++d) red[d][t] = pass == 0 ? lo[d] : hi[d];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (t < h)
+        for (int d = 0; d < 3; ++d)
+          red[d][t] = pass == 0 ? (red[d][t + h] < red[d][t] ? red[d][t + h] : red[d][t])
+                                : (red[d][t + h] > red[d][t] ? red[d][t + h] : red[d][t]);
+      __syncthreads();
+    }
+    if (t == 0)
+      for (int d = 0; d < 3; ++d) (pass == 0 ? lo : hi)[d] = red[d][0];
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int d = 0; d < 3; ++d) X[d] = 0.5 * (lo[d] + hi[d]);
+  __syncthreads();
+  double rmax = 0.0;
+  for (int64_t j = t; j < nb; j += 256) {
+    const double *p = &pos[3 * (b0 + j)];
+    const double dx = p[0] - X[0], dy = p[1] - X[1], dz = p[2] - X[2];
+    const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+    rmax = r > rmax ? r : rmax;
+  }
+  red[0][t] = rmax;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[0][t] = red[0][t + h] > red[0][t] ? red[0][t + h] : red[0][t];
+    __syncthreads();
+  }
+  if (t == 0) geo[c] = make_double4(X[0], X[1], X[2], red[0][0]);
+}
+
+__global__ void narrow_i64(int64_t n, const int64_t *__restrict__ in, int32_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (int32_t)in[i];
+}
+
 }  // namespace
 
 int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_begin,
@@ -256,6 +482,187 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
                            out.m2l_col))
     return rc;
   TRY(hipStreamSynchronize(st));
+  return 0;
+}
+
+
+int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, DeviceTree &out,
+                   TreeData &t, std::string &err) {
+  const hipStream_t st = S_(stream);
+  out = DeviceTree();
+  t = TreeData();
+  t.n = n;
+  t.ncrit = ncrit;
+  if (n == 0) {
+    t.level_begin.assign(1, 0);
+    return 0;
+  }
+  // bounding box, finiteness, FP32 representability
+  const int nblk = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  Buf boxes;
+  TRY(boxes.reserve(nblk * sizeof(Box), st, false));
+  bbox_partial<<<nblk, 256, 0, st>>>(n, xyz, (Box *)boxes.p);
+  TRY(hipGetLastError());
+  std::vector<Box> hb(nblk);
+  TRY(hipMemcpyAsync(hb.data(), boxes.p, nblk * sizeof(Box), hipMemcpyDeviceToHost, st));
+  TRY(hipStreamSynchronize(st));
+  double lo[3], hi[3];
+  bool finite = true, exact = true;
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = hb[0].lo[d];
+    hi[d] = hb[0].hi[d];
+  }
+  for (const Box &b : hb) {
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = b.lo[d] < lo[d] ? b.lo[d] : lo[d];
+      hi[d] = b.hi[d] > hi[d] ? b.hi[d] : hi[d];
+    }
+    finite = finite && b.finite;
+    exact = exact && b.exact;
+  }
+  if (!finite) {
+    err = "fmm_tree_build_gpu: positions must be finite";
+    return -1;
+  }
+  t.fp32_exact = exact;
+  double h = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    t.root_center[d] = 0.5 * (lo[d] + hi[d]);
+    const double half = 0.5 * (hi[d] - lo[d]);
+    h = half > h ? half : h;
+  }
+  t.root_half = h;
+  // keys, stable sort of (key, index)
+  Buf key, idx, key2, idx2, temp;
+  TRY(key.reserve(n * 8, st, false));
+  TRY(idx.reserve(n * 4, st, false));
+  TRY(key2.reserve(n * 8, st, false));
+  TRY(idx2.reserve(n * 4, st, false));
+  morton_keys<<<blocks_for(n, 256), 256, 0, st>>>(n, xyz, t.root_center[0] - h,
+                                                  t.root_center[1] - h, t.root_center[2] - h,
+                                                  2.0 * h, h == 0.0, (uint64_t *)key.p,
+                                                  (int32_t *)idx.p);
+  TRY(hipGetLastError());
+  hipcub::DoubleBuffer<uint64_t> dk((uint64_t *)key.p, (uint64_t *)key2.p);
+  hipcub::DoubleBuffer<int32_t> dv((int32_t *)idx.p, (int32_t *)idx2.p);
+  size_t tb = 0;
+  TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, dk, dv, (int)n, 0, 63, st));
+  TRY(temp.reserve(tb, st, false));
+  TRY(hipcub::DeviceRadixSort::SortPairs(temp.p, tb, dk, dv, (int)n, 0, 63, st));
+  const uint64_t *skeys = dk.Current();
+  const int32_t *sperm = dv.Current();
+  TRY(hipMalloc((void **)&out.perm, n * 4));
+  TRY(hipMemcpyAsync(out.perm, sperm, n * 4, hipMemcpyDeviceToDevice, st));
+  TRY(hipMalloc((void **)&out.pos, n * 24));
+  gather_positions<<<blocks_for(n, 256), 256, 0, st>>>(n, xyz, out.perm, out.pos);
+  TRY(hipGetLastError());
+  // levels
+  Buf bb, nbd, lv, par, cb, nc, nch, off;
+  size_t cap = 1024;
+  auto grow = [&](size_t want) -> hipError_t {
+    if (want <= cap && bb.p) return hipSuccess;
+    while (cap < want) cap *= 2;
+    hipError_t e;
+    if ((e = bb.reserve(cap * 8, st, true)) != hipSuccess) return e;
+    if ((e = nbd.reserve(cap * 8, st, true)) != hipSuccess) return e;
+    if ((e = lv.reserve(cap * 4, st, true)) != hipSuccess) return e;
+    if ((e = par.reserve(cap * 4, st, true)) != hipSuccess) return e;
+    if ((e = cb.reserve(cap * 4, st, true)) != hipSuccess) return e;
+    return nc.reserve(cap * 4, st, true);
+  };
+  TRY(grow(1));
+  {
+    const int64_t zero = 0;
+    const int32_t izero = 0, mone = -1;
+    TRY(hipMemcpyAsync(bb.p, &zero, 8, hipMemcpyHostToDevice, st));
+    TRY(hipMemcpyAsync(nbd.p, &n, 8, hipMemcpyHostToDevice, st));
+    TRY(hipMemcpyAsync(lv.p, &izero, 4, hipMemcpyHostToDevice, st));
+    TRY(hipMemcpyAsync(par.p, &mone, 4, hipMemcpyHostToDevice, st));
+    TRY(hipStreamSynchronize(st));
+  }
+  t.level_begin.assign(1, 0);
+  int64_t c0 = 0, c1 = 1;
+  int level = 0;
+  while (c0 < c1) {
+    t.level_begin.push_back(c1);
+    const int64_t m = c1 - c0;
+    TRY(nch.reserve(m * 4, st, false));
+    TRY(off.reserve(m * 4, st, false));
+    count_children<<<blocks_for(m, 256), 256, 0, st>>>(c0, c1, level, ncrit, h > 0.0, skeys,
+                                                       (const int64_t *)bb.p,
+                                                       (const int64_t *)nbd.p, (int32_t *)nch.p);
+    TRY(hipGetLastError());
+    size_t tsb = 0;
+    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tsb, (int32_t *)nch.p, (int32_t *)off.p, (int)m,
+                                         st));
+    TRY(temp.reserve(tsb, st, false));
+    TRY(hipcub::DeviceScan::ExclusiveSum(temp.p, tsb, (int32_t *)nch.p, (int32_t *)off.p, (int)m,
+                                         st));
+    int32_t last[2];
+    TRY(hipMemcpyAsync(&last[0], (int32_t *)off.p + m - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&last[1], (int32_t *)nch.p + m - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    const int64_t added = (int64_t)last[0] + last[1];
+    TRY(grow(c1 + added));
+    write_children<<<blocks_for(m, 256), 256, 0, st>>>(
+        c0, c1, level, skeys, (const int32_t *)nch.p, (const int32_t *)off.p, c1,
+        (int64_t *)bb.p, (int64_t *)nbd.p, (int32_t *)lv.p, (int32_t *)par.p, (int32_t *)cb.p,
+        (int32_t *)nc.p);
+    TRY(hipGetLastError());
+    c0 = c1;
+    c1 = c1 + added;
+    if (c0 < c1) ++level;
+  }
+  const int64_t ncells = c1;
+  t.max_level = level;
+  t.level_begin.resize(t.max_level + 2);
+  t.level_begin[t.max_level + 1] = ncells;
+  // geometry
+  TRY(hipMalloc((void **)&out.geo, ncells * 32));
+  cell_geometry<<<(unsigned)ncells, 256, 0, st>>>(out.pos, (const int64_t *)bb.p,
+                                                   (const int64_t *)nbd.p, (double4 *)out.geo);
+  TRY(hipGetLastError());
+  TRY(hipMalloc((void **)&out.body_begin, ncells * 4));
+  TRY(hipMalloc((void **)&out.n_body, ncells * 4));
+  narrow_i64<<<blocks_for(ncells, 256), 256, 0, st>>>(ncells, (const int64_t *)bb.p, out.body_begin);
+  narrow_i64<<<blocks_for(ncells, 256), 256, 0, st>>>(ncells, (const int64_t *)nbd.p, out.n_body);
+  TRY(hipGetLastError());
+  for (int32_t **dst : {&out.child_begin, &out.n_child, &out.parent}) TRY(hipMalloc((void **)dst, ncells * 4));
+  TRY(hipMemcpyAsync(out.child_begin, cb.p, ncells * 4, hipMemcpyDeviceToDevice, st));
+  TRY(hipMemcpyAsync(out.n_child, nc.p, ncells * 4, hipMemcpyDeviceToDevice, st));
+  TRY(hipMemcpyAsync(out.parent, par.p, ncells * 4, hipMemcpyDeviceToDevice, st));
+  // host copy of the tree
+  t.perm.resize(n);
+  t.keys.resize(n);
+  t.pos.resize(3 * n);
+  t.level.resize(ncells);
+  t.parent.resize(ncells);
+  t.child_begin.resize(ncells);
+  t.n_child.resize(ncells);
+  t.body_begin.resize(ncells);
+  t.n_body.resize(ncells);
+  t.center.resize(3 * ncells);
+  t.radius.resize(ncells);
+  std::vector<double> geo(4 * ncells);
+  TRY(hipMemcpyAsync(t.perm.data(), out.perm, n * 4, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(t.keys.data(), skeys, n * 8, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(t.pos.data(), out.pos, n * 24, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(t.level.data(), lv.p, ncells * 4, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(t.parent.data(), par.p, ncells * 4, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(t.child_begin.data(), cb.p, ncells * 4, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(t.n_child.data(), nc.p, ncells * 4, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(t.body_begin.data(), bb.p, ncells * 8, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(t.n_body.data(), nbd.p, ncells * 8, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(geo.data(), out.geo, ncells * 32, hipMemcpyDeviceToHost, st));
+  TRY(hipStreamSynchronize(st));
+  t.n_leaves = 0;
+  for (int64_t c = 0; c < ncells; ++c) {
+    for (int d = 0; d < 3; ++d) t.center[3 * c + d] = geo[4 * c + d];
+    t.radius[c] = geo[4 * c + 3];
+    t.n_leaves += t.n_child[c] == 0;
+  }
+  out.n = n;
+  out.n_cells = ncells;
   return 0;
 }
 

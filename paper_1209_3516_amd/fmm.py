@@ -59,7 +59,7 @@ EXPORTS = ("fmm_tree_build", "fmm_tree_set_positions", "fmm_tree_view", "fmm_tre
            "fmm_traverse", "fmm_lists_view", "fmm_lists_stats", "fmm_lists_free",
            "fmm_evaluate", "fmm_evaluate_backward", "fmm_direct", "fmm_last_timings",
            "fmm_last_error", "fmm_num_terms", "fmm_copy_expansions", "fmm_term_exponents",
-           "fmm_traverse_gpu")
+           "fmm_traverse_gpu", "fmm_tree_build_gpu")
 
 _lib = None
 
@@ -83,6 +83,7 @@ def lib():
         "fmm_tree_free": ([vp], None),
         "fmm_traverse": ([vp, dbl, u32, ctypes.POINTER(vp)], i32),
         "fmm_traverse_gpu": ([vp, dbl, u32, ctypes.POINTER(vp), vp], i32),
+        "fmm_tree_build_gpu": ([vp, i64, i32, ctypes.POINTER(vp), vp], i32),
         "fmm_lists_view": ([vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                             ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
         "fmm_lists_stats": ([vp, ctypes.POINTER(_ListStats)], i32),
@@ -143,6 +144,23 @@ class Tree:
         h = ctypes.c_void_p()
         _check(lib().fmm_tree_build(_np_ptr(xyz), self.n, self.ncrit, ctypes.byref(h)))
         self._h = h
+
+    @classmethod
+    def from_device(cls, xyz, ncrit):
+        """Build the tree on the GPU from a CUDA float64 tensor [n, 3] (user
+        order); identical to Tree(xyz.cpu().numpy(), ncrit)."""
+        _check_tensor(xyz, xyz.shape[0], xyz.dtype, "xyz", 3)
+        import torch
+        if xyz.dtype != torch.float64:
+            raise ValueError("xyz must be float64")
+        self = cls.__new__(cls)
+        self.n = xyz.shape[0]
+        self.ncrit = int(ncrit)
+        h = ctypes.c_void_p()
+        _check(lib().fmm_tree_build_gpu(_t_ptr(xyz), self.n, self.ncrit, ctypes.byref(h),
+                                        _stream()))
+        self._h = h
+        return self
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

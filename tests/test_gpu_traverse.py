@@ -1,6 +1,6 @@
-"""Dual tree traversal on the GPU: lists identical bit for bit to the host
-traversal's (which equal the oracle's, tests/test_lib_host.py), and the
-evaluation with either lists identical bit for bit."""
+"""Tree build and dual tree traversal on the GPU: trees and lists identical bit
+for bit to the host code's (which equal the oracle's, tests/test_lib_host.py),
+and the evaluation with either identical bit for bit."""
 import time
 
 import numpy as np
@@ -66,3 +66,72 @@ def test_gpu_traversal_full_size():
     print("host traversal %.1f ms, GPU traversal %.1f ms" % (1e3 * (t1 - t0), 1e3 * (t2 - t1)))
     for k in (fmm.FMM_P2P, fmm.FMM_M2L):
         np.testing.assert_array_equal(host.csr(k)[1], gpu.csr(k)[1])
+
+
+TREE_KEYS = ("perm", "keys", "level", "parent", "n_child", "body_begin", "n_body", "center",
+             "radius")
+
+
+def _tree_inputs():
+    rng = np.random.default_rng(96)
+    b = W.uniform_cube(2000, seed=97)
+    return {
+        "uniform": W.uniform_cube(100_000, seed=98),
+        "plummer": W.plummer(100_000, seed=99),
+        "dup": np.concatenate([b, b[:700], np.tile([[0.3, 0.3, 0.3]], (200, 1))]),
+        "coincident": np.tile([[0.25, 0.5, 0.75]], (500, 1)),
+        "line": np.stack([np.linspace(0, 1, 3000), np.zeros(3000), np.full(3000, 0.5)], 1),
+        "not-fp32": rng.random((20_000, 3)),
+        "one": np.array([[0.1, 0.2, 0.3]]),
+        "two": np.array([[0.0, 0.0, 0.0], [1.0, 2.0, 3.0]]),
+    }
+
+
+@pytest.mark.parametrize("name", list(_tree_inputs().keys()))
+@pytest.mark.parametrize("ncrit", [1, 16, 64])
+def test_gpu_tree_equals_host_tree(name, ncrit):
+    x = _tree_inputs()[name]
+    host = fmm.Tree(x, ncrit)
+    gpu = fmm.Tree.from_device(torch.tensor(x, dtype=torch.float64, device="cuda:0"), ncrit)
+    hv, gv = host.view(), gpu.view()
+    assert hv["n_cells"] == gv["n_cells"] and hv["max_level"] == gv["max_level"]
+    assert hv["fp32_exact"] == gv["fp32_exact"] and hv["n_leaves"] == gv["n_leaves"]
+    for k in TREE_KEYS:
+        np.testing.assert_array_equal(hv[k], gv[k], err_msg=k)
+    inner = hv["n_child"] > 0
+    np.testing.assert_array_equal(hv["child_begin"][inner], gv["child_begin"][inner])
+    a, b = fmm.Lists(host, 0.45), fmm.Lists(gpu, 0.45, device=True)
+    for k in (fmm.FMM_P2P, fmm.FMM_M2L):
+        np.testing.assert_array_equal(a.csr(k)[1], b.csr(k)[1])
+
+
+def test_gpu_tree_rejects_non_finite():
+    x = W.uniform_cube(1000, seed=100)
+    x[17, 2] = np.inf
+    with pytest.raises(fmm.FMMError) as e:
+        fmm.Tree.from_device(torch.tensor(x, device="cuda:0"), 16)
+    assert e.value.code == fmm.FMM_EINVAL
+
+
+def test_end_to_end_on_gpu_full_size():
+    n = 1_000_000
+    x = W.uniform_cube(n)
+    q = W.charges(n)
+    xt = torch.tensor(x, device="cuda:0")
+    qt = torch.tensor(q, dtype=torch.float32, device="cuda:0")
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tree = fmm.Tree.from_device(xt, 64)
+        t1 = time.perf_counter()
+        lists = fmm.Lists(tree, 0.4, device=True)
+        t2 = time.perf_counter()
+        phi, g = fmm.evaluate(tree, lists, qt, 4)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+    print("GPU tree %.1f ms, GPU lists %.1f ms, first evaluation %.1f ms" % (
+        1e3 * (t1 - t0), 1e3 * (t2 - t1), 1e3 * (t3 - t2)))
+    host = fmm.Tree(x, 64)
+    ref = fmm.evaluate(host, fmm.Lists(host, 0.4), qt, 4)
+    torch.cuda.synchronize()
+    assert torch.equal(ref[0], phi) and torch.equal(ref[1], g)
