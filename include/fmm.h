@@ -122,7 +122,8 @@ typedef struct fmm_lists_stats_t {
   int64_t p2p_entries; /* leaf pairs in the P2P list */
   int64_t m2l_entries; /* cell pairs in the M2L list */
   int64_t p2p_pairs;   /* body-body interactions: sum over entries n_A*n_B, minus n_A for (A,A) */
-  int64_t p2p_work_items; /* GPU work items of the P2P kernel (0 before the first evaluation) */
+  int64_t p2p_work_items; /* GPU work items of the P2P kernel (host-built lists: 0 before
+                             the first evaluation) */
   int64_t p2p_max_row_sources; /* largest number of source bodies of one target leaf */
 } fmm_lists_stats_t;
 
@@ -179,15 +180,21 @@ int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **ou
  * The same traversal on the GPU (level-synchronous frontier of cell pairs,
  * same FP64 MAC without FMA contraction, canonical order by a 64-bit radix
  * sort): the lists are identical bit for bit to fmm_traverse's.  Uses the
- * current device and `stream` (hipStream_t or NULL) and synchronises it; the
- * M2L list stays on the device for fmm_evaluate, and both lists are copied to
- * the host for fmm_lists_view.  Errors as fmm_traverse, plus FMM_EDEVICE.
+ * current device and `stream` (hipStream_t or NULL) and synchronises it.
+ * The lists stay on the device, and the P2P work plan of fmm_evaluate is
+ * built there too (the same plan the host builds from the same lists), so
+ * the first evaluation uploads nothing.  The host copy of the lists is made
+ * by the first fmm_lists_view on the handle (a blocking copy; do not call it
+ * concurrently with other calls on the same handle).  Errors as
+ * fmm_traverse, plus FMM_EDEVICE.
  */
 int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out,
                      void *stream);
 
 /* CSR view of one list (library-owned host arrays, valid until fmm_lists_free).
- * nrows = number of cells; row_ptr[nrows+1] int64; col[nnz] int32. */
+ * nrows = number of cells; row_ptr[nrows+1] int64; col[nnz] int32.  For lists
+ * from fmm_traverse_gpu the first call copies them to the host (FMM_EDEVICE
+ * or FMM_ENOMEM if that fails). */
 int fmm_lists_view(const fmm_lists *l, int kind, const int64_t **row_ptr, const int32_t **col,
                    int64_t *nrows, int64_t *nnz);
 int fmm_lists_stats(const fmm_lists *l, fmm_lists_stats_t *s);

@@ -1,13 +1,16 @@
 // C interface of the GPU FMM library (declared in include/fmm.h).
 //
-// Tree build and traversal run on the host and never touch the GPU.  The
-// first evaluation on a (tree, lists) pair uploads the tree, the lists and
-// the P2P work plan; device scratch is sized per (p, precision).  Every
-// kernel of one evaluation is enqueued on the caller's stream with no host
-// synchronisation in between.
+// fmm_tree_build / fmm_traverse run on the host and never touch the GPU; the
+// first evaluation on such a (tree, lists) pair uploads the tree, the lists
+// and the P2P work plan.  fmm_tree_build_gpu / fmm_traverse_gpu build the
+// same tree, lists and plan on the device and keep them there; the host copy
+// of device-built lists is made on the first fmm_lists_view.  Device scratch
+// is sized per (p, precision).  Every kernel of one evaluation is enqueued on
+// the caller's stream with no host synchronisation in between.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -60,15 +63,12 @@ struct DevTree {
 
 struct DevLists {
   int device = -1;
-  bool uploaded = false;
-  bool m2l_on_device = false;  // M2L CSR already on the device (GPU traversal)
-  fmmlib::P2PPlan plan;
-  std::vector<int32_t> m2l_rows_host;
-  int64_t *m2l_ptr = nullptr;
-  int32_t *m2l_col = nullptr, *m2l_rows = nullptr;
-  fmmlib::P2PItem *items = nullptr;
-  int32_t *run_body = nullptr, *run_prefix = nullptr;
-  int32_t *leaf_cell = nullptr, *leaf_pbase = nullptr, *leaf_nchunk = nullptr, *body_leaf = nullptr;
+  bool uploaded = false;  // lists and P2P plan are on the device
+  bool host_valid = true;  // ListData holds the CSR lists (else only the device does)
+  int64_t *m2l_ptr = nullptr, *p2p_ptr = nullptr;
+  int32_t *m2l_col = nullptr, *p2p_col = nullptr;
+  int64_t p2p_nnz = 0, m2l_nnz = 0;
+  fmmlib::dev::DevicePlan plan;
   // scratch for one (p, precision, top) configuration
   int p = 0, prec = -1;
   int64_t n_top = -1;
@@ -98,8 +98,8 @@ struct DevLists {
   }
   void release() {
     release_scratch();
-    void *ptrs[] = {m2l_ptr, m2l_col, m2l_rows, items, run_body, run_prefix,
-                    leaf_cell, leaf_pbase, leaf_nchunk, body_leaf};
+    plan.release();
+    void *ptrs[] = {m2l_ptr, m2l_col, p2p_ptr, p2p_col};
     for (void *p2 : ptrs)
       if (p2) (void)hipFree(p2);
     if (have_events)
@@ -169,6 +169,10 @@ int current_device(int *dev) {
   return FMM_OK;
 }
 
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 int ensure_tree_device(fmm_tree *t, bool fp64) {
   const fmmlib::TreeData &d = t->data;
   DevTree &dv = t->dev;
@@ -222,6 +226,17 @@ int ensure_tree_device(fmm_tree *t, bool fp64) {
   return FMM_OK;
 }
 
+// The lane-layout table of the P2P plan, indexed by target count.
+fmmlib::dev::PlanLayouts plan_layouts() {
+  fmmlib::dev::PlanLayouts lay{};
+  for (int nt = 1; nt <= 64; ++nt) {
+    int R, L, K;
+    fmmlib::p2p_lane_layout(nt, &R, &L, &K);
+    lay.cfg[nt] = nt | (R << 8) | (L << 16) | (K << 24);
+  }
+  return lay;
+}
+
 int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
   DevLists &dv = l->dev;
   if (dv.uploaded) {
@@ -231,30 +246,61 @@ int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
     }
     return FMM_OK;
   }
+  const auto t0 = std::chrono::steady_clock::now();
   const fmmlib::TreeData &td = t->data;
   const fmmlib::ListData &ld = l->data;
-  fmmlib::build_p2p_plan(td, ld, dv.plan);
-  // M2L runs over every cell: a row without entries writes zeros, so L needs
-  // no separate clearing before M2L.
-  dv.m2l_rows_host.resize(ld.n_rows);
-  for (int64_t a = 0; a < ld.n_rows; ++a) dv.m2l_rows_host[a] = (int32_t)a;
-  const auto &pl = dv.plan;
-  if (!dv.m2l_on_device) {
-    if (int rc = dev_upload(&dv.m2l_ptr, ld.m2l_ptr.data(), ld.m2l_ptr.size())) return rc;
-    if (int rc = dev_upload(&dv.m2l_col, ld.m2l_col.data(), ld.m2l_col.size())) return rc;
-  }
-  if (int rc = dev_upload(&dv.m2l_rows, dv.m2l_rows_host.data(), dv.m2l_rows_host.size()))
+  fmmlib::P2PPlan pl;
+  fmmlib::build_p2p_plan(td, ld, pl);
+  auto &dp = dv.plan;
+  dp.release();
+  if (int rc = dev_upload(&dv.m2l_ptr, ld.m2l_ptr.data(), ld.m2l_ptr.size())) return rc;
+  if (int rc = dev_upload(&dv.m2l_col, ld.m2l_col.data(), ld.m2l_col.size())) return rc;
+  if (int rc = dev_upload(&dp.items, pl.items.data(), pl.items.size())) return rc;
+  if (int rc = dev_upload(&dp.run_body, pl.run_body.data(), pl.run_body.size())) return rc;
+  if (int rc = dev_upload(&dp.run_prefix, pl.run_prefix.data(), pl.run_prefix.size())) return rc;
+  if (int rc = dev_upload(&dp.leaf_cell, pl.leaf_cell.data(), pl.leaf_cell.size())) return rc;
+  if (int rc = dev_upload(&dp.leaf_pbase, pl.leaf_pbase.data(), pl.leaf_pbase.size())) return rc;
+  if (int rc = dev_upload(&dp.leaf_nchunk, pl.leaf_nchunk.data(), pl.leaf_nchunk.size()))
     return rc;
-  if (int rc = dev_upload(&dv.items, pl.items.data(), pl.items.size())) return rc;
-  if (int rc = dev_upload(&dv.run_body, pl.run_body.data(), pl.run_body.size())) return rc;
-  if (int rc = dev_upload(&dv.run_prefix, pl.run_prefix.data(), pl.run_prefix.size())) return rc;
-  if (int rc = dev_upload(&dv.leaf_cell, pl.leaf_cell.data(), pl.leaf_cell.size())) return rc;
-  if (int rc = dev_upload(&dv.leaf_pbase, pl.leaf_pbase.data(), pl.leaf_pbase.size())) return rc;
-  if (int rc = dev_upload(&dv.leaf_nchunk, pl.leaf_nchunk.data(), pl.leaf_nchunk.size()))
-    return rc;
-  if (int rc = dev_upload(&dv.body_leaf, pl.body_leaf.data(), pl.body_leaf.size())) return rc;
+  if (int rc = dev_upload(&dp.body_leaf, pl.body_leaf.data(), pl.body_leaf.size())) return rc;
+  dp.n_items = (int64_t)pl.items.size();
+  dp.n_runs = (int64_t)pl.run_body.size();
+  dp.n_leaves = (int64_t)pl.leaf_cell.size();
+  dp.n_partials = pl.n_partials;
+  dp.max_row_sources = pl.max_row_sources;
+  dp.p2p_pairs = ld.p2p_pairs;
   dv.device = t->dev.device;
   dv.uploaded = true;
+  if (std::getenv("FMM_LOG"))
+    std::fprintf(stderr, "[fmm] host work plan + upload: %.2f ms (%lld items, %lld runs)\n",
+                 ms_since(t0), (long long)dp.n_items, (long long)dp.n_runs);
+  return FMM_OK;
+}
+
+// Host copy of lists that were built on the device.
+int ensure_lists_host(fmm_lists *l) {
+  DevLists &dv = l->dev;
+  if (dv.host_valid) return FMM_OK;
+  fmmlib::ListData &ld = l->data;
+  const int64_t nr = ld.n_rows;
+  try {
+    ld.p2p_ptr.assign(nr + 1, 0);
+    ld.m2l_ptr.assign(nr + 1, 0);
+    ld.p2p_col.resize(dv.p2p_nnz);
+    ld.m2l_col.resize(dv.m2l_nnz);
+  } catch (const std::bad_alloc &) {
+    set_error("fmm_lists_view: out of host memory");
+    return FMM_ENOMEM;
+  }
+  if (nr > 0) {
+    HIP_TRY(hipMemcpy(ld.p2p_ptr.data(), dv.p2p_ptr, (nr + 1) * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ld.m2l_ptr.data(), dv.m2l_ptr, (nr + 1) * 8, hipMemcpyDeviceToHost));
+    if (dv.p2p_nnz)
+      HIP_TRY(hipMemcpy(ld.p2p_col.data(), dv.p2p_col, dv.p2p_nnz * 4, hipMemcpyDeviceToHost));
+    if (dv.m2l_nnz)
+      HIP_TRY(hipMemcpy(ld.m2l_col.data(), dv.m2l_col, dv.m2l_nnz * 4, hipMemcpyDeviceToHost));
+  }
+  dv.host_valid = true;
   return FMM_OK;
 }
 
@@ -397,13 +443,13 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
     HIP_TRY(hipStreamWaitEvent(ns, dv.fork, 0));
   }
   if (int rc = mark(8, ns)) return rc;
-  LAUNCH_TRY(D::p2p(fp64, mode, mask_all, (int64_t)pl.items.size(), dv.items, dv.run_body,
-                    dv.run_prefix, bodies, vec, dv.part_s, dv.part_c, ns));
+  LAUNCH_TRY(D::p2p(fp64, mode, mask_all, pl.n_items, pl.items, pl.run_body, pl.run_prefix,
+                    bodies, vec, dv.part_s, dv.part_c, ns));
   if (int rc = mark(9, ns)) return rc;
   if (overlap) HIP_TRY(hipEventRecord(dv.join, ns));
 
   // Far field on the caller's stream.
-  LAUNCH_TRY(D::p2m(p, fp64, (int64_t)pl.leaf_cell.size(), dv.leaf_cell, dt.body_begin, dt.n_body,
+  LAUNCH_TRY(D::p2m(p, fp64, pl.n_leaves, pl.leaf_cell, dt.body_begin, dt.n_body,
                     geo, bodies, mode == D::kDipoles ? vec : nullptr, dv.M, dv.M64, n_top,
                     stream));
   if (int rc = mark(2, s)) return rc;
@@ -416,14 +462,15 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   }
   if (int rc = mark(3, s)) return rc;
   {
-    const auto &rows = dv.m2l_rows_host;
-    const int64_t split =
-        std::lower_bound(rows.begin(), rows.end(), (int32_t)n_top) - rows.begin();
+    // every cell is an M2L row (one without entries writes zeros); the top
+    // n_top cells accumulate in FP64
+    const int64_t nc = td.n_cells();
+    const int64_t split = std::min(n_top, nc);
     if (split > 0)
-      LAUNCH_TRY(D::m2l(p, fp64, 0, split, dv.m2l_rows, dv.m2l_ptr, dv.m2l_col, geo, dv.M, dv.L,
-                        dv.L64, true, stream));
-    LAUNCH_TRY(D::m2l(p, fp64, split, (int64_t)rows.size(), dv.m2l_rows, dv.m2l_ptr, dv.m2l_col,
-                      geo, dv.M, dv.L, dv.L64, false, stream));
+      LAUNCH_TRY(D::m2l(p, fp64, 0, split, dv.m2l_ptr, dv.m2l_col, geo, dv.M, dv.L, dv.L64, true,
+                        stream));
+    LAUNCH_TRY(D::m2l(p, fp64, split, nc, dv.m2l_ptr, dv.m2l_col, geo, dv.M, dv.L, dv.L64, false,
+                      stream));
   }
   if (o->flags & FMM_EVAL_KEEP_STAGES) {
     HIP_TRY(hipMemcpyAsync(dv.Lstage, dv.L, (size_t)td.n_cells() * S * real,
@@ -446,8 +493,8 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   if (int rc = mark(5, s)) return rc;
   if (overlap) HIP_TRY(hipStreamWaitEvent(s, dv.join, 0));
   if (int rc = mark(6, s)) return rc;
-  LAUNCH_TRY(D::l2p_combine(p, fp64, mode, td.n, dv.body_leaf, dv.leaf_cell, dv.leaf_pbase,
-                            dv.leaf_nchunk, dt.body_begin, dt.n_body, geo, dv.L, bodies, vec,
+  LAUNCH_TRY(D::l2p_combine(p, fp64, mode, td.n, pl.body_leaf, pl.leaf_cell, pl.leaf_pbase,
+                            pl.leaf_nchunk, dt.body_begin, dt.n_body, geo, dv.L, bodies, vec,
                             dv.part_s, dv.part_c, dt.perm, phi, grad, stream));
   if (int rc = mark(7, s)) return rc;
   dv.timed_serial = !overlap;
@@ -711,40 +758,39 @@ int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists 
         return hip_fail((hipError_t)rc, "dual_traverse_gpu");
       }
     }
-    const int64_t nr = ld.n_rows;
-    ld.p2p_ptr.resize(nr + 1);
-    ld.m2l_ptr.resize(nr + 1);
-    ld.p2p_col.resize(dl.p2p_nnz);
-    ld.m2l_col.resize(dl.m2l_nnz);
-    hipError_t e = hipSuccess;
-    if (nr > 0) {
-      const std::pair<void *, const void *> cp[4] = {{ld.p2p_ptr.data(), dl.p2p_ptr},
-                                                     {ld.m2l_ptr.data(), dl.m2l_ptr},
-                                                     {ld.p2p_col.data(), dl.p2p_col},
-                                                     {ld.m2l_col.data(), dl.m2l_col}};
-      const size_t sz[4] = {(size_t)(nr + 1) * 8, (size_t)(nr + 1) * 8, (size_t)dl.p2p_nnz * 4,
-                            (size_t)dl.m2l_nnz * 4};
-      for (int k = 0; k < 4 && e == hipSuccess; ++k)
-        if (sz[k]) e = hipMemcpy(cp[k].first, cp[k].second, sz[k], hipMemcpyDeviceToHost);
+    // The lists stay on the device; the P2P plan is built there too.
+    DevLists &dv = l->dev;
+    dv.p2p_ptr = dl.p2p_ptr;
+    dv.p2p_col = dl.p2p_col;
+    dv.m2l_ptr = dl.m2l_ptr;
+    dv.m2l_col = dl.m2l_col;
+    dv.p2p_nnz = dl.p2p_nnz;
+    dv.m2l_nnz = dl.m2l_nnz;
+    dl = fmmlib::dev::DeviceLists();
+    if (td.n_cells() > 0) {
+      const auto t_plan = std::chrono::steady_clock::now();
+      const int rc = fmmlib::dev::build_p2p_plan_gpu(
+          td.n, td.n_cells(), td.n_leaves, tt->dev.n_child, tt->dev.body_begin, tt->dev.n_body,
+          dv.p2p_ptr, dv.p2p_col, plan_layouts(), stream, dv.plan);
+      if (rc != 0) {
+        fmm_lists_free(l);
+        return hip_fail((hipError_t)rc, "build_p2p_plan_gpu");
+      }
+      if (std::getenv("FMM_LOG"))
+        std::fprintf(stderr, "[fmm] device work plan: %.2f ms (%lld items, %lld runs)\n",
+                     ms_since(t_plan), (long long)dv.plan.n_items, (long long)dv.plan.n_runs);
+      ld.p2p_pairs = dv.plan.p2p_pairs;
+      ld.max_row_sources = dv.plan.max_row_sources;
+      dv.host_valid = false;
+      dv.uploaded = true;
+      dv.device = tt->dev.device;
     } else {
       ld.p2p_ptr.assign(1, 0);
       ld.m2l_ptr.assign(1, 0);
     }
-    if (e != hipSuccess) {
-      free_dl();
-      delete l;
-      return hip_fail(e, "fmm_traverse_gpu: copy to host");
-    }
-    fmmlib::list_statistics(td, ld);
-    // keep the M2L list on the device for the evaluation
-    if (dl.p2p_ptr) (void)hipFree(dl.p2p_ptr);
-    if (dl.p2p_col) (void)hipFree(dl.p2p_col);
-    l->dev.m2l_ptr = dl.m2l_ptr;
-    l->dev.m2l_col = dl.m2l_col;
-    l->dev.m2l_on_device = nr > 0;
   } catch (const std::bad_alloc &) {
     free_dl();
-    delete l;
+    if (l) fmm_lists_free(l);
     set_error("fmm_traverse_gpu: out of host memory");
     return FMM_ENOMEM;
   }
@@ -758,6 +804,7 @@ int fmm_lists_view(const fmm_lists *l, int kind, const int64_t **row_ptr, const 
     set_error("fmm_lists_view: bad argument");
     return FMM_EINVAL;
   }
+  if (int rc = ensure_lists_host(const_cast<fmm_lists *>(l))) return rc;
   const fmmlib::ListData &d = l->data;
   *row_ptr = kind == FMM_P2P ? d.p2p_ptr.data() : d.m2l_ptr.data();
   *col = kind == FMM_P2P ? d.p2p_col.data() : d.m2l_col.data();
@@ -771,10 +818,11 @@ int fmm_lists_stats(const fmm_lists *l, fmm_lists_stats_t *s) {
     set_error("fmm_lists_stats: NULL argument");
     return FMM_EINVAL;
   }
-  s->p2p_entries = (int64_t)l->data.p2p_col.size();
-  s->m2l_entries = (int64_t)l->data.m2l_col.size();
+  const bool host = l->dev.host_valid;
+  s->p2p_entries = host ? (int64_t)l->data.p2p_col.size() : l->dev.p2p_nnz;
+  s->m2l_entries = host ? (int64_t)l->data.m2l_col.size() : l->dev.m2l_nnz;
   s->p2p_pairs = l->data.p2p_pairs;
-  s->p2p_work_items = (int64_t)l->dev.plan.items.size();
+  s->p2p_work_items = l->dev.plan.n_items;
   s->p2p_max_row_sources = l->data.max_row_sources;
   return FMM_OK;
 }

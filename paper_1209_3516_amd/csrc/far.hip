@@ -101,21 +101,21 @@ __global__ __launch_bounds__(64) void m2m_kernel(int64_t c0, int64_t c1, const i
 }
 
 // ----------------------------------------------------------------------------
-// M2L: one 64-lane wave per target cell with M2L entries; lane l takes the
+// M2L: one 64-lane wave per target cell (a cell without entries writes
+// zeros, so L needs no clearing before M2L); lane l takes the
 // entries l, l+64, ... of the row, computes D^m G(X_A - X_B) with the
 // recurrence and contracts it with the source multipole.  The 64 lane
 // partials are summed in LDS in a fixed order.
 // ----------------------------------------------------------------------------
 template <int P, typename Real, typename Acc>
-__global__ __launch_bounds__(64) void m2l_kernel(int64_t r0, const int32_t *__restrict__ rows,
-                                                 const int64_t *__restrict__ ptr,
+__global__ __launch_bounds__(64) void m2l_kernel(int64_t r0, const int64_t *__restrict__ ptr,
                                                  const int32_t *__restrict__ col,
                                                  const double4 *__restrict__ geo,
                                                  const Real *__restrict__ M, Acc *__restrict__ Lout) {
   constexpr int T = nterms(P), S = pad4(T);
   __shared__ Acc red[64 * (T + 1)];
   const int lane = threadIdx.x;
-  const int A = rows[r0 + xcd_remap(blockIdx.x, gridDim.x)];
+  const int A = (int)(r0 + xcd_remap(blockIdx.x, gridDim.x));
   const double4 ga = geo[A];
   Acc acc[T];
   static_for<T>([&](auto I) { acc[decltype(I)::value] = Acc(0); });
@@ -361,7 +361,7 @@ int m2m(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *child_begin,
   });
 }
 
-int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int32_t *rows, const int64_t *ptr,
+int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
         const int32_t *col, const double *geo, const void *M, void *L, double *L64,
         bool acc_fp64, void *stream) {
   if (r1 <= r0) return 0;
@@ -370,13 +370,13 @@ int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int32_t *rows, const int
   return with_p(p, [&](auto PC) {
     constexpr int PP = decltype(PC)::value;
     if (fp64)
-      m2l_kernel<PP, double, double><<<G, 64, 0, S_(stream)>>>(r0, rows, ptr, col, g,
+      m2l_kernel<PP, double, double><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
                                                                (const double *)M, (double *)L);
     else if (acc_fp64)
-      m2l_kernel<PP, float, double><<<G, 64, 0, S_(stream)>>>(r0, rows, ptr, col, g,
+      m2l_kernel<PP, float, double><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
                                                               (const float *)M, L64);
     else
-      m2l_kernel<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, rows, ptr, col, g,
+      m2l_kernel<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
                                                              (const float *)M, (float *)L);
   });
 }

@@ -49,9 +49,9 @@ int m2m(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *child_begin,
         const int32_t *n_child, const double *geo, void *M, double *M64, bool child_fp64,
         bool out_fp64, void *stream);
 
-// Rows [r0, r1) of `rows` (target cells with M2L entries); acc_fp64: the row
-// accumulates in FP64 into L64, else into L (FP32 in mixed mode).
-int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int32_t *rows, const int64_t *ptr,
+// Target cells [r0, r1); acc_fp64: the row accumulates in FP64 into L64, else
+// into L (FP32 in mixed mode).
+int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
         const int32_t *col, const double *geo, const void *M, void *L, double *L64,
         bool acc_fp64, void *stream);
 
@@ -101,6 +101,28 @@ struct DeviceTree {
 // a hipError_t, or -1 with `err` set for non-finite positions.
 int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, DeviceTree &out,
                    TreeData &t, std::string &err);
+
+// P2P work plan on the device (the layout of P2PPlan, see plan.cpp).
+struct PlanLayouts {
+  int32_t cfg[65];  // tgt_cfg bits (n_tgt | R << 8 | L << 16 | K << 24) for n_tgt = 0..64
+};
+struct DevicePlan {
+  P2PItem *items = nullptr;
+  int32_t *run_body = nullptr, *run_prefix = nullptr;
+  int32_t *leaf_cell = nullptr, *leaf_pbase = nullptr, *leaf_nchunk = nullptr,
+          *body_leaf = nullptr;
+  int64_t n_items = 0, n_runs = 0, n_leaves = 0, n_partials = 0;
+  int64_t max_row_sources = 0, p2p_pairs = 0;
+  void release();
+};
+
+// Build the P2P work plan from device CSR P2P lists and the device tree
+// arrays; the result is the plan build_p2p_plan makes, entry for entry.
+// Synchronises `stream`.  Returns 0 or a hipError_t (on error `out` is empty).
+int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32_t *n_child,
+                       const int32_t *body_begin, const int32_t *n_body, const int64_t *p2p_ptr,
+                       const int32_t *p2p_col, const PlanLayouts &layouts, void *stream,
+                       DevicePlan &out);
 
 int direct_sum(const double *xyz, const double *q, int64_t n, const int64_t *targets, int64_t m,
                double *phi, double *grad, void *stream);

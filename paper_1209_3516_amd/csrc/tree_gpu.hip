@@ -15,6 +15,9 @@
 
 #include <cstdint>
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <hipcub/hipcub.hpp>
 #include <string>
 #include <vector>
@@ -410,6 +413,10 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
                       const int32_t *n_child, double theta, bool leaf_first, void *stream,
                       DeviceLists &out) {
   const hipStream_t st = S_(stream);
+  const bool log = std::getenv("FMM_LOG") != nullptr;
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  const auto t_start = now();
+  int n_levels = 0;
   const double theta2 = theta * theta;
   const double4 *g = (const double4 *)geo;
   out = DeviceLists();
@@ -468,7 +475,9 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
     n_m2l += add_m2l;
     nf = n_next;
     cur = 1 - cur;
+    ++n_levels;
   }
+  const auto t_front = now();
   TRY(hipMalloc((void **)&out.p2p_ptr, (n_cells + 1) * sizeof(int64_t)));
   TRY(hipMalloc((void **)&out.m2l_ptr, (n_cells + 1) * sizeof(int64_t)));
   TRY(hipMalloc((void **)&out.p2p_col, (n_p2p > 0 ? n_p2p : 1) * sizeof(int32_t)));
@@ -482,6 +491,12 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
                            out.m2l_col))
     return rc;
   TRY(hipStreamSynchronize(st));
+  if (log) {
+    const auto t_end = now();
+    std::fprintf(stderr, "[fmm] gpu traversal: %d steps %.2f ms, sort+csr %.2f ms\n", n_levels,
+                 std::chrono::duration<double, std::milli>(t_front - t_start).count(),
+                 std::chrono::duration<double, std::milli>(t_end - t_front).count());
+  }
   return 0;
 }
 

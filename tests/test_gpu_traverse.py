@@ -44,14 +44,37 @@ def test_gpu_lists_equal_host_lists(kind, ncrit, theta, leaf_first):
     assert host.stats()["p2p_pairs"] == gpu.stats()["p2p_pairs"]
 
 
-def test_evaluation_with_gpu_lists_is_identical():
-    x = W.uniform_cube(200_000, seed=94)
-    q = torch.tensor(W.charges(200_000, seed=95), dtype=torch.float32, device="cuda:0")
-    t = fmm.Tree(x, 64)
-    a = fmm.evaluate(t, fmm.Lists(t, 0.4), q, 4)
-    b = fmm.evaluate(t, fmm.Lists(t, 0.4, device=True), q, 4)
+@pytest.mark.parametrize("kind,n,ncrit,theta,leaf_first", [
+    ("uniform", 200_000, 64, 0.4, False),
+    # small theta: rows of more than 8192 sources and 256 runs are chunked
+    ("uniform", 100_000, 64, 0.15, False),
+    ("plummer", 100_000, 16, 0.5, True),
+    ("dup", 4300, 8, 0.6, False),
+    ("one", 1, 8, 0.5, False),
+])
+def test_evaluation_with_gpu_lists_is_identical(kind, n, ncrit, theta, leaf_first):
+    """The device-built P2P work plan is the host plan: same statistics, and
+    the same evaluation bit for bit (chunking fixes the summation order)."""
+    x = {"uniform": lambda: W.uniform_cube(n, seed=94), "plummer": lambda: W.plummer(n, seed=94),
+         "dup": lambda: _points("dup"), "one": lambda: _points("one")}[kind]()
+    m = x.shape[0]
+    q = torch.tensor(W.charges(m, seed=95), dtype=torch.float32, device="cuda:0")
+    t = fmm.Tree(x, ncrit)
+    host = fmm.Lists(t, theta, leaf_first=leaf_first)
+    gpu = fmm.Lists(t, theta, leaf_first=leaf_first, device=True)
+    a = fmm.evaluate(t, host, q, 4)
+    b = fmm.evaluate(t, gpu, q, 4)
     torch.cuda.synchronize()
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    hs, gs = host.stats(), gpu.stats()
+    assert hs == gs, (hs, gs)
+    if theta < 0.2:
+        assert gs["p2p_max_row_sources"] > 8192
+        assert gs["p2p_work_items"] > t.view()["n_leaves"]
+    # the host copy of device lists is made on demand and matches
+    for k in (fmm.FMM_P2P, fmm.FMM_M2L):
+        np.testing.assert_array_equal(host.csr(k)[1], gpu.csr(k)[1])
+    assert gpu.stats() == gs
 
 
 def test_gpu_traversal_full_size():
