@@ -53,8 +53,15 @@ struct DevTree {
   double *geo = nullptr;  // double4[n_cells]: centre, radius
   int32_t *body_begin = nullptr, *n_body = nullptr, *child_begin = nullptr, *n_child = nullptr,
           *parent = nullptr;
+  // trees built on the device: Morton-ordered FP64 positions and keys stay
+  // there, and the host copies of perm, keys and positions are made on demand
+  double *pos = nullptr;
+  uint64_t *keys = nullptr;
+  uint64_t pos_dev_version = ~0ull;  // tree positions version that `pos` holds
+  bool host_bodies = true;
   void release() {
-    void *ptrs[] = {b32, b64, perm, geo, body_begin, n_body, child_begin, n_child, parent};
+    void *ptrs[] = {b32, b64, perm, geo, body_begin, n_body, child_begin, n_child, parent, pos,
+                    keys};
     for (void *p : ptrs)
       if (p) (void)hipFree(p);
     *this = DevTree();
@@ -173,8 +180,29 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-int ensure_tree_device(fmm_tree *t, bool fp64) {
-  const fmmlib::TreeData &d = t->data;
+// Host copies of the per-body arrays of a tree built on the device.
+int ensure_tree_host_bodies(fmm_tree *t) {
+  DevTree &dv = t->dev;
+  if (dv.host_bodies) return FMM_OK;
+  fmmlib::TreeData &d = t->data;
+  const int64_t n = d.n;
+  try {
+    d.perm.resize(n);
+    d.keys.resize(n);
+    d.pos.resize(3 * n);
+  } catch (const std::bad_alloc &) {
+    set_error("out of host memory");
+    return FMM_ENOMEM;
+  }
+  HIP_TRY(hipMemcpy(d.perm.data(), dv.perm, n * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(d.keys.data(), dv.keys, n * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(d.pos.data(), dv.pos, n * 24, hipMemcpyDeviceToHost));
+  dv.host_bodies = true;
+  return FMM_OK;
+}
+
+int ensure_tree_device(fmm_tree *t, bool fp64, void *stream) {
+  fmmlib::TreeData &d = t->data;
   DevTree &dv = t->dev;
   int dev;
   if (int rc = current_device(&dev)) return rc;
@@ -203,6 +231,19 @@ int ensure_tree_device(fmm_tree *t, bool fp64) {
     if (int rc = dev_upload(&dv.n_child, d.n_child.data(), nc)) return rc;
     if (int rc = dev_upload(&dv.parent, d.parent.data(), nc)) return rc;
   }
+  const bool dev_pos = dv.pos && dv.pos_dev_version == d.pos_version;
+  if (dev_pos && ((fp64 && dv.pos_version_64 != d.pos_version) ||
+                  (!fp64 && dv.pos_version_32 != d.pos_version))) {
+    // pack from the device positions
+    void **dst = fp64 ? &dv.b64 : &dv.b32;
+    if (!*dst) HIP_TRY(hipMalloc(dst, std::max<int64_t>(1, d.n) * (fp64 ? 32 : 16)));
+    HIP_TRY((hipError_t)fmmlib::dev::pack_positions(fp64, d.n, dv.pos, *dst, stream));
+    HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+    (fp64 ? dv.pos_version_64 : dv.pos_version_32) = d.pos_version;
+  }
+  if ((fp64 && dv.pos_version_64 != d.pos_version) ||
+      (!fp64 && dv.pos_version_32 != d.pos_version))
+    if (int rc = ensure_tree_host_bodies(t)) return rc;
   if (fp64 && dv.pos_version_64 != d.pos_version) {
     std::vector<double> b(4 * d.n);
     for (int64_t i = 0; i < d.n; ++i) {
@@ -389,7 +430,7 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   namespace D = fmmlib::dev;
   const fmmlib::TreeData &td = t->data;
   const bool fp64 = o->precision == FMM_FP64;
-  if (int rc = ensure_tree_device(t, fp64)) return rc;
+  if (int rc = ensure_tree_device(t, fp64, stream)) return rc;
   if (int rc = ensure_lists_device(t, l)) return rc;
   if (int rc = ensure_scratch(t, l, o)) return rc;
   DevLists &dv = l->dev;
@@ -581,7 +622,7 @@ int fmm_tree_build_gpu(const void *xyz_dev, int64_t n, int ncrit, fmm_tree **out
   fmmlib::dev::DeviceTree dtree;
   auto free_dev = [&]() {
     void *ptrs[] = {dtree.perm, dtree.body_begin, dtree.n_body, dtree.child_begin,
-                    dtree.n_child, dtree.parent, dtree.geo, dtree.pos};
+                    dtree.n_child, dtree.parent, dtree.geo, dtree.pos, dtree.keys};
     for (void *p : ptrs)
       if (p) (void)hipFree(p);
   };
@@ -617,7 +658,16 @@ int fmm_tree_build_gpu(const void *xyz_dev, int64_t n, int ncrit, fmm_tree **out
       dv.child_begin = dtree.child_begin;
       dv.n_child = dtree.n_child;
       dv.parent = dtree.parent;
-      (void)hipFree(dtree.pos);
+      dv.pos = dtree.pos;
+      dv.keys = dtree.keys;
+      dv.pos_dev_version = t->data.pos_version;
+      dv.host_bodies = false;
+      dtree = fmmlib::dev::DeviceTree();
+      // FP32 bodies for the evaluation, packed on the device
+      if (int rc2 = ensure_tree_device(t, false, stream)) {
+        fmm_tree_free(t);
+        return rc2;
+      }
     }
   } catch (const std::bad_alloc &) {
     free_dev();
@@ -641,6 +691,7 @@ int fmm_tree_set_positions(fmm_tree *t, const double *xyz) {
       set_error("fmm_tree_set_positions: positions must be finite");
       return FMM_EINVAL;
     }
+  if (int rc = ensure_tree_host_bodies(t)) return rc;
   for (int64_t i = 0; i < d.n; ++i)
     for (int k = 0; k < 3; ++k) d.pos[3 * i + k] = xyz[3 * (int64_t)d.perm[i] + k];
   // Moved bodies may now coincide with bodies of other leaves: from here on
@@ -655,6 +706,7 @@ int fmm_tree_view(const fmm_tree *t, fmm_tree_view_t *v) {
     set_error("fmm_tree_view: NULL argument");
     return FMM_EINVAL;
   }
+  if (int rc = ensure_tree_host_bodies(const_cast<fmm_tree *>(t))) return rc;
   const fmmlib::TreeData &d = t->data;
   v->n = d.n;
   v->n_cells = d.n_cells();
@@ -728,6 +780,7 @@ int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists 
     return FMM_EINVAL;
   }
   *out = nullptr;
+  const auto t_call = std::chrono::steady_clock::now();
   fmm_tree *tt = const_cast<fmm_tree *>(t);
   fmm_lists *l = nullptr;
   fmmlib::dev::DeviceLists dl;
@@ -745,7 +798,7 @@ int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists 
     ld.flags = flags;
     ld.n_rows = td.n_cells();
     if (td.n_cells() > 0) {
-      if (int rc = ensure_tree_device(tt, false)) {
+      if (int rc = ensure_tree_device(tt, false, stream)) {
         delete l;
         return rc;
       }
@@ -794,6 +847,8 @@ int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists 
     set_error("fmm_traverse_gpu: out of host memory");
     return FMM_ENOMEM;
   }
+  if (std::getenv("FMM_LOG"))
+    std::fprintf(stderr, "[fmm] fmm_traverse_gpu: %.2f ms in all\n", ms_since(t_call));
   *out = l;
   return FMM_OK;
 }
@@ -871,7 +926,7 @@ int fmm_evaluate_backward(const fmm_tree *t, const fmm_lists *l, const fmm_eval_
   namespace D = fmmlib::dev;
   try {
     const bool fp64 = o->precision == FMM_FP64;
-    if (int rc = ensure_tree_device(tt, fp64)) return rc;
+    if (int rc = ensure_tree_device(tt, fp64, stream)) return rc;
     if (int rc = ensure_lists_device(tt, ll)) return rc;
     if (int rc = ensure_scratch(tt, ll, o)) return rc;
     DevLists &dv = ll->dev;

@@ -94,13 +94,21 @@ struct DeviceTree {
   int32_t *perm = nullptr, *body_begin = nullptr, *n_body = nullptr, *child_begin = nullptr,
           *n_child = nullptr, *parent = nullptr;
   double *geo = nullptr, *pos = nullptr;
+  uint64_t *keys = nullptr;
 };
 
-// Tree build on the GPU with the rules of build_tree; fills `t` (host copy)
-// and `out` (device arrays).  xyz: device [n][3] FP64, user order.  Returns 0,
+// Tree build on the GPU with the rules of build_tree; fills `t` (host copy of
+// the cell arrays; perm, keys and pos are left empty) and `out` (device
+// arrays, including the Morton-ordered positions and keys).  xyz: device [n][3] FP64, user order.  Returns 0,
 // a hipError_t, or -1 with `err` set for non-finite positions.
 int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, DeviceTree &out,
                    TreeData &t, std::string &err);
+
+// Scratch of the tree build, traversal and plan builder comes from the
+// device's default stream-ordered pool, which keeps up to this many freed
+// bytes for reuse instead of returning them to the driver.
+constexpr uint64_t kPoolKeepBytes = 4ull << 30;
+int keep_pool_memory();
 
 // P2P work plan on the device (the layout of P2PPlan, see plan.cpp).
 struct PlanLayouts {
@@ -123,6 +131,10 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
                        const int32_t *body_begin, const int32_t *n_body, const int64_t *p2p_ptr,
                        const int32_t *p2p_col, const PlanLayouts &layouts, void *stream,
                        DevicePlan &out);
+
+// pos: device [n][3] FP64 (Morton order) -> out: device [n] double4 (fp64)
+// or float4 (rounded to nearest), (x, y, z, 0).
+int pack_positions(bool fp64, int64_t n, const double *pos, void *out, void *stream);
 
 int direct_sum(const double *xyz, const double *q, int64_t n, const int64_t *targets, int64_t m,
                double *phi, double *grad, void *stream);

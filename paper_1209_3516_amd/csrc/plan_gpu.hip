@@ -175,21 +175,29 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
           *nparts = nullptr, *run_off = nullptr, *item_off = nullptr;
   unsigned long long *totals = nullptr;
   void *scan_tmp = nullptr;
-  auto release = [&]() {
+  // temporaries from the stream-ordered pool, freed in stream order
+  auto free_temps = [&]() {
     void *ps[] = {leaf_flag, leaf_of, nruns, nitems, nparts, run_off, item_off, totals, scan_tmp};
     for (void *p : ps)
-      if (p) (void)hipFree(p);
+      if (p) (void)hipFreeAsync(p, st);
+    leaf_flag = leaf_of = nruns = nitems = nparts = run_off = item_off = nullptr;
+    totals = nullptr;
+    scan_tmp = nullptr;
+  };
+  auto release = [&]() {
+    free_temps();
     out.release();
   };
+  if (int rc = keep_pool_memory()) return rc;
   const size_t nl = (size_t)n_leaves, nc = (size_t)n_cells;
-  PTRY(hipMalloc(&leaf_flag, nc * 4));
-  PTRY(hipMalloc(&leaf_of, nc * 4));
-  PTRY(hipMalloc(&nruns, nl * 4));
-  PTRY(hipMalloc(&nitems, nl * 4));
-  PTRY(hipMalloc(&nparts, nl * 4));
-  PTRY(hipMalloc(&run_off, nl * 4));
-  PTRY(hipMalloc(&item_off, nl * 4));
-  PTRY(hipMalloc(&totals, 8 * sizeof(unsigned long long)));
+  PTRY(hipMallocAsync((void **)&leaf_flag, nc * 4, st));
+  PTRY(hipMallocAsync((void **)&leaf_of, nc * 4, st));
+  PTRY(hipMallocAsync((void **)&nruns, nl * 4, st));
+  PTRY(hipMallocAsync((void **)&nitems, nl * 4, st));
+  PTRY(hipMallocAsync((void **)&nparts, nl * 4, st));
+  PTRY(hipMallocAsync((void **)&run_off, nl * 4, st));
+  PTRY(hipMallocAsync((void **)&item_off, nl * 4, st));
+  PTRY(hipMallocAsync((void **)&totals, 8 * sizeof(unsigned long long), st));
   PTRY(hipMalloc(&out.leaf_cell, nl * 4));
   PTRY(hipMalloc(&out.leaf_pbase, nl * 4));
   PTRY(hipMalloc(&out.leaf_nchunk, nl * 4));
@@ -199,7 +207,7 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
   PTRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, leaf_flag, leaf_of, (int)nc, st));
   PTRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, nruns, run_off, (int)nl, st));
   tb = tb > tb2 ? tb : tb2;
-  PTRY(hipMalloc(&scan_tmp, tb > 0 ? tb : 1));
+  PTRY(hipMallocAsync(&scan_tmp, tb > 0 ? tb : 1, st));
 
   const unsigned bc = (unsigned)((nc + 255) / 256), bl = (unsigned)((nl + 255) / 256);
   leaf_flags<<<bc, 256, 0, st>>>((int64_t)nc, n_child, leaf_flag);
@@ -241,12 +249,8 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
                                  run_off, item_off, out.leaf_pbase, out.leaf_nchunk, layouts,
                                  out.items, out.run_body, out.run_prefix, out.body_leaf);
   PTRY(hipGetLastError());
+  free_temps();
   PTRY(hipStreamSynchronize(st));
-  {
-    void *ps[] = {leaf_flag, leaf_of, nruns, nitems, nparts, run_off, item_off, totals, scan_tmp};
-    for (void *p : ps)
-      if (p) (void)hipFree(p);
-  }
   return 0;
 }
 

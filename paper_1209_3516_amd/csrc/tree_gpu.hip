@@ -127,35 +127,36 @@ __global__ void csr_cols(int64_t nnz, const uint64_t *__restrict__ keys, int32_t
   if (i < nnz) col[i] = (int32_t)(keys[i] & 0xffffffffull);
 }
 
-// Growable device buffer.
+// Growable scratch buffer from the device's stream-ordered memory pool:
+// hipFreeAsync hands the memory back in stream order, without a device
+// synchronisation, and later builds and traversals reuse it from the pool.
 struct Buf {
   void *p = nullptr;
   size_t bytes = 0;
-  hipError_t reserve(size_t want, hipStream_t st, bool keep) {
+  hipStream_t st = nullptr;
+  hipError_t reserve(size_t want, hipStream_t s, bool keep) {
     if (want <= bytes) return hipSuccess;
     size_t nb = bytes ? bytes : 1024;
     while (nb < want) nb *= 2;
     void *np = nullptr;
-    hipError_t e = hipMalloc(&np, nb);
+    hipError_t e = hipMallocAsync(&np, nb, s);
     if (e != hipSuccess) return e;
     if (keep && p) {
-      e = hipMemcpyAsync(np, p, bytes, hipMemcpyDeviceToDevice, st);
-      if (e != hipSuccess) return e;
-      e = hipStreamSynchronize(st);
-      if (e != hipSuccess) return e;
+      e = hipMemcpyAsync(np, p, bytes, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) {
+        (void)hipFreeAsync(np, s);
+        return e;
+      }
     }
-    if (p) {
-      // earlier kernels on the stream may still read the old buffer
-      e = hipStreamSynchronize(st);
-      if (e != hipSuccess) return e;
-      (void)hipFree(p);
-    }
+    // stream order: the kernels that still read the old buffer come first
+    if (p) (void)hipFreeAsync(p, st);
     p = np;
     bytes = nb;
+    st = s;
     return hipSuccess;
   }
   ~Buf() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, st);
   }
 };
 
@@ -164,6 +165,21 @@ struct Buf {
     hipError_t e_ = (x);                   \
     if (e_ != hipSuccess) return (int)e_;  \
   } while (0)
+
+}  // namespace
+
+int keep_pool_memory() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  hipMemPool_t pool;
+  e = hipDeviceGetDefaultMemPool(&pool, dev);
+  if (e != hipSuccess) return (int)e;
+  uint64_t keep = kPoolKeepBytes;
+  return (int)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+}
+
+namespace {
 
 int sort_to_csr(uint64_t *keys, int64_t nnz, int64_t n_rows, hipStream_t st, Buf &alt,
                 Buf &temp, int64_t *row_ptr_dev, int32_t *col_dev) {
@@ -282,6 +298,19 @@ __global__ void gather_positions(int64_t n, const double *__restrict__ xyz,
   if (i >= n) return;
   const int64_t u = perm[i];
   for (int d = 0; d < 3; ++d) pos[3 * i + d] = xyz[3 * u + d];
+}
+
+// Morton-ordered FP64 positions -> (x, y, z, 0) bodies; FP32 rounds to
+// nearest, as the host packing does.
+__global__ void pack_f32(int64_t n, const double *__restrict__ pos, float4 *__restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  b[i] = make_float4((float)pos[3 * i], (float)pos[3 * i + 1], (float)pos[3 * i + 2], 0.0f);
+}
+__global__ void pack_f64(int64_t n, const double *__restrict__ pos, double4 *__restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  b[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 0.0);
 }
 
 // Octant boundaries of cell c at level L: bodies [b0, b1) have sorted keys,
@@ -412,6 +441,7 @@ __global__ void narrow_i64(int64_t n, const int64_t *__restrict__ in, int32_t *_
 int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_begin,
                       const int32_t *n_child, double theta, bool leaf_first, void *stream,
                       DeviceLists &out) {
+  if (int rc = keep_pool_memory()) return rc;
   const hipStream_t st = S_(stream);
   const bool log = std::getenv("FMM_LOG") != nullptr;
   auto now = [] { return std::chrono::steady_clock::now(); };
@@ -501,8 +531,18 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
 }
 
 
+int pack_positions(bool fp64, int64_t n, const double *pos, void *out, void *stream) {
+  if (n <= 0) return 0;
+  if (fp64)
+    pack_f64<<<blocks_for(n, 256), 256, 0, S_(stream)>>>(n, pos, (double4 *)out);
+  else
+    pack_f32<<<blocks_for(n, 256), 256, 0, S_(stream)>>>(n, pos, (float4 *)out);
+  return (int)hipGetLastError();
+}
+
 int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, DeviceTree &out,
                    TreeData &t, std::string &err) {
+  if (int rc = keep_pool_memory()) return rc;
   const hipStream_t st = S_(stream);
   out = DeviceTree();
   t = TreeData();
@@ -646,10 +686,9 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
   TRY(hipMemcpyAsync(out.child_begin, cb.p, ncells * 4, hipMemcpyDeviceToDevice, st));
   TRY(hipMemcpyAsync(out.n_child, nc.p, ncells * 4, hipMemcpyDeviceToDevice, st));
   TRY(hipMemcpyAsync(out.parent, par.p, ncells * 4, hipMemcpyDeviceToDevice, st));
-  // host copy of the tree
-  t.perm.resize(n);
-  t.keys.resize(n);
-  t.pos.resize(3 * n);
+  TRY(hipMalloc((void **)&out.keys, n * 8));
+  TRY(hipMemcpyAsync(out.keys, skeys, n * 8, hipMemcpyDeviceToDevice, st));
+  // host copy of the cell arrays (the per-body arrays stay on the device)
   t.level.resize(ncells);
   t.parent.resize(ncells);
   t.child_begin.resize(ncells);
@@ -659,9 +698,6 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
   t.center.resize(3 * ncells);
   t.radius.resize(ncells);
   std::vector<double> geo(4 * ncells);
-  TRY(hipMemcpyAsync(t.perm.data(), out.perm, n * 4, hipMemcpyDeviceToHost, st));
-  TRY(hipMemcpyAsync(t.keys.data(), skeys, n * 8, hipMemcpyDeviceToHost, st));
-  TRY(hipMemcpyAsync(t.pos.data(), out.pos, n * 24, hipMemcpyDeviceToHost, st));
   TRY(hipMemcpyAsync(t.level.data(), lv.p, ncells * 4, hipMemcpyDeviceToHost, st));
   TRY(hipMemcpyAsync(t.parent.data(), par.p, ncells * 4, hipMemcpyDeviceToHost, st));
   TRY(hipMemcpyAsync(t.child_begin.data(), cb.p, ncells * 4, hipMemcpyDeviceToHost, st));

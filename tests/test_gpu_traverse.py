@@ -128,6 +128,31 @@ def test_gpu_tree_equals_host_tree(name, ncrit):
         np.testing.assert_array_equal(a.csr(k)[1], b.csr(k)[1])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gpu_tree_evaluation_and_set_positions(precision):
+    """A device-built tree evaluates exactly as the host-built one, in both
+    precisions (bodies packed on the device), and after set_positions
+    (host copies of the per-body arrays fetched on demand)."""
+    x = W.uniform_cube(30_000, seed=101)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    q = torch.tensor(W.charges(30_000, seed=102), dtype=dt, device="cuda:0")
+    host = fmm.Tree(x, 32)
+    gpu = fmm.Tree.from_device(torch.tensor(x, device="cuda:0"), 32)
+    lh, lg = fmm.Lists(host, 0.5), fmm.Lists(gpu, 0.5, device=True)
+    a = fmm.evaluate(host, lh, q, 4, precision)
+    b = fmm.evaluate(gpu, lg, q, 4, precision)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    y = x + 1e-3 * W.uniform_cube(30_000, seed=103)
+    host.set_positions(y)
+    gpu.set_positions(y)
+    a = fmm.evaluate(host, lh, q, 4, precision)
+    b = fmm.evaluate(gpu, lg, q, 4, precision)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    np.testing.assert_array_equal(host.view()["perm"], gpu.view()["perm"])
+
+
 def test_gpu_tree_rejects_non_finite():
     x = W.uniform_cube(1000, seed=100)
     x[17, 2] = np.inf
