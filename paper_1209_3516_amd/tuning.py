@@ -43,15 +43,18 @@ class Problem:
         self.ref_phi = ph.cpu().numpy()
         self.ref_grad = g.cpu().numpy()
 
-    def run(self, p, theta, ncrit, precision="mixed", tree=None, timed=True):
-        """One FMM at (p, theta): errors and times (host tree/traversal, GPU phases)."""
+    def run(self, p, theta, ncrit, precision="mixed", tree=None, timed=True, device=False):
+        """One FMM at (p, theta): errors and times (tree build, traversal on the
+        host or with device=True on the GPU, GPU phases)."""
         import torch
 
+        xd = torch.tensor(self.x, device=self.device) if device and tree is None else None
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         if tree is None:
-            tree = fmm.Tree(self.x, ncrit)
+            tree = fmm.Tree.from_device(xd, ncrit) if device else fmm.Tree(self.x, ncrit)
         t1 = time.perf_counter()
-        lists = fmm.Lists(tree, theta)
+        lists = fmm.Lists(tree, theta, device=device)
         t2 = time.perf_counter()
         dt = torch.float64 if precision == "fp64" else torch.float32
         qt = torch.tensor(self.q, dtype=dt, device=self.device)
@@ -69,7 +72,7 @@ class Problem:
 
 
 def largest_theta(problem, p, target, ncrit, metric="e_force", lo=0.02, hi=0.98, step=0.04,
-                  refine=7, precision="mixed"):
+                  refine=7, precision="mixed", device=False):
     """Largest theta in [lo, hi] whose error metric is <= target: scan from
     large theta downwards in `step`, then bisect inside the bracketing step.
     Returns (theta, run) or (None, None) if even `lo` misses the target."""
@@ -78,7 +81,7 @@ def largest_theta(problem, p, target, ncrit, metric="e_force", lo=0.02, hi=0.98,
     good = None
     bad = None
     for th in grid:
-        r = problem.run(p, float(th), ncrit, precision, tree=tree, timed=False)
+        r = problem.run(p, float(th), ncrit, precision, tree=tree, timed=False, device=device)
         if r[metric] <= target:
             good = (float(th), r)
             break
@@ -91,7 +94,7 @@ def largest_theta(problem, p, target, ncrit, metric="e_force", lo=0.02, hi=0.98,
     best = good
     for _ in range(refine):
         mid = 0.5 * (a + b)
-        r = problem.run(p, mid, ncrit, precision, tree=tree, timed=False)
+        r = problem.run(p, mid, ncrit, precision, tree=tree, timed=False, device=device)
         if r[metric] <= target:
             a, best = mid, (mid, r)
         else:
