@@ -378,57 +378,112 @@ __global__ void write_children(int64_t c0, int64_t c1, int level, const uint64_t
 
 // One 256-thread work-group per cell: tight bounding box of its bodies, its
 // middle as the centre, and the largest centre-to-body distance.
-__global__ __launch_bounds__(256) void cell_geometry(const double *__restrict__ pos,
-                                                     const int64_t *__restrict__ body_begin,
-                                                     const int64_t *__restrict__ n_body,
-                                                     double4 *__restrict__ geo) {
-  __shared__ double red[3][256];
-  __shared__ double X[3];
-  const int64_t c = blockIdx.x;
-  const int64_t b0 = body_begin[c], nb = n_body[c];
-  const int t = threadIdx.x;
-  double lo[3], hi[3];
+// Cell geometry in three passes over chunks of at most kGeoChunk bodies of
+// one cell (so the root's million bodies are spread over many blocks):
+// bounding box, centre = middle of the box, radius = largest centre-to-body
+// distance.  Partial minima and maxima of chunks are combined with 64-bit
+// integer atomics on an order-preserving encoding of the doubles, which is
+// exact and independent of the order, so the result equals the host's.
+constexpr int64_t kGeoChunk = 2048;
+
+__device__ __forceinline__ uint64_t order_key(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double order_value(uint64_t k) {
+  return __longlong_as_double((long long)((k >> 63) ? (k & 0x7fffffffffffffffull) : ~k));
+}
+
+__global__ void geo_chunk_count(int64_t ncells, const int64_t *__restrict__ n_body,
+                                int32_t *__restrict__ nchunk) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncells) nchunk[c] = (int32_t)((n_body[c] + kGeoChunk - 1) / kGeoChunk);
+}
+
+// chunk table entry: cell | chunk index << 32; also resets the accumulators
+__global__ void geo_chunk_fill(int64_t ncells, const int32_t *__restrict__ nchunk,
+                               const int32_t *__restrict__ off, uint64_t *__restrict__ tab,
+                               uint64_t *__restrict__ acc) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  for (int32_t k = 0; k < nchunk[c]; ++k) tab[off[c] + k] = (uint64_t)c | ((uint64_t)k << 32);
   for (int d = 0; d < 3; ++d) {
-    lo[d] = __builtin_inf();
-    hi[d] = -__builtin_inf();
+    acc[7 * c + d] = ~0ull;     // lo: min of keys
+    acc[7 * c + 3 + d] = 0ull;  // hi: max of keys
   }
-  for (int64_t j = t; j < nb; j += 256)
+  acc[7 * c + 6] = 0ull;        // radius bits (non-negative doubles order as integers)
+}
+
+template <int PASS>
+__global__ __launch_bounds__(256) void geo_chunk(const double *__restrict__ pos,
+                                                 const int64_t *__restrict__ body_begin,
+                                                 const int64_t *__restrict__ n_body,
+                                                 const uint64_t *__restrict__ tab,
+                                                 const double4 *__restrict__ geo,
+                                                 uint64_t *__restrict__ acc) {
+  __shared__ uint64_t red[6][256];
+  const uint64_t e = tab[blockIdx.x];
+  const int64_t c = (int64_t)(e & 0xffffffffull), k = (int64_t)(e >> 32);
+  const int64_t j0 = k * kGeoChunk;
+  const int64_t j1 = n_body[c] < j0 + kGeoChunk ? n_body[c] : j0 + kGeoChunk;
+  const double *p = pos + 3 * body_begin[c];
+  const int t = threadIdx.x;
+  if (PASS == 0) {
+    uint64_t lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0ull, 0ull, 0ull};
+    for (int64_t j = j0 + t; j < j1; j += 256)
+      for (int d = 0; d < 3; ++d) {
+        const uint64_t v = order_key(p[3 * j + d]);
+        lo[d] = v < lo[d] ? v : lo[d];
+        hi[d] = v > hi[d] ? v : hi[d];
+      }
     for (int d = 0; d < 3; ++d) {
-      const double v = pos[3 * (b0 + j) + d];
-      lo[d] = v < lo[d] ? v : lo[d];
-      hi[d] = v > hi[d] ? v : hi[d];
+      red[d][t] = lo[d];
+      red[3 + d][t] = hi[d];
     }
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int d = 0; d < 3; ++d) red[d][t] = pass == 0 ? lo[d] : hi[d];
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
       if (t < h)
-        for (int d = 0; d < 3; ++d)
-          red[d][t] = pass == 0 ? (red[d][t + h] < red[d][t] ? red[d][t + h] : red[d][t])
-                                : (red[d][t + h] > red[d][t] ? red[d][t + h] : red[d][t]);
+        for (int d = 0; d < 3; ++d) {
+          red[d][t] = red[d][t + h] < red[d][t] ? red[d][t + h] : red[d][t];
+          red[3 + d][t] = red[3 + d][t + h] > red[3 + d][t] ? red[3 + d][t + h] : red[3 + d][t];
+        }
       __syncthreads();
     }
-    if (t == 0)
-      for (int d = 0; d < 3; ++d) (pass == 0 ? lo : hi)[d] = red[d][0];
+    if (t < 3) atomicMin((unsigned long long *)&acc[7 * c + t], (unsigned long long)red[t][0]);
+    else if (t < 6)
+      atomicMax((unsigned long long *)&acc[7 * c + t], (unsigned long long)red[t][0]);
+  } else {
+    const double4 g = geo[c];
+    double rmax = 0.0;
+    for (int64_t j = j0 + t; j < j1; j += 256) {
+      const double dx = p[3 * j] - g.x, dy = p[3 * j + 1] - g.y, dz = p[3 * j + 2] - g.z;
+      const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+      rmax = r > rmax ? r : rmax;
+    }
+    red[0][t] = (uint64_t)__double_as_longlong(rmax);
     __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (t < h) red[0][t] = red[0][t + h] > red[0][t] ? red[0][t + h] : red[0][t];
+      __syncthreads();
+    }
+    if (t == 0) atomicMax((unsigned long long *)&acc[7 * c + 6], (unsigned long long)red[0][0]);
   }
-  if (t == 0)
-    for (int d = 0; d < 3; ++d) X[d] = 0.5 * (lo[d] + hi[d]);
-  __syncthreads();
-  double rmax = 0.0;
-  for (int64_t j = t; j < nb; j += 256) {
-    const double *p = &pos[3 * (b0 + j)];
-    const double dx = p[0] - X[0], dy = p[1] - X[1], dz = p[2] - X[2];
-    const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-    rmax = r > rmax ? r : rmax;
+}
+
+// PASS 0: centre from the box (radius 0 for now); PASS 1: radius.
+template <int PASS>
+__global__ void geo_finish(int64_t ncells, const uint64_t *__restrict__ acc,
+                           double4 *__restrict__ geo) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  if (PASS == 0) {
+    double X[3];
+    for (int d = 0; d < 3; ++d)
+      X[d] = 0.5 * (order_value(acc[7 * c + d]) + order_value(acc[7 * c + 3 + d]));
+    geo[c] = make_double4(X[0], X[1], X[2], 0.0);
+  } else {
+    geo[c].w = __longlong_as_double((long long)acc[7 * c + 6]);
   }
-  red[0][t] = rmax;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (t < h) red[0][t] = red[0][t + h] > red[0][t] ? red[0][t + h] : red[0][t];
-    __syncthreads();
-  }
-  if (t == 0) geo[c] = make_double4(X[0], X[1], X[2], red[0][0]);
 }
 
 __global__ void narrow_i64(int64_t n, const int64_t *__restrict__ in, int32_t *__restrict__ out) {
@@ -674,9 +729,46 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
   t.level_begin[t.max_level + 1] = ncells;
   // geometry
   TRY(hipMalloc((void **)&out.geo, ncells * 32));
-  cell_geometry<<<(unsigned)ncells, 256, 0, st>>>(out.pos, (const int64_t *)bb.p,
-                                                   (const int64_t *)nbd.p, (double4 *)out.geo);
-  TRY(hipGetLastError());
+  {
+    Buf gcnt, goff, gtab, gacc;
+    TRY(gcnt.reserve(ncells * 4, st, false));
+    TRY(goff.reserve(ncells * 4, st, false));
+    TRY(gacc.reserve(ncells * 7 * 8, st, false));
+    const unsigned gb = blocks_for(ncells, 256);
+    geo_chunk_count<<<gb, 256, 0, st>>>(ncells, (const int64_t *)nbd.p, (int32_t *)gcnt.p);
+    TRY(hipGetLastError());
+    size_t tsb = 0;
+    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tsb, (int32_t *)gcnt.p, (int32_t *)goff.p,
+                                         (int)ncells, st));
+    TRY(temp.reserve(tsb, st, false));
+    TRY(hipcub::DeviceScan::ExclusiveSum(temp.p, tsb, (int32_t *)gcnt.p, (int32_t *)goff.p,
+                                         (int)ncells, st));
+    int32_t last[2];
+    TRY(hipMemcpyAsync(&last[0], (int32_t *)goff.p + ncells - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&last[1], (int32_t *)gcnt.p + ncells - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    const int64_t nchunks = (int64_t)last[0] + last[1];
+    TRY(gtab.reserve(nchunks * 8, st, false));
+    geo_chunk_fill<<<gb, 256, 0, st>>>(ncells, (const int32_t *)gcnt.p, (const int32_t *)goff.p,
+                                       (uint64_t *)gtab.p, (uint64_t *)gacc.p);
+    TRY(hipGetLastError());
+    geo_chunk<0><<<(unsigned)nchunks, 256, 0, st>>>(out.pos, (const int64_t *)bb.p,
+                                                     (const int64_t *)nbd.p,
+                                                     (const uint64_t *)gtab.p,
+                                                     (const double4 *)out.geo,
+                                                     (uint64_t *)gacc.p);
+    TRY(hipGetLastError());
+    geo_finish<0><<<gb, 256, 0, st>>>(ncells, (const uint64_t *)gacc.p, (double4 *)out.geo);
+    TRY(hipGetLastError());
+    geo_chunk<1><<<(unsigned)nchunks, 256, 0, st>>>(out.pos, (const int64_t *)bb.p,
+                                                     (const int64_t *)nbd.p,
+                                                     (const uint64_t *)gtab.p,
+                                                     (const double4 *)out.geo,
+                                                     (uint64_t *)gacc.p);
+    TRY(hipGetLastError());
+    geo_finish<1><<<gb, 256, 0, st>>>(ncells, (const uint64_t *)gacc.p, (double4 *)out.geo);
+    TRY(hipGetLastError());
+  }
   TRY(hipMalloc((void **)&out.body_begin, ncells * 4));
   TRY(hipMalloc((void **)&out.n_body, ncells * 4));
   narrow_i64<<<blocks_for(ncells, 256), 256, 0, st>>>(ncells, (const int64_t *)bb.p, out.body_begin);
