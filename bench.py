@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--config", default="uniform-1e6-p4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--share-gpus", type=int, default=8,
+                    help="also time one GPU's share of the targets when they are split into "
+                         "this many Morton ranges (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first, as a reference "
                          "for hardware memory-traffic counters")
@@ -154,6 +157,31 @@ def main():
     p2p_s = phase_ms["p2p"] * 1e-3
     achieved = FLOP_PER_PAIR * pairs / p2p_s / 1e12
 
+    # One GPU's share: the targets split into G weighted Morton ranges, each
+    # range evaluated alone (P2P, M2L, L2L, L2P for its cells; the upward
+    # pass in full), device time per range.
+    share = None
+    if args.share_gpus > 0:
+        G = args.share_gpus
+        bounds = fmm.partition(tree, lists, G, p=p)
+        per = []
+        for k in range(G):
+            rng = (bounds[k], bounds[k + 1])
+            fmm.evaluate(tree, lists, qt, p, out=(phi, grad), body_range=rng)
+            tot = 0.0
+            for _ in range(5):
+                fmm.evaluate(tree, lists, qt, p, timing=True, out=(phi, grad), body_range=rng)
+                tot += fmm.last_timings(lists)["total"]
+            per.append(tot / 5)
+        torch.cuda.synchronize()
+        share = {"n_ranges": G, "range_ms": per, "max_ms": max(per),
+                 "mean_ms": sum(per) / G, "imbalance": max(per) / (sum(per) / G),
+                 "full_eval_ms": phase_ms["total"],
+                 "bodies": [int(b) for b in bounds]}
+        print("share: max %.3f ms mean %.3f ms (full %.3f ms)" % (
+            share["max_ms"], share["mean_ms"], share["full_eval_ms"]), file=sys.stderr, flush=True)
+        fmm.evaluate(tree, lists, qt, p, out=(phi, grad))  # restore the full result
+
     # accuracy against an FP64 direct sum on 1000 sampled targets
     tg = W.sample_targets(n, 1000)
     dphi, dg = fmm.direct(torch.tensor(x, device=dev), torch.tensor(q, device=dev),
@@ -221,6 +249,7 @@ def main():
         "phase_ms": phase_ms,
         "host_s": {"tree_build": t_tree, "traverse": t_trav},
         "gpu_build": gpu_build,
+        "one_gpu_share": share,
         "lists": stats,
         "accuracy_vs_fp64_direct_1000": {"e_phi": e_phi, "e_grad": e_grad, "e_force": e_force},
         "fwd_bwd": fb,

@@ -218,6 +218,37 @@ int fmm_evaluate(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o, 
                  void *phi_dev, void *grad_dev, void *stream);
 
 /*
+ * Evaluation for the targets of one range of leaves in Morton order: the
+ * share of one GPU when the target bodies are split into contiguous Morton
+ * ranges (the partition of a global Morton order with work weights that
+ * section 2 of the paper describes for distributed trees).
+ *   body_begin, body_end  Morton positions, 0 <= body_begin <= body_end <= n,
+ *                         each the first body of a leaf or n (else FMM_EINVAL);
+ *                         an empty range is a no-op.
+ *   q_dev, phi_dev, grad_dev, stream  as fmm_evaluate (user order, full length n).
+ * Writes phi and grad only for the bodies of the range (user index perm[b],
+ * see fmm_tree_view); other entries are left unchanged.  P2P, M2L, L2L and
+ * L2P run only for the cells that hold bodies of the range; P2M and M2M run
+ * for the whole tree (on several GPUs: local subtrees plus an exchange of
+ * multipoles).  The values written are bit for bit those of fmm_evaluate.
+ */
+int fmm_evaluate_range(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o,
+                       int64_t body_begin, int64_t body_end, const void *q_dev, void *phi_dev,
+                       void *grad_dev, void *stream);
+
+/*
+ * Split the target leaves, in Morton order, into n_parts contiguous ranges of
+ * about equal work for fmm_evaluate_range: a leaf weighs its P2P body pairs
+ * plus m2l_weight times its M2L entries, where the entries of a cell's row are
+ * shared among its bodies and passed down to the leaves below it.
+ *   bounds  host, [n_parts + 1] out: bounds[0] = 0, bounds[n_parts] = n,
+ *           non-decreasing, every bound a leaf boundary (ranges may be empty).
+ * Host only; for lists from fmm_traverse_gpu it makes their host copy.
+ */
+int fmm_partition_targets(const fmm_tree *t, const fmm_lists *l, int n_parts, double m2l_weight,
+                          int64_t *bounds);
+
+/*
  * Backward of L = sum_i w_i phi_i + sum_i v_i . grad_i for the forward above,
  * with the tree, lists, centres and radii held fixed.  The method is linear in
  * q and its far-field operator is symmetric (the lists are symmetric), so

@@ -23,6 +23,7 @@
 #include "fmm.h"
 #include "fmm_internal.h"
 #include "kernels.h"
+#include "shard.h"
 
 namespace {
 
@@ -76,6 +77,9 @@ struct DevLists {
   int32_t *m2l_col = nullptr, *p2p_col = nullptr;
   int64_t p2p_nnz = 0, m2l_nnz = 0;
   fmmlib::dev::DevicePlan plan;
+  // host copies for target-range evaluations: chunks and first item per leaf
+  std::vector<int32_t> leaf_nchunk_host;
+  std::vector<int64_t> leaf_item_host;
   // scratch for one (p, precision, top) configuration
   int p = 0, prec = -1;
   int64_t n_top = -1;
@@ -123,6 +127,8 @@ struct DevLists {
 struct fmm_tree {
   fmmlib::TreeData data;
   DevTree dev;
+  fmmlib::LeafIndex leaf_ix;  // built on the first target-range call
+  bool leaf_ix_valid = false;
 };
 
 struct fmm_lists {
@@ -310,6 +316,7 @@ int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
   dp.n_partials = pl.n_partials;
   dp.max_row_sources = pl.max_row_sources;
   dp.p2p_pairs = ld.p2p_pairs;
+  dv.leaf_nchunk_host = pl.leaf_nchunk;
   dv.device = t->dev.device;
   dv.uploaded = true;
   if (std::getenv("FMM_LOG"))
@@ -342,6 +349,34 @@ int ensure_lists_host(fmm_lists *l) {
       HIP_TRY(hipMemcpy(ld.m2l_col.data(), dv.m2l_col, dv.m2l_nnz * 4, hipMemcpyDeviceToHost));
   }
   dv.host_valid = true;
+  return FMM_OK;
+}
+
+// Leaf index of the tree and first P2P work item of every leaf.
+int ensure_range_tables(fmm_tree *t, fmm_lists *l) {
+  if (!t->leaf_ix_valid) {
+    fmmlib::build_leaf_index(t->data, t->leaf_ix);
+    t->leaf_ix_valid = true;
+  }
+  DevLists &dv = l->dev;
+  if (!dv.leaf_item_host.empty()) return FMM_OK;
+  const auto &ix = t->leaf_ix;
+  const int64_t nl = (int64_t)ix.cell.size();
+  if (dv.leaf_nchunk_host.size() != (size_t)nl) {
+    dv.leaf_nchunk_host.resize(nl);
+    if (nl > 0)
+      HIP_TRY(hipMemcpy(dv.leaf_nchunk_host.data(), dv.plan.leaf_nchunk, nl * 4,
+                        hipMemcpyDeviceToHost));
+  }
+  // items of one leaf: one per (group of 64 targets, source chunk), in leaf order
+  dv.leaf_item_host.assign(nl + 1, 0);
+  for (int64_t i = 0; i < nl; ++i)
+    dv.leaf_item_host[i + 1] = dv.leaf_item_host[i] +
+                               (t->data.n_body[ix.cell[i]] + 63) / 64 * dv.leaf_nchunk_host[i];
+  if (dv.leaf_item_host[nl] != dv.plan.n_items) {
+    set_error("internal error: P2P work items do not match the leaf table");
+    return FMM_EDEVICE;
+  }
   return FMM_OK;
 }
 
@@ -424,15 +459,23 @@ int check_pair(const fmm_tree *t, const fmm_lists *l) {
 // Enqueue one evaluation; outputs in user order.  mode kCharges: charges q ->
 // (phi, grad).  kDipoles: charges q plus dipoles -v_user (v_user [n][3]) ->
 // (phi, grad).  kHessVec: charges q; grad receives H[q] v_user.
+// rb0 <= rb1 (rb1 >= 0): only the targets of Morton positions [rb0, rb1),
+// which start and end on leaf boundaries; rb1 < 0: all targets.
 int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void *q, void *phi,
                   void *grad, void *stream, int mode = fmmlib::dev::kCharges,
-                  const void *v_user = nullptr) {
+                  const void *v_user = nullptr, int64_t rb0 = 0, int64_t rb1 = -1) {
   namespace D = fmmlib::dev;
   const fmmlib::TreeData &td = t->data;
   const bool fp64 = o->precision == FMM_FP64;
   if (int rc = ensure_tree_device(t, fp64, stream)) return rc;
   if (int rc = ensure_lists_device(t, l)) return rc;
   if (int rc = ensure_scratch(t, l, o)) return rc;
+  const bool ranged = rb1 >= 0;
+  fmmlib::RangeCells rcells;
+  if (ranged) {
+    if (int rc = ensure_range_tables(t, l)) return rc;
+    fmmlib::range_cells(td, t->leaf_ix, rb0, rb1, rcells);
+  }
   DevLists &dv = l->dev;
   DevTree &dt = t->dev;
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -484,8 +527,19 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
     HIP_TRY(hipStreamWaitEvent(ns, dv.fork, 0));
   }
   if (int rc = mark(8, ns)) return rc;
-  LAUNCH_TRY(D::p2p(fp64, mode, mask_all, pl.n_items, pl.items, pl.run_body, pl.run_prefix,
-                    bodies, vec, dv.part_s, dv.part_c, ns));
+  if (!ranged) {
+    LAUNCH_TRY(D::p2p(fp64, mode, mask_all, pl.n_items, pl.items, pl.run_body, pl.run_prefix,
+                      bodies, vec, dv.part_s, dv.part_c, ns));
+  } else {
+    // the items of the range's leaves: one contiguous run per level
+    for (int lev = 0; lev <= max_level; ++lev) {
+      const int64_t i0 = dv.leaf_item_host[rcells.leaf_lo[lev]];
+      const int64_t i1 = dv.leaf_item_host[rcells.leaf_hi[lev]];
+      if (i1 > i0)
+        LAUNCH_TRY(D::p2p(fp64, mode, mask_all, i1 - i0, pl.items + i0, pl.run_body,
+                          pl.run_prefix, bodies, vec, dv.part_s, dv.part_c, ns));
+    }
+  }
   if (int rc = mark(9, ns)) return rc;
   if (overlap) HIP_TRY(hipEventRecord(dv.join, ns));
 
@@ -504,14 +558,24 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   if (int rc = mark(3, s)) return rc;
   {
     // every cell is an M2L row (one without entries writes zeros); the top
-    // n_top cells accumulate in FP64
-    const int64_t nc = td.n_cells();
-    const int64_t split = std::min(n_top, nc);
-    if (split > 0)
-      LAUNCH_TRY(D::m2l(p, fp64, 0, split, dv.m2l_ptr, dv.m2l_col, geo, dv.M, dv.L, dv.L64, true,
-                        stream));
-    LAUNCH_TRY(D::m2l(p, fp64, split, nc, dv.m2l_ptr, dv.m2l_col, geo, dv.M, dv.L, dv.L64, false,
-                      stream));
+    // n_top cells accumulate in FP64.  A target range takes, level by level,
+    // the cells holding its bodies.
+    auto m2l_cells = [&](int64_t c0, int64_t c1) -> int {
+      const int64_t split = std::max(c0, std::min(n_top, c1));
+      if (split > c0)
+        LAUNCH_TRY(D::m2l(p, fp64, c0, split, dv.m2l_ptr, dv.m2l_col, geo, dv.M, dv.L, dv.L64,
+                          true, stream));
+      if (c1 > split)
+        LAUNCH_TRY(D::m2l(p, fp64, split, c1, dv.m2l_ptr, dv.m2l_col, geo, dv.M, dv.L, dv.L64,
+                          false, stream));
+      return FMM_OK;
+    };
+    if (!ranged) {
+      if (int rc = m2l_cells(0, td.n_cells())) return rc;
+    } else {
+      for (int lev = 0; lev <= max_level; ++lev)
+        if (int rc = m2l_cells(rcells.cell_lo[lev], rcells.cell_hi[lev])) return rc;
+    }
   }
   if (o->flags & FMM_EVAL_KEEP_STAGES) {
     HIP_TRY(hipMemcpyAsync(dv.Lstage, dv.L, (size_t)td.n_cells() * S * real,
@@ -528,13 +592,16 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
     const int64_t c0 = td.level_begin[lev], c1 = td.level_begin[lev + 1];
     const bool parent64 = td.level_begin[lev] <= n_top && n_top > 0;
     const bool child64 = c1 <= n_top;
-    LAUNCH_TRY(D::l2l(p, fp64, c0, c1, dt.parent, geo, dv.L, dv.L64, parent64, child64, stream));
+    const int64_t r0 = ranged ? rcells.cell_lo[lev] : c0, r1 = ranged ? rcells.cell_hi[lev] : c1;
+    if (r1 > r0)
+      LAUNCH_TRY(D::l2l(p, fp64, r0, r1, dt.parent, geo, dv.L, dv.L64, parent64, child64,
+                        stream));
   }
   if (n_top > 0) LAUNCH_TRY(D::copy_top_locals(p, n_top, dv.L64, (float *)dv.L, stream));
   if (int rc = mark(5, s)) return rc;
   if (overlap) HIP_TRY(hipStreamWaitEvent(s, dv.join, 0));
   if (int rc = mark(6, s)) return rc;
-  LAUNCH_TRY(D::l2p_combine(p, fp64, mode, td.n, pl.body_leaf, pl.leaf_cell, pl.leaf_pbase,
+  LAUNCH_TRY(D::l2p_combine(p, fp64, mode, ranged ? rb0 : 0, ranged ? rb1 : td.n, pl.body_leaf, pl.leaf_cell, pl.leaf_pbase,
                             pl.leaf_nchunk, dt.body_begin, dt.n_body, geo, dv.L, bodies, vec,
                             dv.part_s, dv.part_c, dt.perm, phi, grad, stream));
   if (int rc = mark(7, s)) return rc;
@@ -904,6 +971,66 @@ int fmm_evaluate(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o, 
     set_error("fmm_evaluate: out of host memory");
     return FMM_ENOMEM;
   }
+}
+
+int fmm_evaluate_range(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o,
+                       int64_t body_begin, int64_t body_end, const void *q_dev, void *phi_dev,
+                       void *grad_dev, void *stream) {
+  if (int rc = check_pair(t, l)) return rc;
+  if (int rc = check_opts(o)) return rc;
+  fmm_tree *tt = const_cast<fmm_tree *>(t);
+  const int64_t n = t->data.n;
+  if (body_begin < 0 || body_end < body_begin || body_end > n) {
+    set_error("fmm_evaluate_range: need 0 <= body_begin <= body_end <= n");
+    return FMM_EINVAL;
+  }
+  if (n == 0 || body_begin == body_end) return FMM_OK;
+  if (!q_dev || !phi_dev) {
+    set_error("fmm_evaluate_range: q and phi must not be NULL");
+    return FMM_EINVAL;
+  }
+  try {
+    if (!tt->leaf_ix_valid) {
+      fmmlib::build_leaf_index(t->data, tt->leaf_ix);
+      tt->leaf_ix_valid = true;
+    }
+    if (!fmmlib::is_leaf_boundary(t->data, t->leaf_ix, body_begin) ||
+        !fmmlib::is_leaf_boundary(t->data, t->leaf_ix, body_end)) {
+      set_error("fmm_evaluate_range: body_begin and body_end must be leaf boundaries");
+      return FMM_EINVAL;
+    }
+    return evaluate_impl(tt, const_cast<fmm_lists *>(l), o, q_dev, phi_dev, grad_dev, stream,
+                         fmmlib::dev::kCharges, nullptr, body_begin, body_end);
+  } catch (const std::bad_alloc &) {
+    set_error("fmm_evaluate_range: out of host memory");
+    return FMM_ENOMEM;
+  }
+}
+
+int fmm_partition_targets(const fmm_tree *t, const fmm_lists *l, int n_parts, double m2l_weight,
+                          int64_t *bounds) {
+  if (int rc = check_pair(t, l)) return rc;
+  if (n_parts < 1 || !bounds || !(m2l_weight >= 0.0)) {
+    set_error("fmm_partition_targets: need n_parts >= 1, bounds != NULL, m2l_weight >= 0");
+    return FMM_EINVAL;
+  }
+  fmm_tree *tt = const_cast<fmm_tree *>(t);
+  try {
+    if (t->data.n == 0) {
+      for (int k = 0; k <= n_parts; ++k) bounds[k] = 0;
+      return FMM_OK;
+    }
+    if (int rc = ensure_lists_host(const_cast<fmm_lists *>(l))) return rc;
+    if (!tt->leaf_ix_valid) {
+      fmmlib::build_leaf_index(t->data, tt->leaf_ix);
+      tt->leaf_ix_valid = true;
+    }
+    fmmlib::partition_targets(t->data, l->data, t->leaf_ix, n_parts, m2l_weight, bounds);
+  } catch (const std::bad_alloc &) {
+    set_error("fmm_partition_targets: out of host memory");
+    return FMM_ENOMEM;
+  }
+  return FMM_OK;
 }
 
 int fmm_evaluate_backward(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o,

@@ -223,7 +223,7 @@ __global__ void copy_top_kernel(int64_t n, const double *__restrict__ src, float
 // ----------------------------------------------------------------------------
 template <int P, typename Real, bool KAHAN, bool HESS>
 __global__ __launch_bounds__(256) void l2p_combine_kernel(
-    int64_t n, const int32_t *__restrict__ body_leaf, const int32_t *__restrict__ leaf_cell,
+    int64_t i0, int64_t i1, const int32_t *__restrict__ body_leaf, const int32_t *__restrict__ leaf_cell,
     const int32_t *__restrict__ leaf_pbase, const int32_t *__restrict__ leaf_nchunk,
     const int32_t *__restrict__ cell_body_begin, const int32_t *__restrict__ cell_n_body,
     const double4 *__restrict__ geo, const Real *__restrict__ L,
@@ -234,8 +234,8 @@ __global__ __launch_bounds__(256) void l2p_combine_kernel(
     Real *__restrict__ phi_out, Real *__restrict__ grad_out) {
   using V4 = typename Vec<Real>::V4;
   constexpr int T = nterms(P), S = pad4(T);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int64_t i = i0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= i1) return;
   const int a = body_leaf[i];
   const int c = leaf_cell[a];
   const V4 b = bodies[i];
@@ -411,7 +411,7 @@ int copy_top_locals(int p, int64_t n_top, const double *L64, float *L, void *str
 }
 
 template <int PP, typename Real, bool HESS>
-void launch_l2p(unsigned nb, hipStream_t st, int64_t n, const int32_t *body_leaf,
+void launch_l2p(unsigned nb, hipStream_t st, int64_t i0, int64_t i1, const int32_t *body_leaf,
                 const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
                 const int32_t *cell_body_begin, const int32_t *cell_n_body, const double4 *g,
                 const void *L, const void *bodies, const void *tvec, const void *part_s,
@@ -419,37 +419,37 @@ void launch_l2p(unsigned nb, hipStream_t st, int64_t n, const int32_t *body_leaf
   using V4 = typename Vec<Real>::V4;
   constexpr bool kahan = std::is_same<Real, float>::value;
   l2p_combine_kernel<PP, Real, kahan, HESS><<<nb, 256, 0, st>>>(
-      n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk, cell_body_begin, cell_n_body, g,
+      i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk, cell_body_begin, cell_n_body, g,
       (const Real *)L, (const V4 *)bodies, (const V4 *)tvec, (const V4 *)part_s,
       (const V4 *)part_c, perm, (Real *)phi, (Real *)grad);
 }
 
-int l2p_combine(int p, bool fp64, int mode, int64_t n, const int32_t *body_leaf,
+int l2p_combine(int p, bool fp64, int mode, int64_t i0, int64_t i1, const int32_t *body_leaf,
                 const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
                 const int32_t *cell_body_begin, const int32_t *cell_n_body, const double *geo,
                 const void *L, const void *bodies, const void *tvec, const void *part_s,
                 const void *part_c, const int32_t *perm, void *phi, void *grad, void *stream) {
-  if (n == 0) return 0;
-  const unsigned nb = blocks_for(n, 256);
+  if (i1 <= i0) return 0;
+  const unsigned nb = blocks_for(i1 - i0, 256);
   const double4 *g = (const double4 *)geo;
   const hipStream_t st = S_(stream);
   const bool hess = mode == kHessVec;
   return with_p(p, [&](auto PC) {
     constexpr int PP = decltype(PC)::value;
     if (fp64 && hess)
-      launch_l2p<PP, double, true>(nb, st, n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
+      launch_l2p<PP, double, true>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                    cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
                                    nullptr, perm, nullptr, grad);
     else if (fp64)
-      launch_l2p<PP, double, false>(nb, st, n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
+      launch_l2p<PP, double, false>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                     cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
                                     nullptr, perm, phi, grad);
     else if (hess)
-      launch_l2p<PP, float, true>(nb, st, n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
+      launch_l2p<PP, float, true>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                   cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
                                   part_c, perm, nullptr, grad);
     else
-      launch_l2p<PP, float, false>(nb, st, n, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
+      launch_l2p<PP, float, false>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                    cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
                                    part_c, perm, phi, grad);
   });

@@ -63,7 +63,8 @@ int copy_top_locals(int p, int64_t n_top, const double *L64, float *L, void *str
 
 // kHessVec: tvec holds the per-target vectors (Morton order) and grad receives
 // H v; phi is not written.
-int l2p_combine(int p, bool fp64, int mode, int64_t n, const int32_t *body_leaf,
+// Bodies [i0, i1) (Morton positions).
+int l2p_combine(int p, bool fp64, int mode, int64_t i0, int64_t i1, const int32_t *body_leaf,
                 const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
                 const int32_t *cell_body_begin, const int32_t *cell_n_body, const double *geo,
                 const void *L, const void *bodies, const void *tvec, const void *part_s,

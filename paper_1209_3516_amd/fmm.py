@@ -59,7 +59,8 @@ EXPORTS = ("fmm_tree_build", "fmm_tree_set_positions", "fmm_tree_view", "fmm_tre
            "fmm_traverse", "fmm_lists_view", "fmm_lists_stats", "fmm_lists_free",
            "fmm_evaluate", "fmm_evaluate_backward", "fmm_direct", "fmm_last_timings",
            "fmm_last_error", "fmm_num_terms", "fmm_copy_expansions", "fmm_term_exponents",
-           "fmm_traverse_gpu", "fmm_tree_build_gpu")
+           "fmm_traverse_gpu", "fmm_tree_build_gpu", "fmm_evaluate_range",
+           "fmm_partition_targets")
 
 _lib = None
 
@@ -89,6 +90,9 @@ def lib():
         "fmm_lists_stats": ([vp, ctypes.POINTER(_ListStats)], i32),
         "fmm_lists_free": ([vp], None),
         "fmm_evaluate": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp], i32),
+        "fmm_evaluate_range": ([vp, vp, ctypes.POINTER(_EvalOpts), i64, i64, vp, vp, vp, vp],
+                               i32),
+        "fmm_partition_targets": ([vp, vp, i32, dbl, vp], i32),
         "fmm_evaluate_backward": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp, vp, vp,
                                    vp], i32),
         "fmm_direct": ([vp, vp, i64, vp, i64, vp, vp, vp], i32),
@@ -265,10 +269,12 @@ def _check_tensor(t, n, dtype, name, cols=None):
 
 
 def evaluate(tree, lists, q, p, precision="mixed", grad=True, timing=False, keep_stages=False,
-             fp64_top_levels=-1, out=None, serial=False):
+             fp64_top_levels=-1, out=None, serial=False, body_range=None):
     """One FMM evaluation.  q: CUDA tensor [n] (float32 for "mixed", float64 for
     "fp64"), user order.  Returns (phi [n], grad [n,3] or None).  serial=True
-    keeps the near field on the caller's stream (no overlap with the far field)."""
+    keeps the near field on the caller's stream (no overlap with the far field).
+    body_range=(b0, b1): only the targets at Morton positions [b0, b1) (leaf
+    boundaries, e.g. from partition()); other output entries are not written."""
     import torch
     dt = _dtype(precision)
     _check_tensor(q, tree.n, dt, "q")
@@ -280,9 +286,32 @@ def evaluate(tree, lists, q, p, precision="mixed", grad=True, timing=False, keep
     flags = ((FMM_EVAL_TIMING if timing else 0) | (FMM_EVAL_KEEP_STAGES if keep_stages else 0)
              | (FMM_EVAL_SERIAL if serial else 0))
     o = _opts(p, precision, flags, fp64_top_levels)
-    _check(lib().fmm_evaluate(tree._h, lists._h, ctypes.byref(o), _t_ptr(q), _t_ptr(phi),
-                              _t_ptr(g), _stream()))
+    if body_range is None:
+        _check(lib().fmm_evaluate(tree._h, lists._h, ctypes.byref(o), _t_ptr(q), _t_ptr(phi),
+                                  _t_ptr(g), _stream()))
+    else:
+        b0, b1 = (int(v) for v in body_range)
+        _check(lib().fmm_evaluate_range(tree._h, lists._h, ctypes.byref(o), b0, b1, _t_ptr(q),
+                                        _t_ptr(phi), _t_ptr(g), _stream()))
     return phi, g
+
+
+def m2l_weight(p):
+    """Estimated cost of one M2L entry in units of one P2P pair at order p: the
+    contraction's multiply-adds, C(p+5, 6), plus about 8 operations per
+    derivative term of the recurrence, over 14 instructions per pair."""
+    from math import comb
+    return (comb(p + 5, 6) + 8 * (p * (p + 1) * (p + 2) // 6)) / 14.0
+
+
+def partition(tree, lists, n_parts, weight=None, p=4):
+    """Split the targets into n_parts contiguous Morton ranges of about equal
+    work (P2P pairs + weight * M2L entries; weight defaults to m2l_weight(p)).
+    Returns int64 bounds [n_parts + 1]; range k is [bounds[k], bounds[k+1])."""
+    w = m2l_weight(p) if weight is None else float(weight)
+    bounds = np.zeros(int(n_parts) + 1, np.int64)
+    _check(lib().fmm_partition_targets(tree._h, lists._h, int(n_parts), w, _np_ptr(bounds)))
+    return bounds
 
 
 def evaluate_backward(tree, lists, q, grad_q, w, p, precision="mixed", need_dq=True,

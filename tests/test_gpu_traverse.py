@@ -183,3 +183,42 @@ def test_end_to_end_on_gpu_full_size():
     ref = fmm.evaluate(host, fmm.Lists(host, 0.4), qt, 4)
     torch.cuda.synchronize()
     assert torch.equal(ref[0], phi) and torch.equal(ref[1], g)
+
+
+@pytest.mark.parametrize("kind,n,ncrit,theta,p,precision,G,device", [
+    ("uniform", 100_000, 64, 0.4, 4, "mixed", 8, True),
+    ("uniform", 100_000, 64, 0.4, 4, "mixed", 3, False),
+    ("plummer", 60_000, 16, 0.35, 6, "mixed", 7, True),
+    ("uniform", 30_000, 16, 0.5, 8, "mixed", 5, True),   # FP64 top levels split inside ranges
+    ("uniform", 20_000, 32, 0.5, 4, "fp64", 4, False),
+    ("dup", 4300, 8, 0.6, 3, "mixed", 64, True),          # more ranges than some levels have cells
+])
+def test_target_ranges_reassemble_the_full_evaluation(kind, n, ncrit, theta, p, precision, G,
+                                                      device):
+    """Evaluating the G ranges of a partition, each writing only its targets,
+    gives the full evaluation bit for bit."""
+    x = {"uniform": lambda: W.uniform_cube(n, seed=120), "plummer": lambda: W.plummer(n, seed=120),
+         "dup": lambda: _points("dup")}[kind]()
+    m = x.shape[0]
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    q = torch.tensor(W.charges(m, seed=121), dtype=dt, device="cuda:0")
+    t = fmm.Tree(x, ncrit)
+    lst = fmm.Lists(t, theta, device=device)
+    ref = fmm.evaluate(t, lst, q, p, precision)
+    bounds = fmm.partition(t, lst, G, p=p)
+    phi = torch.full((m,), float("nan"), dtype=dt, device="cuda:0")
+    g = torch.full((m, 3), float("nan"), dtype=dt, device="cuda:0")
+    for k in range(G):
+        fmm.evaluate(t, lst, q, p, precision, out=(phi, g), body_range=(bounds[k], bounds[k + 1]))
+    torch.cuda.synchronize()
+    assert torch.equal(ref[0], phi) and torch.equal(ref[1], g)
+    # a range writes exactly its own targets
+    perm = t.view()["perm"]
+    b0, b1 = int(bounds[G // 2]), int(bounds[G // 2 + 1])
+    phi2 = torch.full((m,), float("nan"), dtype=dt, device="cuda:0")
+    fmm.evaluate(t, lst, q, p, precision, out=(phi2, None), body_range=(b0, b1))
+    torch.cuda.synchronize()
+    written = ~torch.isnan(phi2).cpu().numpy()
+    expect = np.zeros(m, bool)
+    expect[perm[b0:b1]] = True
+    np.testing.assert_array_equal(written, expect)
