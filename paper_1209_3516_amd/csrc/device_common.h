@@ -105,6 +105,38 @@ struct M2LTable {
 template <int P>
 inline constexpr M2LTable<P> kM2L{};
 
+// The same contraction ordered by source term n, so that each group of four
+// consecutive source terms (one 16-byte load of a multipole row) is used at
+// once: the entries of group g are [gbeg[g], gbeg[g + 1]).  For every target
+// term k the source terms still come in ascending order, as in M2LTable.
+template <int P>
+struct M2LTableBySource {
+  static constexpr int N = m2l_count(P);
+  static constexpr int G = (nterms(P) + 3) / 4;
+  int k[N], n[N], s[N], gbeg[G + 1];
+  constexpr M2LTableBySource() : k(), n(), s(), gbeg() {
+    constexpr int T = nterms(P);
+    Basis<P> B{};
+    int i = 0;
+    for (int g = 0; g < G; ++g) {
+      gbeg[g] = i;
+      for (int nn = 4 * g; nn < 4 * g + 4 && nn < T; ++nn)
+        for (int kk = 0; kk < T; ++kk) {
+          const int ss =
+              term_index(P, B.ex[kk] + B.ex[nn], B.ey[kk] + B.ey[nn], B.ez[kk] + B.ez[nn]);
+          if (ss < 0) continue;
+          k[i] = kk;
+          n[i] = nn;
+          s[i] = ss;
+          ++i;
+        }
+    }
+    gbeg[G] = i;
+  }
+};
+template <int P>
+inline constexpr M2LTableBySource<P> kM2LS{};
+
 // (hi, lo, diff): lo <= hi componentwise, diff = term of hi - lo.
 constexpr int shift_count(int p) {
   int c = 0;
@@ -220,6 +252,23 @@ template <int N, typename Real>
 __device__ __forceinline__ void load_row(const Real *__restrict__ src, Real (&dst)[N]) {
   const Real *p = static_cast<const Real *>(__builtin_assume_aligned(src, 16));
   static_for<N>([&](auto I) { dst[decltype(I)::value] = p[decltype(I)::value]; });
+}
+
+// Four consecutive values from a 16-byte aligned address.
+__device__ __forceinline__ void load4(const float *__restrict__ src, float (&dst)[4]) {
+  const float4 v = *static_cast<const float4 *>(__builtin_assume_aligned(src, 16));
+  dst[0] = v.x;
+  dst[1] = v.y;
+  dst[2] = v.z;
+  dst[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double *__restrict__ src, double (&dst)[4]) {
+  const double2 *p = static_cast<const double2 *>(__builtin_assume_aligned(src, 16));
+  const double2 a = p[0], b = p[1];
+  dst[0] = a.x;
+  dst[1] = a.y;
+  dst[2] = b.x;
+  dst[3] = b.y;
 }
 
 // Work-group b of G is placed on XCD b % 8; give each XCD a contiguous range

@@ -107,13 +107,16 @@ __global__ __launch_bounds__(64) void m2m_kernel(int64_t c0, int64_t c1, const i
 // recurrence and contracts it with the source multipole.  The 64 lane
 // partials are summed in LDS in a fixed order.
 // ----------------------------------------------------------------------------
+// Terms per round of the final cross-lane sum of M2L.
+constexpr int m2l_red_terms(int T) { return T < 64 ? T : 64; }
+
 template <int P, typename Real, typename Acc>
-__global__ __launch_bounds__(64) void m2l_kernel(int64_t r0, const int64_t *__restrict__ ptr,
-                                                 const int32_t *__restrict__ col,
-                                                 const double4 *__restrict__ geo,
-                                                 const Real *__restrict__ M, Acc *__restrict__ Lout) {
+__device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ ptr,
+                                        const int32_t *__restrict__ col,
+                                        const double4 *__restrict__ geo,
+                                        const Real *__restrict__ M, Acc *__restrict__ Lout,
+                                        Acc *__restrict__ red) {
   constexpr int T = nterms(P), S = pad4(T);
-  __shared__ Acc red[64 * (T + 1)];
   const int lane = threadIdx.x;
   const int A = (int)(r0 + xcd_remap(blockIdx.x, gridDim.x));
   const double4 ga = geo[A];
@@ -158,27 +161,66 @@ __global__ __launch_bounds__(64) void m2l_kernel(int64_t r0, const int64_t *__re
       e += 64;
     }
   } else {
-    // High orders: registers are the limit, so no prefetch.
+    // High orders: the accumulators and the derivatives fill the registers,
+    // so the source multipole is streamed in groups of four terms, each used
+    // by all its contraction entries as soon as it arrives (same order of
+    // additions per target term as above).
+    constexpr int G = kM2LS<P>.G;
     for (int64_t e = ptr[A] + lane; e < e1; e += 64) {
       const int B = col[e];
       const double4 gb = geo[B];
       Real D[T];
       derivatives<P, Real>(Real(ga.x - gb.x), Real(ga.y - gb.y), Real(ga.z - gb.z), D);
-      Real mb[T];
-      load_row<T>(M + (int64_t)B * S, mb);
-      static_for<kM2L<P>.N>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        acc[kM2L<P>.k[i]] += Acc(mb[kM2L<P>.n[i]] * D[kM2L<P>.s[i]]);
+      const Real *mrow = M + (int64_t)B * S;
+      static_for<G>([&](auto Gi) {
+        constexpr int g = decltype(Gi)::value;
+        Real m4[4];
+        load4(mrow + 4 * g, m4);
+        static_for<kM2LS<P>.gbeg[g + 1] - kM2LS<P>.gbeg[g]>([&](auto J) {
+          constexpr int i = kM2LS<P>.gbeg[g] + decltype(J)::value;
+          acc[kM2LS<P>.k[i]] += Acc(m4[kM2LS<P>.n[i] - 4 * g] * D[kM2LS<P>.s[i]]);
+        });
       });
     }
   }
-  static_for<T>([&](auto I) { red[lane * (T + 1) + decltype(I)::value] = acc[decltype(I)::value]; });
-  __syncthreads();
-  for (int t = lane; t < T; t += 64) {
-    Acc sum = Acc(0);
-    for (int l = 0; l < 64; ++l) sum += red[l * (T + 1) + t];
-    Lout[(int64_t)A * S + t] = sum;
-  }
+  // Sum the 64 lane partials of each term in lane order, at most 64 terms at
+  // a time (so that the LDS buffer does not limit how many waves a CU holds).
+  constexpr int CH = m2l_red_terms(T);
+  static_for<(T + CH - 1) / CH>([&](auto Ci) {
+    constexpr int c0 = decltype(Ci)::value * CH;
+    constexpr int nt = T - c0 < CH ? T - c0 : CH;
+    if constexpr (c0 > 0) __syncthreads();
+    static_for<nt>([&](auto I) {
+      constexpr int j = decltype(I)::value;
+      red[lane * (CH + 1) + j] = acc[c0 + j];
+    });
+    __syncthreads();
+    if (lane < nt) {
+      Acc sum = Acc(0);
+      for (int l = 0; l < 64; ++l) sum += red[l * (CH + 1) + lane];
+      Lout[(int64_t)A * S + c0 + lane] = sum;
+    }
+  });
+}
+
+template <int P, typename Real, typename Acc>
+__global__ __launch_bounds__(64) void m2l_kernel(int64_t r0, const int64_t *__restrict__ ptr,
+                                                 const int32_t *__restrict__ col,
+                                                 const double4 *__restrict__ geo,
+                                                 const Real *__restrict__ M, Acc *__restrict__ Lout) {
+  __shared__ Acc red[64 * (m2l_red_terms(nterms(P)) + 1)];
+  m2l_row<P, Real, Acc>(r0, ptr, col, geo, M, Lout, red);
+}
+
+// The same for high orders in FP32, held to two waves per SIMD (at most 256
+// registers per lane) so that one wave's multipole loads overlap the other
+// wave's arithmetic.
+template <int P, typename Real, typename Acc>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_kernel_w2(
+    int64_t r0, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+    const double4 *__restrict__ geo, const Real *__restrict__ M, Acc *__restrict__ Lout) {
+  __shared__ Acc red[64 * (m2l_red_terms(nterms(P)) + 1)];
+  m2l_row<P, Real, Acc>(r0, ptr, col, geo, M, Lout, red);
 }
 
 // ----------------------------------------------------------------------------
@@ -375,6 +417,9 @@ int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
     else if (acc_fp64)
       m2l_kernel<PP, float, double><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
                                                               (const float *)M, L64);
+    else if constexpr (nterms(PP) > 56)
+      m2l_kernel_w2<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
+                                                                (const float *)M, (float *)L);
     else
       m2l_kernel<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
                                                              (const float *)M, (float *)L);
