@@ -10,9 +10,11 @@ namespace {
 // of its source leaves).  Sources are staged through LDS in batches of kNB
 // bodies with coalesced 16-byte loads; lane (s, u) keeps R targets in
 // registers and reads every K-th staged source (a broadcast among the lanes
-// of one stream).  Within a batch each lane sums in plain arithmetic; the
-// batch partial is then added with Kahan compensation (FP32), and the K
-// streams and the chunks of a row are merged with the same compensation.
+// of one stream).  Each lane sums in plain arithmetic over its share of one
+// batch, or of ceil(K/8) consecutive batches when K > 8 (so a plain partial
+// covers at least 64 sources when the share is small); that partial is then
+// added with Kahan compensation (FP32), and the K streams and the chunks of
+// a row are merged with the same compensation.
 //
 // Modes (compile time):
 //   kCharges      sources are charges q: (phi, grad phi)
@@ -25,6 +27,23 @@ namespace {
 // the merge are shared.
 // ----------------------------------------------------------------------------
 constexpr int kNB = 512;
+
+// An LDS pointer in the LDS address space, as global_load_lds takes it.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(3))) void *lds_ptr(T *p) {
+  return (__attribute__((address_space(3))) void *)(p);
+}
+
+// Value of `v` in the lane whose byte address (4 * lane) is `addr`.
+__device__ __forceinline__ float lane_shuffle(float v, int addr) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_shuffle(double v, int addr) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 static_assert(kP2PMaxRuns == 256, "LDS run table size");
 
 template <typename Real, int MODE, int R, bool KAHAN, bool MASK, typename IndexFn>
@@ -39,31 +58,72 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
   using V4 = typename Vec<Real>::V4;
   const int lane = threadIdx.x;
   const Real far = Vec<Real>::kFar;
-  for (int off = 0; off < nsrc; off += kNB) {
-    const int nb = min(kNB, nsrc - off);
+  constexpr int NQ = kNB / 64 + 1;  // staged positions per lane (the last 64 are padding)
+  // The plain partial of a stream is added into (S, C) every `kb` batches, so
+  // that it covers at least 64 sources when a stream's share of one batch is
+  // smaller (kb = ceil(K / 8)).
+  const int kb = (K + 7) >> 3;
+  Real p[R][4];
 #pragma unroll
-    for (int q = 0; q <= kNB / 64; ++q) {
+  for (int r = 0; r < R; ++r) p[r][0] = p[r][1] = p[r][2] = p[r][3] = Real(0);
+  int batch = 0;
+  for (int off = 0; off < nsrc; off += kNB, ++batch) {
+    const int nb = min(kNB, nsrc - off);
+    // Staging.  FP32 bodies go from global memory straight into LDS
+    // (global_load_lds_dwordx4: lane l's 16 bytes land at base + 16 l), all
+    // loads of the batch in flight together and no registers held; positions
+    // past the batch load body 0 and are then overwritten with far-away
+    // zero-charge bodies.  FP64 bodies (32 bytes) are staged through
+    // registers, with all indices computed and all loads issued before the
+    // stores.
+    constexpr int NL = kNB / 64;  // positions that can hold sources
+    int bi[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
       const int pos = q * 64 + lane;
-      V4 v, dv;
-      if (pos < nb) {
-        const int b = body_of(off + pos);
-        v = bodies[b];
-        if constexpr (MODE == kDipoles) dv = dipoles[b];
-      } else {
-        v.x = far;
-        v.y = far;
-        v.z = far;
-        v.w = Real(0);
-        if constexpr (MODE == kDipoles) dv.x = dv.y = dv.z = dv.w = Real(0);
+      bi[q] = pos < nb ? body_of(off + pos) : 0;
+    }
+    if constexpr (sizeof(V4) == 16) {
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        __builtin_amdgcn_global_load_lds(static_cast<const void *>(bodies + bi[q]),
+                                         lds_ptr(src + q * 64), 16, 0, 0);
+        if constexpr (MODE == kDipoles)
+          __builtin_amdgcn_global_load_lds(static_cast<const void *>(dipoles + bi[q]),
+                                           lds_ptr(srcd + q * 64), 16, 0, 0);
       }
-      src[pos] = v;
-      if constexpr (MODE == kDipoles) srcd[pos] = dv;
+      __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of the loads are done
+    } else {
+      V4 v[NL];
+#pragma unroll
+      for (int q = 0; q < NL; ++q) v[q] = bodies[bi[q]];
+#pragma unroll
+      for (int q = 0; q < NL; ++q) src[q * 64 + lane] = v[q];
+      if constexpr (MODE == kDipoles) {
+#pragma unroll
+        for (int q = 0; q < NL; ++q) v[q] = dipoles[bi[q]];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) srcd[q * 64 + lane] = v[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if (q * 64 + lane >= nb) {
+        V4 fb;
+        fb.x = far;
+        fb.y = far;
+        fb.z = far;
+        fb.w = Real(0);
+        src[q * 64 + lane] = fb;
+        if constexpr (MODE == kDipoles) {
+          V4 z;
+          z.x = z.y = z.z = z.w = Real(0);
+          srcd[q * 64 + lane] = z;
+        }
+      }
     }
     __syncthreads();
     const int iters = (nb + K - 1) / K;
-    Real p[R][4];
-#pragma unroll
-    for (int r = 0; r < R; ++r) p[r][0] = p[r][1] = p[r][2] = p[r][3] = Real(0);
 #pragma unroll 2
     for (int j = 0; j < iters; ++j) {
       const V4 sj = src[s + K * j];
@@ -101,19 +161,22 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
         }
       }
     }
+    if (batch % kb == kb - 1 || off + kNB >= nsrc) {
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+      for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if constexpr (KAHAN) {
-          const Real y = p[r][c] - C[r][c];
-          const Real t = S[r][c] + y;
-          C[r][c] = (t - S[r][c]) - y;
-          S[r][c] = t;
-        } else {
-          S[r][c] += p[r][c];
+        for (int c = 0; c < 4; ++c) {
+          if constexpr (KAHAN) {
+            const Real y = p[r][c] - C[r][c];
+            const Real t = S[r][c] + y;
+            C[r][c] = (t - S[r][c]) - y;
+            S[r][c] = t;
+          } else {
+            S[r][c] += p[r][c];
+          }
+          p[r][c] = Real(0);
         }
-      }
+    }
     __syncthreads();
   }
 }
@@ -185,40 +248,43 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
         bodies, vec, src, srcd, s, K, xi, yi, zi, vt, S, C);
   }
 
-  // Merge the K streams (lanes s*L + u) into the lanes of stream 0.
-  V4 *red = src;
+  // Merge the K streams (lanes s*L + u) into the lanes of stream 0 as a tree:
+  // while more than one stream is left, the upper ceil-half folds into the
+  // lower part (stream s takes stream s + h), with values moved across lanes
+  // by ds_bpermute.  log2(K) steps with every lane busy, no LDS buffer.
+  int kc = K;
+  while (kc > 1) {
+    const int h = (kc + 1) >> 1;
+    const bool take = s < kc - h;
+    const int from = (lane + h * L) << 2;  // byte address of the partner lane
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    red[2 * lane] = V4{S[r][0], S[r][1], S[r][2], S[r][3]};
-    red[2 * lane + 1] = V4{C[r][0], C[r][1], C[r][2], C[r][3]};
-    __syncthreads();
-    if (lane < L) {
-      Real s4[4] = {S[r][0], S[r][1], S[r][2], S[r][3]};
-      Real c4[4] = {C[r][0], C[r][1], C[r][2], C[r][3]};
-      for (int s2 = 1; s2 < K; ++s2) {
-        const V4 ps = red[2 * (s2 * L + lane)];
-        const V4 pc = red[2 * (s2 * L + lane) + 1];
-        const Real vs[4] = {ps.x, ps.y, ps.z, ps.w};
-        const Real vc[4] = {pc.x, pc.y, pc.z, pc.w};
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if constexpr (KAHAN) {
-            const Real y = (vs[c] - vc[c]) - c4[c];
-            const Real t = s4[c] + y;
-            c4[c] = (t - s4[c]) - y;
-            s4[c] = t;
-          } else {
-            s4[c] += vs[c];
+      for (int c = 0; c < 4; ++c) {
+        const Real vs = lane_shuffle(S[r][c], from);
+        if constexpr (KAHAN) {
+          const Real vc = lane_shuffle(C[r][c], from);
+          if (take) {
+            const Real y = (vs - vc) - C[r][c];
+            const Real t = S[r][c] + y;
+            C[r][c] = (t - S[r][c]) - y;
+            S[r][c] = t;
           }
+        } else {
+          if (take) S[r][c] += vs;
         }
       }
+    kc = h;
+  }
+  if (s == 0 && lane < L) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
       const int t = lane + L * r;
       if (t < nt) {
-        out_s[it.out_off + t] = V4{s4[0], s4[1], s4[2], s4[3]};
-        if constexpr (KAHAN) out_c[it.out_off + t] = V4{c4[0], c4[1], c4[2], c4[3]};
+        out_s[it.out_off + t] = V4{S[r][0], S[r][1], S[r][2], S[r][3]};
+        if constexpr (KAHAN) out_c[it.out_off + t] = V4{C[r][0], C[r][1], C[r][2], C[r][3]};
       }
     }
-    __syncthreads();
   }
 }
 
