@@ -166,6 +166,30 @@ void l2p(const Terms &T, const double XA[3], const double *L, const double y[3],
   g[2] += gz;
 }
 
+// M2P (the treecode's evaluation of a multipole at a body, Algorithm 1):
+// Taylor's theorem for G(y - x_j) about y - X_B gives
+//   phi(y)         = sum_{|n| <= p-1} M_n(B) D^n G(y - X_B),
+//   d phi / d y_d  = sum_{|n| <= p-1} M_n(B) D^(n+e_d) G(y - X_B),
+// so the gradient needs derivatives up to degree p (a set of order p+1).
+void m2p(const Terms &T, const double XB[3], const double *M, const double y[3], double *phi,
+         double g[3]) {
+  const Terms T1(T.p + 1);
+  const double R[3] = {y[0] - XB[0], y[1] - XB[1], y[2] - XB[2]};
+  std::vector<double> D(T1.count());
+  derivatives(T1, R, D.data());
+  double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int n = 0; n < T.count(); ++n) {
+    f += M[n] * D[T1.index(T.ex[n], T.ey[n], T.ez[n])];
+    gx += M[n] * D[T1.index(T.ex[n] + 1, T.ey[n], T.ez[n])];
+    gy += M[n] * D[T1.index(T.ex[n], T.ey[n] + 1, T.ez[n])];
+    gz += M[n] * D[T1.index(T.ex[n], T.ey[n], T.ez[n] + 1)];
+  }
+  *phi += f;
+  g[0] += gx;
+  g[1] += gy;
+  g[2] += gz;
+}
+
 // P2P for one target point: phi += q_j / r, grad += q_j (x_j - x_i) / r^3,
 // pairs at zero distance contribute nothing (this also drops the self term).
 void p2p_point(const double xi[3], const double *x, const double *y, const double *z,
@@ -392,15 +416,24 @@ void build_tree(const double *xyz, int64_t n, int ncrit, Tree &tr) {
 // ---------------------------------------------------------------------------
 struct Lists {
   int64_t n_rows = 0;
-  std::vector<int64_t> p2p_ptr, m2l_ptr;
-  std::vector<int32_t> p2p_col, m2l_col;
+  std::vector<int64_t> p2p_ptr, m2l_ptr, m2p_ptr;
+  std::vector<int32_t> p2p_col, m2l_col, m2p_col;
 };
 
+// The traversal of Algorithms 3 and 4.  With m2p_max > 0 it is the
+// treecode/FMM hybrid: an accepted pair whose target is a leaf of at most
+// m2p_max bodies is evaluated by M2P at those bodies instead of M2L.
 struct Traversal {
   const Tree &tr;
   double theta;
   bool leaf_first;
-  std::vector<std::pair<int32_t, int32_t>> p2p, m2l;
+  int m2p_max;
+  std::vector<std::pair<int32_t, int32_t>> p2p, m2l, m2p;
+
+  void accepted(int a, int b) {
+    if (leaf(a) && tr.cells[a].n_body <= m2p_max) m2p.emplace_back(a, b);
+    else m2l.emplace_back(a, b);
+  }
 
   bool leaf(int c) const { return tr.cells[c].n_child == 0; }
   bool mac(int a, int b) const {
@@ -413,9 +446,9 @@ struct Traversal {
   void visit(int a, int b) {
     if (leaf_first) {
       if (leaf(a) && leaf(b)) { p2p.emplace_back(a, b); return; }
-      if (mac(a, b)) { m2l.emplace_back(a, b); return; }
+      if (mac(a, b)) { accepted(a, b); return; }
     } else {
-      if (mac(a, b)) { m2l.emplace_back(a, b); return; }
+      if (mac(a, b)) { accepted(a, b); return; }
       if (leaf(a) && leaf(b)) { p2p.emplace_back(a, b); return; }
     }
     const Cell &A = tr.cells[a], &B = tr.cells[b];
@@ -447,12 +480,13 @@ void to_csr(std::vector<std::pair<int32_t, int32_t>> &pairs, int64_t n_rows,
   for (int64_t r = 0; r < n_rows; ++r) ptr[r + 1] += ptr[r];
 }
 
-void traverse(const Tree &tr, double theta, bool leaf_first, Lists &ls) {
+void traverse(const Tree &tr, double theta, bool leaf_first, int m2p_max, Lists &ls) {
   ls.n_rows = (int64_t)tr.cells.size();
-  Traversal tv{tr, theta, leaf_first, {}, {}};
+  Traversal tv{tr, theta, leaf_first, m2p_max, {}, {}, {}};
   if (!tr.cells.empty()) tv.visit(0, 0);
   to_csr(tv.p2p, ls.n_rows, ls.p2p_ptr, ls.p2p_col);
   to_csr(tv.m2l, ls.n_rows, ls.m2l_ptr, ls.m2l_col);
+  to_csr(tv.m2p, ls.n_rows, ls.m2p_ptr, ls.m2p_col);
 }
 
 // Upward pass: P2M on every leaf, then M2M from the deepest level upwards.
@@ -500,7 +534,18 @@ int oracle_build(const double *xyz, int64_t n, int ncrit, double theta, int leaf
   if (n < 0 || ncrit < 1 || !(theta > 0.0)) return -1;
   oracle_fmm *o = new oracle_fmm;
   build_tree(xyz, n, ncrit, o->tree);
-  traverse(o->tree, theta, leaf_first != 0, o->lists);
+  traverse(o->tree, theta, leaf_first != 0, 0, o->lists);
+  *out = o;
+  return 0;
+}
+
+// The treecode/FMM hybrid lists (m2p_max >= 0; 0 gives oracle_build's lists).
+int oracle_build_hybrid(const double *xyz, int64_t n, int ncrit, double theta, int leaf_first,
+                        int m2p_max, oracle_fmm **out) {
+  if (n < 0 || ncrit < 1 || !(theta > 0.0) || m2p_max < 0) return -1;
+  oracle_fmm *o = new oracle_fmm;
+  build_tree(xyz, n, ncrit, o->tree);
+  traverse(o->tree, theta, leaf_first != 0, m2p_max, o->lists);
   *out = o;
   return 0;
 }
@@ -529,14 +574,16 @@ void oracle_tree(const oracle_fmm *o, int32_t *perm, uint64_t *keys, int32_t *le
   }
 }
 
-// kind 0 = P2P, 1 = M2L
+// kind 0 = P2P, 1 = M2L, 2 = M2P
 int64_t oracle_list_nnz(const oracle_fmm *o, int kind) {
-  return (int64_t)(kind == 0 ? o->lists.p2p_col.size() : o->lists.m2l_col.size());
+  const Lists &l = o->lists;
+  return (int64_t)(kind == 0 ? l.p2p_col.size() : kind == 1 ? l.m2l_col.size() : l.m2p_col.size());
 }
 
 void oracle_list(const oracle_fmm *o, int kind, int64_t *row_ptr, int32_t *col) {
-  const auto &p = kind == 0 ? o->lists.p2p_ptr : o->lists.m2l_ptr;
-  const auto &c = kind == 0 ? o->lists.p2p_col : o->lists.m2l_col;
+  const Lists &l = o->lists;
+  const auto &p = kind == 0 ? l.p2p_ptr : kind == 1 ? l.m2l_ptr : l.m2p_ptr;
+  const auto &c = kind == 0 ? l.p2p_col : kind == 1 ? l.m2l_col : l.m2p_col;
   std::copy(p.begin(), p.end(), row_ptr);
   std::copy(c.begin(), c.end(), col);
 }
@@ -555,7 +602,7 @@ void oracle_term_exponents(int p, int32_t *abc) {
 // Full evaluation with charges q (user order).  Outputs in user order:
 // phi[n], grad[n][3].  Optional staged outputs (NULL to skip), in sorted body
 // order / cell order: near_phi, near_grad (P2P only), far_phi, far_grad (L2P
-// only), M[n_cells][T], L_m2l[n_cells][T] (after M2L, before L2L),
+// and, for hybrid lists, M2P), M[n_cells][T], L_m2l[n_cells][T] (after M2L, before L2L),
 // L_all[n_cells][T] (after L2L).
 int oracle_evaluate(const oracle_fmm *o, int p, const double *q, double *phi, double *grad,
                     double *near_phi, double *near_grad, double *far_phi, double *far_grad,
@@ -605,6 +652,10 @@ int oracle_evaluate(const oracle_fmm *o, int p, const double *q, double *phi, do
     for (int64_t i = A.body_begin; i < A.body_begin + A.n_body; ++i) {
       const double xi[3] = {tr.xs[i], tr.ys[i], tr.zs[i]};
       l2p(T, A.X, &L[a * nt], xi, &fphi[i], &fg[3 * i]);
+      for (int64_t e = ls.m2p_ptr[a]; e < ls.m2p_ptr[a + 1]; ++e) {
+        const int b = ls.m2p_col[e];
+        m2p(T, tr.cells[b].X, &M[b * nt], xi, &fphi[i], &fg[3 * i]);
+      }
       for (int64_t e = ls.p2p_ptr[a]; e < ls.p2p_ptr[a + 1]; ++e) {
         const Cell &B = tr.cells[ls.p2p_col[e]];
         int64_t b = B.body_begin;
@@ -672,6 +723,16 @@ void oracle_op_m2l(int p, const double *XA, const double *XB, const double *M, d
   Terms T(p);
   m2l(T, XA, XB, M, L);
 }
+void oracle_op_m2p(int p, const double *XB, const double *M, const double *y, int64_t m,
+                   double *phi, double *grad) {
+  Terms T(p);
+  for (int64_t i = 0; i < m; ++i) {
+    phi[i] = 0.0;
+    grad[3 * i] = grad[3 * i + 1] = grad[3 * i + 2] = 0.0;
+    m2p(T, XB, M, &y[3 * i], &phi[i], &grad[3 * i]);
+  }
+}
+
 void oracle_op_l2l(int p, const double *XP, const double *Xc, const double *LP, double *Lc) {
   Terms T(p);
   l2l(T, XP, Xc, LP, Lc);
@@ -696,6 +757,7 @@ void oracle_op_l2p(int p, const double *XA, const double *L, const double *y, in
 int64_t oracle_evaluate_leaves(const oracle_fmm *o, int p, const double *q, const int32_t *leaves,
                                int64_t n_leaves, int64_t *user_index, double *phi,
                                double *grad) {
+  if (!o->lists.m2p_col.empty()) return -2;  // hybrid lists: oracle_evaluate only
   if (p < 1 || p > 16) return -1;
   const Tree &tr = o->tree;
   const Lists &ls = o->lists;
@@ -765,6 +827,7 @@ void oracle_set_positions(oracle_fmm *o, const double *xyz) {
 // the Hessian through second derivatives of the local expansion.
 int oracle_evaluate_general(const oracle_fmm *o, int p, const double *q, const double *s,
                             const double *v, double *phi, double *grad, double *hv) {
+  if (!o->lists.m2p_col.empty()) return -2;  // hybrid lists: oracle_evaluate only
   if (p < 1 || p > 16 || (s && v)) return -1;
   const Tree &tr = o->tree;
   const Lists &ls = o->lists;

@@ -28,6 +28,8 @@ def _load():
     dbl = ctypes.c_double
     lib.oracle_build.argtypes = [vp, i64, i32, dbl, i32, ctypes.POINTER(vp)]
     lib.oracle_build.restype = i32
+    lib.oracle_build_hybrid.argtypes = [vp, i64, i32, dbl, i32, i32, ctypes.POINTER(vp)]
+    lib.oracle_build_hybrid.restype = i32
     lib.oracle_free.argtypes = [vp]
     lib.oracle_free.restype = None
     lib.oracle_num_cells.argtypes = [vp]
@@ -64,6 +66,7 @@ def _load():
     lib.oracle_op_m2l.argtypes = [i32, vp, vp, vp, vp]
     lib.oracle_op_l2l.argtypes = [i32, vp, vp, vp, vp]
     lib.oracle_op_l2p.argtypes = [i32, vp, vp, vp, i64, vp, vp]
+    lib.oracle_op_m2p.argtypes = [i32, vp, vp, vp, i64, vp, vp]
     for name in ("oracle_op_derivatives", "oracle_op_p2m", "oracle_op_m2m", "oracle_op_m2l",
                  "oracle_op_l2l", "oracle_op_l2p"):
         getattr(lib, name).restype = None
@@ -94,15 +97,21 @@ def term_exponents(p):
 
 
 class OracleFMM:
-    """Tree + interaction lists built by the oracle; evaluate() runs the FP64 FMM."""
+    """Tree + interaction lists built by the oracle; evaluate() runs the FP64 FMM.
+    m2p_max > 0: the treecode/FMM hybrid lists (accepted pairs whose target is
+    a leaf of at most m2p_max bodies go to the M2P list, kind 2)."""
 
-    def __init__(self, xyz, ncrit, theta, leaf_first=False):
+    def __init__(self, xyz, ncrit, theta, leaf_first=False, m2p_max=0):
         lib = _load()
         self.xyz = _f64(xyz, (-1, 3))
         self.n = self.xyz.shape[0]
         h = ctypes.c_void_p()
-        rc = lib.oracle_build(_p(self.xyz), self.n, int(ncrit), float(theta),
-                              1 if leaf_first else 0, ctypes.byref(h))
+        if m2p_max:
+            rc = lib.oracle_build_hybrid(_p(self.xyz), self.n, int(ncrit), float(theta),
+                                         1 if leaf_first else 0, int(m2p_max), ctypes.byref(h))
+        else:
+            rc = lib.oracle_build(_p(self.xyz), self.n, int(ncrit), float(theta),
+                                  1 if leaf_first else 0, ctypes.byref(h))
         if rc != 0:
             raise ValueError("oracle_build failed")
         self._h = h
@@ -277,6 +286,16 @@ def l2l(p, XP, Xc, LP):
     Lc = np.zeros(num_terms(p))
     _load().oracle_op_l2l(p, _p(_f64(XP, (3,))), _p(_f64(Xc, (3,))), _p(_f64(LP)), _p(Lc))
     return Lc
+
+
+def m2p(p, XB, M, y):
+    """Multipole M (order p, about XB) evaluated at the points y: (phi, grad)."""
+    y = _f64(y, (-1, 3))
+    phi = np.zeros(y.shape[0])
+    grad = np.zeros((y.shape[0], 3))
+    _load().oracle_op_m2p(p, _p(_f64(XB, (3,))), _p(_f64(M)), _p(y), y.shape[0], _p(phi),
+                          _p(grad))
+    return phi, grad
 
 
 def l2p(p, XA, L, y):
