@@ -61,7 +61,8 @@ enum fmm_traverse_flags {
   FMM_LEAF_FIRST = 1u /* leaf test first, as printed in Algorithm 4 */
 };
 
-enum fmm_list_kind { FMM_P2P = 0, FMM_M2L = 1 };
+enum fmm_list_kind { FMM_P2P = 0, FMM_M2L = 1, FMM_M2P = 2 };
+enum { FMM_MAX_M2P = 64 }; /* largest m2p_max of fmm_traverse_hybrid */
 
 enum fmm_eval_flags {
   FMM_EVAL_TIMING = 1, /* record per-phase device times (fmm_last_timings) */
@@ -77,7 +78,7 @@ enum fmm_phase {
   FMM_PHASE_P2P = 1,    /* near field */
   FMM_PHASE_P2M = 2,
   FMM_PHASE_M2M = 3,
-  FMM_PHASE_M2L = 4,
+  FMM_PHASE_M2L = 4, /* M2L, and M2P for hybrid lists */
   FMM_PHASE_L2L = 5,
   FMM_PHASE_L2P = 6, /* L2P + near/far combine + scatter to user order */
   FMM_PHASE_TOTAL = 7,
@@ -125,6 +126,7 @@ typedef struct fmm_lists_stats_t {
   int64_t p2p_work_items; /* GPU work items of the P2P kernel (host-built lists: 0 before
                              the first evaluation) */
   int64_t p2p_max_row_sources; /* largest number of source bodies of one target leaf */
+  int64_t m2p_entries; /* cell pairs in the M2P list (hybrid lists; else 0) */
 } fmm_lists_stats_t;
 
 /*
@@ -177,6 +179,22 @@ void fmm_tree_free(fmm_tree *t);
 int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out);
 
 /*
+ * Treecode/FMM hybrid lists: the traversal of fmm_traverse, except that an
+ * accepted pair (A, B) whose target A is a leaf of at most m2p_max bodies goes
+ * to a third list, M2P, instead of M2L: B's multipole is then evaluated
+ * directly at A's bodies (the treecode's kernel, Algorithm 1; the M2L/M2P
+ * choice of the auto-tuned hybrid codes that section 2 of the paper
+ * describes).  The P2P list and the union of M2L and M2P equal fmm_traverse's.
+ *   m2p_max  0..FMM_MAX_M2P; 0 gives fmm_traverse's lists.
+ * M2P uses derivatives of 1/r up to degree p (its gradient keeps one more
+ * degree than L2P's).  The far-field operator is then no longer symmetric, so
+ * fmm_evaluate_backward returns FMM_ESTATE and fmm_evaluate_range FMM_EINVAL
+ * for such lists.  Host only, like fmm_traverse.
+ */
+int fmm_traverse_hybrid(const fmm_tree *t, double theta, unsigned flags, int m2p_max,
+                        fmm_lists **out);
+
+/*
  * The same traversal on the GPU (level-synchronous frontier of cell pairs,
  * same FP64 MAC without FMA contraction, canonical order by a 64-bit radix
  * sort): the lists are identical bit for bit to fmm_traverse's.  Uses the
@@ -192,6 +210,7 @@ int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists 
                      void *stream);
 
 /* CSR view of one list (library-owned host arrays, valid until fmm_lists_free).
+ * kind FMM_P2P, FMM_M2L or FMM_M2P (empty unless the lists are hybrid).
  * nrows = number of cells; row_ptr[nrows+1] int64; col[nnz] int32.  For lists
  * from fmm_traverse_gpu the first call copies them to the host (FMM_EDEVICE
  * or FMM_ENOMEM if that fails). */

@@ -76,6 +76,11 @@ struct DevLists {
   int64_t *m2l_ptr = nullptr, *p2p_ptr = nullptr;
   int32_t *m2l_col = nullptr, *p2p_col = nullptr;
   int64_t p2p_nnz = 0, m2l_nnz = 0;
+  // hybrid lists: M2P CSR and the target leaves that have M2P entries
+  int64_t *m2p_ptr = nullptr;
+  int32_t *m2p_col = nullptr, *m2p_rows = nullptr;
+  int64_t n_m2p_rows = 0;
+  void *m2p_buf = nullptr;  // [n] (phi, grad) of M2P, Morton order; zero where unused
   fmmlib::dev::DevicePlan plan;
   // host copies for target-range evaluations: chunks and first item per leaf
   std::vector<int32_t> leaf_nchunk_host;
@@ -97,10 +102,10 @@ struct DevLists {
   bool have_events = false, timing_valid = false, timed_serial = false;
   void release_scratch() {
     void *ptrs[] = {M, L, Lstage, M64, L64, L64stage, part_s, part_c, tmp_phi, tmp_grad,
-                    vec4, tmp_hv};
+                    vec4, tmp_hv, m2p_buf};
     for (void *p2 : ptrs)
       if (p2) (void)hipFree(p2);
-    M = L = Lstage = part_s = part_c = tmp_phi = tmp_grad = vec4 = tmp_hv = nullptr;
+    M = L = Lstage = part_s = part_c = tmp_phi = tmp_grad = vec4 = tmp_hv = m2p_buf = nullptr;
     M64 = L64 = L64stage = nullptr;
     p = 0;
     prec = -1;
@@ -110,7 +115,7 @@ struct DevLists {
   void release() {
     release_scratch();
     plan.release();
-    void *ptrs[] = {m2l_ptr, m2l_col, p2p_ptr, p2p_col};
+    void *ptrs[] = {m2l_ptr, m2l_col, p2p_ptr, p2p_col, m2p_ptr, m2p_col, m2p_rows};
     for (void *p2 : ptrs)
       if (p2) (void)hipFree(p2);
     if (have_events)
@@ -302,6 +307,15 @@ int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
   dp.release();
   if (int rc = dev_upload(&dv.m2l_ptr, ld.m2l_ptr.data(), ld.m2l_ptr.size())) return rc;
   if (int rc = dev_upload(&dv.m2l_col, ld.m2l_col.data(), ld.m2l_col.size())) return rc;
+  if (!ld.m2p_col.empty()) {
+    std::vector<int32_t> rows;
+    for (int64_t c = 0; c < ld.n_rows; ++c)
+      if (ld.m2p_ptr[c + 1] > ld.m2p_ptr[c]) rows.push_back((int32_t)c);
+    if (int rc = dev_upload(&dv.m2p_ptr, ld.m2p_ptr.data(), ld.m2p_ptr.size())) return rc;
+    if (int rc = dev_upload(&dv.m2p_col, ld.m2p_col.data(), ld.m2p_col.size())) return rc;
+    if (int rc = dev_upload(&dv.m2p_rows, rows.data(), rows.size())) return rc;
+    dv.n_m2p_rows = (int64_t)rows.size();
+  }
   if (int rc = dev_upload(&dp.items, pl.items.data(), pl.items.size())) return rc;
   if (int rc = dev_upload(&dp.run_body, pl.run_body.data(), pl.run_body.size())) return rc;
   if (int rc = dev_upload(&dp.run_prefix, pl.run_prefix.data(), pl.run_prefix.size())) return rc;
@@ -334,6 +348,7 @@ int ensure_lists_host(fmm_lists *l) {
   try {
     ld.p2p_ptr.assign(nr + 1, 0);
     ld.m2l_ptr.assign(nr + 1, 0);
+    ld.m2p_ptr.assign(nr + 1, 0);  // the GPU traversal builds no M2P list
     ld.p2p_col.resize(dv.p2p_nnz);
     ld.m2l_col.resize(dv.m2l_nnz);
   } catch (const std::bad_alloc &) {
@@ -414,6 +429,11 @@ int ensure_scratch(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o) {
   HIP_TRY(hipMalloc(&dv.tmp_grad, std::max<int64_t>(1, n) * 3 * real));
   HIP_TRY(hipMalloc(&dv.vec4, std::max<int64_t>(1, n) * 4 * real));
   HIP_TRY(hipMalloc(&dv.tmp_hv, std::max<int64_t>(1, n) * 3 * real));
+  if (dv.n_m2p_rows > 0) {
+    // bodies of leaves without M2P entries are never written: zero once
+    HIP_TRY(hipMalloc(&dv.m2p_buf, std::max<int64_t>(1, n) * 4 * real));
+    HIP_TRY(hipMemset(dv.m2p_buf, 0, std::max<int64_t>(1, n) * 4 * real));
+  }
   dv.p = o->p;
   dv.prec = o->precision;
   dv.n_top = n_top;
@@ -577,6 +597,9 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
         if (int rc = m2l_cells(rcells.cell_lo[lev], rcells.cell_hi[lev])) return rc;
     }
   }
+  if (dv.n_m2p_rows > 0)
+    LAUNCH_TRY(D::m2p(p, fp64, dv.n_m2p_rows, dv.m2p_rows, dv.m2p_ptr, dv.m2p_col, dt.body_begin,
+                      dt.n_body, geo, dv.M, bodies, dv.m2p_buf, stream));
   if (o->flags & FMM_EVAL_KEEP_STAGES) {
     HIP_TRY(hipMemcpyAsync(dv.Lstage, dv.L, (size_t)td.n_cells() * S * real,
                            hipMemcpyDeviceToDevice, s));
@@ -603,7 +626,8 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   if (int rc = mark(6, s)) return rc;
   LAUNCH_TRY(D::l2p_combine(p, fp64, mode, ranged ? rb0 : 0, ranged ? rb1 : td.n, pl.body_leaf, pl.leaf_cell, pl.leaf_pbase,
                             pl.leaf_nchunk, dt.body_begin, dt.n_body, geo, dv.L, bodies, vec,
-                            dv.part_s, dv.part_c, dt.perm, phi, grad, stream));
+                            dv.part_s, dv.part_c, dv.n_m2p_rows > 0 ? dv.m2p_buf : nullptr,
+                            dt.perm, phi, grad, stream));
   if (int rc = mark(7, s)) return rc;
   dv.timed_serial = !overlap;
   dv.timing_valid = timing;
@@ -799,17 +823,26 @@ void fmm_tree_free(fmm_tree *t) {
   delete t;
 }
 
-int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out) {
+}  // extern "C"
+
+namespace {
+
+int traverse_host(const fmm_tree *t, double theta, unsigned flags, int m2p_max, fmm_lists **out,
+                  const char *fn) {
   if (!t || !out) {
-    set_error("fmm_traverse: NULL argument");
+    set_error(std::string(fn) + ": NULL argument");
     return FMM_EINVAL;
   }
   if (!(theta > 0.0 && theta < 1.0)) {
-    set_error("fmm_traverse: theta must be in (0, 1)");
+    set_error(std::string(fn) + ": theta must be in (0, 1)");
     return FMM_EINVAL;
   }
   if (flags & ~(unsigned)FMM_LEAF_FIRST) {
-    set_error("fmm_traverse: unknown flags");
+    set_error(std::string(fn) + ": unknown flags");
+    return FMM_EINVAL;
+  }
+  if (m2p_max < 0 || m2p_max > FMM_MAX_M2P) {
+    set_error(std::string(fn) + ": m2p_max must be in 0..64");
     return FMM_EINVAL;
   }
   *out = nullptr;
@@ -817,19 +850,32 @@ int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **ou
   fmmlib::reset_alloc_checkpoints();
   try {
     l = new fmm_lists();
-    fmmlib::dual_traverse(t->data, theta, (flags & FMM_LEAF_FIRST) != 0, l->data);
+    fmmlib::dual_traverse(t->data, theta, (flags & FMM_LEAF_FIRST) != 0, m2p_max, l->data);
   } catch (const std::bad_alloc &) {
     delete l;
-    set_error("fmm_traverse: out of host memory");
+    set_error(std::string(fn) + ": out of host memory");
     return FMM_ENOMEM;
   }
   if (std::getenv("FMM_LOG"))
-    std::fprintf(stderr, "[fmm] lists: theta=%g %s p2p=%lld m2l=%lld pairs=%lld\n", theta,
-                 (flags & FMM_LEAF_FIRST) ? "leaf-first" : "mac-first",
+    std::fprintf(stderr, "[fmm] lists: theta=%g %s p2p=%lld m2l=%lld m2p=%lld pairs=%lld\n",
+                 theta, (flags & FMM_LEAF_FIRST) ? "leaf-first" : "mac-first",
                  (long long)l->data.p2p_col.size(), (long long)l->data.m2l_col.size(),
-                 (long long)l->data.p2p_pairs);
+                 (long long)l->data.m2p_col.size(), (long long)l->data.p2p_pairs);
   *out = l;
   return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out) {
+  return traverse_host(t, theta, flags, 0, out, "fmm_traverse");
+}
+
+int fmm_traverse_hybrid(const fmm_tree *t, double theta, unsigned flags, int m2p_max,
+                        fmm_lists **out) {
+  return traverse_host(t, theta, flags, m2p_max, out, "fmm_traverse_hybrid");
 }
 
 int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out,
@@ -922,16 +968,24 @@ int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists 
 
 int fmm_lists_view(const fmm_lists *l, int kind, const int64_t **row_ptr, const int32_t **col,
                    int64_t *nrows, int64_t *nnz) {
-  if (!l || !row_ptr || !col || !nrows || !nnz || (kind != FMM_P2P && kind != FMM_M2L)) {
+  if (!l || !row_ptr || !col || !nrows || !nnz ||
+      (kind != FMM_P2P && kind != FMM_M2L && kind != FMM_M2P)) {
     set_error("fmm_lists_view: bad argument");
     return FMM_EINVAL;
   }
   if (int rc = ensure_lists_host(const_cast<fmm_lists *>(l))) return rc;
   const fmmlib::ListData &d = l->data;
-  *row_ptr = kind == FMM_P2P ? d.p2p_ptr.data() : d.m2l_ptr.data();
-  *col = kind == FMM_P2P ? d.p2p_col.data() : d.m2l_col.data();
+  if (kind == FMM_M2P && d.m2p_ptr.empty()) {
+    set_error("fmm_lists_view: no M2P list");
+    return FMM_ESTATE;
+  }
+  *row_ptr = kind == FMM_P2P ? d.p2p_ptr.data() : kind == FMM_M2L ? d.m2l_ptr.data()
+                                                                  : d.m2p_ptr.data();
+  *col = kind == FMM_P2P ? d.p2p_col.data() : kind == FMM_M2L ? d.m2l_col.data()
+                                                              : d.m2p_col.data();
   *nrows = d.n_rows;
-  *nnz = (int64_t)(kind == FMM_P2P ? d.p2p_col.size() : d.m2l_col.size());
+  *nnz = (int64_t)(kind == FMM_P2P ? d.p2p_col.size()
+                                   : kind == FMM_M2L ? d.m2l_col.size() : d.m2p_col.size());
   return FMM_OK;
 }
 
@@ -945,6 +999,7 @@ int fmm_lists_stats(const fmm_lists *l, fmm_lists_stats_t *s) {
   s->m2l_entries = host ? (int64_t)l->data.m2l_col.size() : l->dev.m2l_nnz;
   s->p2p_pairs = l->data.p2p_pairs;
   s->p2p_work_items = l->dev.plan.n_items;
+  s->m2p_entries = (int64_t)l->data.m2p_col.size();
   s->p2p_max_row_sources = l->data.max_row_sources;
   return FMM_OK;
 }
@@ -978,6 +1033,10 @@ int fmm_evaluate_range(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opt
                        void *grad_dev, void *stream) {
   if (int rc = check_pair(t, l)) return rc;
   if (int rc = check_opts(o)) return rc;
+  if (!l->data.m2p_col.empty()) {
+    set_error("fmm_evaluate_range: hybrid (M2P) lists are not supported");
+    return FMM_EINVAL;
+  }
   fmm_tree *tt = const_cast<fmm_tree *>(t);
   const int64_t n = t->data.n;
   if (body_begin < 0 || body_end < body_begin || body_end > n) {
@@ -1038,6 +1097,11 @@ int fmm_evaluate_backward(const fmm_tree *t, const fmm_lists *l, const fmm_eval_
                           const void *v_dev, void *dq_dev, void *dx_dev, void *stream) {
   if (int rc = check_pair(t, l)) return rc;
   if (int rc = check_opts(o)) return rc;
+  if (!l->data.m2p_col.empty()) {
+    // M2P breaks the symmetry of the far-field operator that the backward uses
+    set_error("fmm_evaluate_backward: hybrid (M2P) lists are not supported");
+    return FMM_ESTATE;
+  }
   if (t->data.n == 0) return FMM_OK;
   if ((!w_dev && !v_dev) || (dx_dev && (!q_dev || !grad_q_dev))) {
     set_error("fmm_evaluate_backward: w or v is required; dx needs q and grad_q");

@@ -224,6 +224,79 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 }
 
 // ----------------------------------------------------------------------------
+// M2P (treecode/FMM hybrid): one 64-lane wave per target leaf with M2P
+// entries (at most 64 bodies).  The lanes form G = 64 / nA groups of nA lanes;
+// lane (g, t) evaluates the entries g, g + G, ... at body t with derivatives
+// of 1/r up to degree p; the G partials of a body are summed in group order.
+// Output: (phi, grad) per body in Morton order.
+// ----------------------------------------------------------------------------
+template <int P, typename Real>
+__global__ __launch_bounds__(64) void m2p_kernel(const int32_t *__restrict__ rows,
+                                                 const int64_t *__restrict__ ptr,
+                                                 const int32_t *__restrict__ col,
+                                                 const int32_t *__restrict__ cell_body_begin,
+                                                 const int32_t *__restrict__ cell_n_body,
+                                                 const double4 *__restrict__ geo,
+                                                 const Real *__restrict__ M,
+                                                 const typename Vec<Real>::V4 *__restrict__ bodies,
+                                                 typename Vec<Real>::V4 *__restrict__ out) {
+  using V4 = typename Vec<Real>::V4;
+  constexpr int T = nterms(P), T1 = nterms(P + 1), S = pad4(T);
+  __shared__ V4 red[64];
+  const int A = rows[blockIdx.x];
+  const int nA = cell_n_body[A];
+  const int G = 64 / nA;
+  const int lane = threadIdx.x;
+  const int g = lane / nA, t = lane - g * nA;
+  Real f = Real(0), gx = Real(0), gy = Real(0), gz = Real(0);
+  if (g < G) {
+    const V4 b = bodies[cell_body_begin[A] + t];
+    for (int64_t e = ptr[A] + g; e < ptr[A + 1]; e += G) {
+      const int B = col[e];
+      const double4 gb = geo[B];
+      Real D[T1];
+      derivatives<P + 1, Real>(Real((double)b.x - gb.x), Real((double)b.y - gb.y),
+                               Real((double)b.z - gb.z), D);
+      Real mb[T];
+      load_row<T>(M + (int64_t)B * S, mb);
+      // terms are ordered by degree, so term n has the same index among the
+      // terms of order P + 1
+      static_for<T>([&](auto I) {
+        constexpr int n = decltype(I)::value;
+        constexpr int ex = kBasis<P>.ex[n], ey = kBasis<P>.ey[n], ez = kBasis<P>.ez[n];
+        f += mb[n] * D[n];
+        gx += mb[n] * D[term_index(P + 1, ex + 1, ey, ez)];
+        gy += mb[n] * D[term_index(P + 1, ex, ey + 1, ez)];
+        gz += mb[n] * D[term_index(P + 1, ex, ey, ez + 1)];
+      });
+    }
+  }
+  V4 v;
+  v.x = f;
+  v.y = gx;
+  v.z = gy;
+  v.w = gz;
+  red[lane] = v;
+  __syncthreads();
+  if (lane < nA) {
+    Real s[4] = {Real(0), Real(0), Real(0), Real(0)};
+    for (int k = 0; k < G; ++k) {
+      const V4 r = red[k * nA + lane];
+      s[0] += r.x;
+      s[1] += r.y;
+      s[2] += r.z;
+      s[3] += r.w;
+    }
+    V4 o;
+    o.x = s[0];
+    o.y = s[1];
+    o.z = s[2];
+    o.w = s[3];
+    out[cell_body_begin[A] + lane] = o;
+  }
+}
+
+// ----------------------------------------------------------------------------
 // L2L: one thread per child cell of one level; the child pulls from its
 // parent.  PT: parent's storage type, AT: arithmetic type, CT: child's.
 // ----------------------------------------------------------------------------
@@ -272,7 +345,8 @@ __global__ __launch_bounds__(256) void l2p_combine_kernel(
     const typename Vec<Real>::V4 *__restrict__ bodies,
     const typename Vec<Real>::V4 *__restrict__ tvec,
     const typename Vec<Real>::V4 *__restrict__ part_s,
-    const typename Vec<Real>::V4 *__restrict__ part_c, const int32_t *__restrict__ perm,
+    const typename Vec<Real>::V4 *__restrict__ part_c,
+    const typename Vec<Real>::V4 *__restrict__ m2p_in, const int32_t *__restrict__ perm,
     Real *__restrict__ phi_out, Real *__restrict__ grad_out) {
   using V4 = typename Vec<Real>::V4;
   constexpr int T = nterms(P), S = pad4(T);
@@ -338,6 +412,13 @@ __global__ __launch_bounds__(256) void l2p_combine_kernel(
 #pragma unroll
       for (int k = 0; k < 4; ++k) s4[k] += vs[k];
     }
+  }
+  if (m2p_in) {  // hybrid lists: the M2P part of the far field
+    const V4 mp = m2p_in[i];
+    f += mp.x;
+    gx += mp.y;
+    gy += mp.z;
+    gz += mp.w;
   }
   const int64_t u = perm[i];
   if (phi_out) phi_out[u] = (s4[0] - c4[0]) + f;
@@ -426,6 +507,25 @@ int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
   });
 }
 
+int m2p(int p, bool fp64, int64_t n_rows, const int32_t *rows, const int64_t *ptr,
+        const int32_t *col, const int32_t *cell_body_begin, const int32_t *cell_n_body,
+        const double *geo, const void *M, const void *bodies, void *out, void *stream) {
+  if (n_rows <= 0) return 0;
+  const unsigned G = (unsigned)n_rows;
+  const double4 *g = (const double4 *)geo;
+  return with_p(p, [&](auto PC) {
+    constexpr int PP = decltype(PC)::value;
+    if (fp64)
+      m2p_kernel<PP, double><<<G, 64, 0, S_(stream)>>>(rows, ptr, col, cell_body_begin,
+                                                       cell_n_body, g, (const double *)M,
+                                                       (const double4 *)bodies, (double4 *)out);
+    else
+      m2p_kernel<PP, float><<<G, 64, 0, S_(stream)>>>(rows, ptr, col, cell_body_begin,
+                                                      cell_n_body, g, (const float *)M,
+                                                      (const float4 *)bodies, (float4 *)out);
+  });
+}
+
 int l2l(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *parent, const double *geo,
         void *L, double *L64, bool parent_fp64, bool child_fp64, void *stream) {
   if (c1 <= c0) return 0;
@@ -460,20 +560,22 @@ void launch_l2p(unsigned nb, hipStream_t st, int64_t i0, int64_t i1, const int32
                 const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
                 const int32_t *cell_body_begin, const int32_t *cell_n_body, const double4 *g,
                 const void *L, const void *bodies, const void *tvec, const void *part_s,
-                const void *part_c, const int32_t *perm, void *phi, void *grad) {
+                const void *part_c, const void *m2p_in, const int32_t *perm, void *phi,
+                void *grad) {
   using V4 = typename Vec<Real>::V4;
   constexpr bool kahan = std::is_same<Real, float>::value;
   l2p_combine_kernel<PP, Real, kahan, HESS><<<nb, 256, 0, st>>>(
       i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk, cell_body_begin, cell_n_body, g,
       (const Real *)L, (const V4 *)bodies, (const V4 *)tvec, (const V4 *)part_s,
-      (const V4 *)part_c, perm, (Real *)phi, (Real *)grad);
+      (const V4 *)part_c, (const V4 *)m2p_in, perm, (Real *)phi, (Real *)grad);
 }
 
 int l2p_combine(int p, bool fp64, int mode, int64_t i0, int64_t i1, const int32_t *body_leaf,
                 const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
                 const int32_t *cell_body_begin, const int32_t *cell_n_body, const double *geo,
                 const void *L, const void *bodies, const void *tvec, const void *part_s,
-                const void *part_c, const int32_t *perm, void *phi, void *grad, void *stream) {
+                const void *part_c, const void *m2p_in, const int32_t *perm, void *phi,
+                void *grad, void *stream) {
   if (i1 <= i0) return 0;
   const unsigned nb = blocks_for(i1 - i0, 256);
   const double4 *g = (const double4 *)geo;
@@ -484,19 +586,19 @@ int l2p_combine(int p, bool fp64, int mode, int64_t i0, int64_t i1, const int32_
     if (fp64 && hess)
       launch_l2p<PP, double, true>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                    cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
-                                   nullptr, perm, nullptr, grad);
+                                   nullptr, m2p_in, perm, nullptr, grad);
     else if (fp64)
       launch_l2p<PP, double, false>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                     cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
-                                    nullptr, perm, phi, grad);
+                                    nullptr, m2p_in, perm, phi, grad);
     else if (hess)
       launch_l2p<PP, float, true>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                   cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
-                                  part_c, perm, nullptr, grad);
+                                  part_c, m2p_in, perm, nullptr, grad);
     else
       launch_l2p<PP, float, false>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                    cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
-                                   part_c, perm, phi, grad);
+                                   part_c, m2p_in, perm, phi, grad);
   });
 }
 

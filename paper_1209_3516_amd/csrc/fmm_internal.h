@@ -39,6 +39,11 @@ struct ListData {
   int64_t n_rows = 0;
   std::vector<int64_t> p2p_ptr, m2l_ptr;
   std::vector<int32_t> p2p_col, m2l_col;
+  // treecode/FMM hybrid: accepted pairs whose target is a leaf of at most
+  // m2p_max bodies (empty when m2p_max == 0)
+  int m2p_max = 0;
+  std::vector<int64_t> m2p_ptr;
+  std::vector<int32_t> m2p_col;
   int64_t p2p_pairs = 0;
   int64_t max_row_sources = 0;
 };
@@ -86,7 +91,7 @@ void reset_alloc_checkpoints();
 constexpr int kP2PChunkSources = 8192;
 
 int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string &err);
-void dual_traverse(const TreeData &t, double theta, bool leaf_first, ListData &l);
+void dual_traverse(const TreeData &t, double theta, bool leaf_first, int m2p_max, ListData &l);
 // p2p_pairs and max_row_sources of finished lists.
 void list_statistics(const TreeData &t, ListData &l);
 void build_p2p_plan(const TreeData &t, const ListData &l, P2PPlan &plan);

@@ -63,12 +63,21 @@ int copy_top_locals(int p, int64_t n_top, const double *L64, float *L, void *str
 
 // kHessVec: tvec holds the per-target vectors (Morton order) and grad receives
 // H v; phi is not written.
-// Bodies [i0, i1) (Morton positions).
+// Bodies [i0, i1) (Morton positions).  m2p_in: [n] (phi, grad) from m2p(),
+// added to the far field, or NULL.
 int l2p_combine(int p, bool fp64, int mode, int64_t i0, int64_t i1, const int32_t *body_leaf,
                 const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
                 const int32_t *cell_body_begin, const int32_t *cell_n_body, const double *geo,
                 const void *L, const void *bodies, const void *tvec, const void *part_s,
-                const void *part_c, const int32_t *perm, void *phi, void *grad, void *stream);
+                const void *part_c, const void *m2p_in, const int32_t *perm, void *phi,
+                void *grad, void *stream);
+
+// M2P for the target leaves rows[0..n_rows) (each at most 64 bodies) over the
+// M2P CSR list: out[b] = (phi, grad) of body b (Morton order) from the
+// multipoles of the row's source cells.
+int m2p(int p, bool fp64, int64_t n_rows, const int32_t *rows, const int64_t *ptr,
+        const int32_t *col, const int32_t *cell_body_begin, const int32_t *cell_n_body,
+        const double *geo, const void *M, const void *bodies, void *out, void *stream);
 
 // dx = w * grad_q + q * grad_w (+ hv if not NULL), user order.
 int backward_combine(bool fp64, int64_t n, const void *q, const void *w, const void *grad_q,

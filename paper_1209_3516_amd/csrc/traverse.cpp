@@ -11,7 +11,9 @@
 //  * otherwise a self pair splits into all child pairs, a pair of distinct
 //    cells splits the cell with the larger radius (equal: lower number), and
 //    a leaf is never split (the other cell is);
-//  * the traversal starts by visiting (root, root).
+//  * the traversal starts by visiting (root, root);
+//  * treecode/FMM hybrid (m2p_max > 0): an accepted pair whose target is a
+//    leaf of at most m2p_max bodies goes to the M2P list instead of M2L.
 // The set of pairs does not depend on the visiting order, so the frontier is
 // processed in parallel and the lists are then put in canonical CSR order
 // (rows = target cells, sources ascending).
@@ -29,13 +31,14 @@ namespace fmmlib {
 namespace {
 
 struct PairBuf {
-  std::vector<int32_t> p2p_a, p2p_b, m2l_a, m2l_b;
+  std::vector<int32_t> p2p_a, p2p_b, m2l_a, m2l_b, m2p_a, m2p_b;
 };
 
 struct Walker {
   const TreeData &t;
   double theta2;
   bool leaf_first;
+  int m2p_max;  // hybrid: accepted pairs with a leaf target of <= m2p_max bodies -> M2P
 
   bool is_leaf(int32_t c) const { return t.n_child[c] == 0; }
 
@@ -48,13 +51,22 @@ struct Walker {
     return theta2 * d2 > s * s;
   }
 
+  void accepted(int32_t a, int32_t b, PairBuf &out) const {
+    if (is_leaf(a) && t.n_body[a] <= m2p_max) {
+      out.m2p_a.push_back(a);
+      out.m2p_b.push_back(b);
+    } else {
+      out.m2l_a.push_back(a);
+      out.m2l_b.push_back(b);
+    }
+  }
+
   // One step: record the pair, or push the pairs it splits into.
   template <class Push>
   void step(int32_t a, int32_t b, PairBuf &out, Push push) const {
     const bool both_leaves = is_leaf(a) && is_leaf(b);
     if (!leaf_first && accept(a, b)) {
-      out.m2l_a.push_back(a);
-      out.m2l_b.push_back(b);
+      accepted(a, b, out);
       return;
     }
     if (both_leaves) {
@@ -63,8 +75,7 @@ struct Walker {
       return;
     }
     if (leaf_first && accept(a, b)) {
-      out.m2l_a.push_back(a);
-      out.m2l_b.push_back(b);
+      accepted(a, b, out);
       return;
     }
     if (a == b) {
@@ -85,19 +96,26 @@ struct Walker {
   }
 };
 
-void to_csr(const std::vector<PairBuf> &bufs, bool m2l, int64_t n_rows, std::vector<int64_t> &ptr,
+// kind: 0 P2P, 1 M2L, 2 M2P
+void to_csr(const std::vector<PairBuf> &bufs, int kind, int64_t n_rows, std::vector<int64_t> &ptr,
             std::vector<int32_t> &col) {
+  auto rows_of = [&](const PairBuf &b) -> const std::vector<int32_t> & {
+    return kind == 0 ? b.p2p_a : kind == 1 ? b.m2l_a : b.m2p_a;
+  };
+  auto cols_of = [&](const PairBuf &b) -> const std::vector<int32_t> & {
+    return kind == 0 ? b.p2p_b : kind == 1 ? b.m2l_b : b.m2p_b;
+  };
   ptr.assign(n_rows + 1, 0);
   for (const auto &b : bufs) {
-    const auto &ra = m2l ? b.m2l_a : b.p2p_a;
+    const auto &ra = rows_of(b);
     for (int32_t a : ra) ptr[a + 1]++;
   }
   for (int64_t r = 0; r < n_rows; ++r) ptr[r + 1] += ptr[r];
   col.resize(ptr[n_rows]);
   std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
   for (const auto &b : bufs) {
-    const auto &ra = m2l ? b.m2l_a : b.p2p_a;
-    const auto &rb = m2l ? b.m2l_b : b.p2p_b;
+    const auto &ra = rows_of(b);
+    const auto &rb = cols_of(b);
     for (size_t i = 0; i < ra.size(); ++i) col[fill[ra[i]]++] = rb[i];
   }
 #pragma omp parallel for schedule(dynamic, 256)
@@ -106,12 +124,13 @@ void to_csr(const std::vector<PairBuf> &bufs, bool m2l, int64_t n_rows, std::vec
 
 }  // namespace
 
-void dual_traverse(const TreeData &t, double theta, bool leaf_first, ListData &l) {
+void dual_traverse(const TreeData &t, double theta, bool leaf_first, int m2p_max, ListData &l) {
   l.tree_id = t.id;
   l.theta = theta;
   l.flags = leaf_first ? FMM_LEAF_FIRST : FMM_MAC_FIRST;
   l.n_rows = t.n_cells();
-  Walker w{t, theta * theta, leaf_first};
+  l.m2p_max = m2p_max;
+  Walker w{t, theta * theta, leaf_first, m2p_max};
 
   int nthreads = 1;
 #ifdef _OPENMP
@@ -151,9 +170,10 @@ void dual_traverse(const TreeData &t, double theta, bool leaf_first, ListData &l
     }
   }
   alloc_checkpoint();
-  to_csr(bufs, false, l.n_rows, l.p2p_ptr, l.p2p_col);
+  to_csr(bufs, 0, l.n_rows, l.p2p_ptr, l.p2p_col);
   alloc_checkpoint();
-  to_csr(bufs, true, l.n_rows, l.m2l_ptr, l.m2l_col);
+  to_csr(bufs, 1, l.n_rows, l.m2l_ptr, l.m2l_col);
+  to_csr(bufs, 2, l.n_rows, l.m2p_ptr, l.m2p_col);
   list_statistics(t, l);
 }
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfmm.so")
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ESTATE = 0, -1, -2, -3, -4
 FMM_MIXED, FMM_FP64 = 0, 1
 FMM_MAC_FIRST, FMM_LEAF_FIRST = 0, 1
-FMM_P2P, FMM_M2L = 0, 1
+FMM_P2P, FMM_M2L, FMM_M2P = 0, 1, 2
 FMM_EVAL_TIMING, FMM_EVAL_KEEP_STAGES, FMM_EVAL_SERIAL = 1, 2, 4
 PHASES = ("gather", "p2p", "p2m", "m2m", "m2l", "l2l", "l2p", "total")
 
@@ -52,7 +52,7 @@ class _TreeView(ctypes.Structure):
 class _ListStats(ctypes.Structure):
     _fields_ = [("p2p_entries", ctypes.c_int64), ("m2l_entries", ctypes.c_int64),
                 ("p2p_pairs", ctypes.c_int64), ("p2p_work_items", ctypes.c_int64),
-                ("p2p_max_row_sources", ctypes.c_int64)]
+                ("p2p_max_row_sources", ctypes.c_int64), ("m2p_entries", ctypes.c_int64)]
 
 
 EXPORTS = ("fmm_tree_build", "fmm_tree_set_positions", "fmm_tree_view", "fmm_tree_free",
@@ -60,7 +60,7 @@ EXPORTS = ("fmm_tree_build", "fmm_tree_set_positions", "fmm_tree_view", "fmm_tre
            "fmm_evaluate", "fmm_evaluate_backward", "fmm_direct", "fmm_last_timings",
            "fmm_last_error", "fmm_num_terms", "fmm_copy_expansions", "fmm_term_exponents",
            "fmm_traverse_gpu", "fmm_tree_build_gpu", "fmm_evaluate_range",
-           "fmm_partition_targets")
+           "fmm_partition_targets", "fmm_traverse_hybrid")
 
 _lib = None
 
@@ -84,6 +84,7 @@ def lib():
         "fmm_tree_free": ([vp], None),
         "fmm_traverse": ([vp, dbl, u32, ctypes.POINTER(vp)], i32),
         "fmm_traverse_gpu": ([vp, dbl, u32, ctypes.POINTER(vp), vp], i32),
+        "fmm_traverse_hybrid": ([vp, dbl, u32, i32, ctypes.POINTER(vp)], i32),
         "fmm_tree_build_gpu": ([vp, i64, i32, ctypes.POINTER(vp), vp], i32),
         "fmm_lists_view": ([vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                             ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
@@ -216,12 +217,19 @@ class Tree:
 
 class Lists:
     """P2P and M2L interaction lists from the dual tree traversal, on the host
-    or (device=True) on the GPU; both give identical lists."""
+    or (device=True) on the GPU; both give identical lists.  m2p_max > 0: the
+    treecode/FMM hybrid (host only), accepted pairs whose target is a leaf of
+    at most m2p_max bodies go to an M2P list."""
 
-    def __init__(self, tree, theta, leaf_first=False, device=False):
+    def __init__(self, tree, theta, leaf_first=False, device=False, m2p_max=0):
         h = ctypes.c_void_p()
         flags = FMM_LEAF_FIRST if leaf_first else FMM_MAC_FIRST
-        if device:
+        if m2p_max:
+            if device:
+                raise ValueError("hybrid (M2P) lists are built on the host only")
+            _check(lib().fmm_traverse_hybrid(tree._h, float(theta), flags, int(m2p_max),
+                                             ctypes.byref(h)))
+        elif device:
             _check(lib().fmm_traverse_gpu(tree._h, float(theta), flags, ctypes.byref(h),
                                           _stream()))
         else:

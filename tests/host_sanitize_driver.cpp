@@ -28,7 +28,7 @@ static int run_case(const std::vector<double> &xyz, int ncrit, double theta, boo
   if (build_tree(xyz.data(), (int64_t)xyz.size() / 3, ncrit, t, err) != 0) return 1;
   ListData l;
   reset_alloc_checkpoints();
-  dual_traverse(t, theta, leaf_first, l);
+  dual_traverse(t, theta, leaf_first, 0, l);
   P2PPlan plan;
   build_p2p_plan(t, l, plan);
   // every body has exactly one leaf; every item covers valid ranges
