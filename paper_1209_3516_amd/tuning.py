@@ -1,4 +1,5 @@
-"""Accuracy-driven choice of the opening angle theta (section 3.2, Table 4).
+"""Accuracy-driven choice of the opening angle theta (section 3.2, Table 4), and
+auto-tuning of the bodies per leaf and of the M2L/M2P choice.
 
 For a given order p the paper searches for the largest theta whose FMM result
 meets a target relative L2 error of the force against a direct sum.  The same
@@ -100,3 +101,77 @@ def largest_theta(problem, p, target, ncrit, metric="e_force", lo=0.02, hi=0.98,
         else:
             b = mid
     return best
+
+
+def autotune(x, q, p, theta, ncrits=(16, 24, 32, 48, 64, 96, 128), m2p_values=(0, 2, 4, 8),
+             n_targets=1000, reps=5, device="cuda:0"):
+    """Time the evaluation for every (ncrit, m2p_max) and return the fastest,
+    with the table of all options (the auto-tuning of the hybrid codes that the
+    paper's section 2 describes: bodies per leaf trades P2P against M2L work,
+    and M2P replaces M2L for small target leaves).  Times are device times of a
+    warm evaluation (median of `reps`); errors are against the FP64 direct sum
+    on `n_targets` sampled targets.  m2p_max = 0 uses the GPU-built lists."""
+    import torch
+
+    from . import workloads as W
+
+    n = x.shape[0]
+    tg = W.sample_targets(n, min(n_targets, n))
+    xd = torch.tensor(x, device=device)
+    ref = fmm.direct(xd, torch.tensor(q, device=device), torch.tensor(tg, device=device))
+    torch.cuda.synchronize()
+    ref_phi, ref_grad = ref[0].cpu().numpy(), ref[1].cpu().numpy()
+    qt = torch.tensor(q, dtype=torch.float32, device=device)
+    rows = []
+    for ncrit in ncrits:
+        tree = fmm.Tree.from_device(xd, ncrit)
+        for m in m2p_values:
+            lists = fmm.Lists(tree, theta, device=(m == 0), m2p_max=m)
+            phi, g = fmm.evaluate(tree, lists, qt, p)
+            ts = []
+            for _ in range(reps):
+                fmm.evaluate(tree, lists, qt, p, timing=True, out=(phi, g))
+                ts.append(fmm.last_timings(lists)["total"])
+            torch.cuda.synchronize()
+            e = errors(phi.double().cpu().numpy()[tg], g.double().cpu().numpy()[tg], ref_phi,
+                       ref_grad, q[tg])
+            st = lists.stats()
+            rows.append(dict(ncrit=ncrit, m2p_max=m, eval_ms=float(np.median(ts)),
+                             p2p_pairs=st["p2p_pairs"], m2l_entries=st["m2l_entries"],
+                             m2p_entries=st["m2p_entries"], **e))
+            del lists
+        del tree
+    best = min(rows, key=lambda r: r["eval_ms"])
+    return best, rows
+
+
+def _main():
+    import argparse
+    import json
+    import sys
+
+    from . import workloads as W
+
+    ap = argparse.ArgumentParser(description="auto-tune ncrit and the M2P threshold")
+    ap.add_argument("--config", default="uniform-1e6-p4")
+    ap.add_argument("--json", default=None)
+    args = ap.parse_args()
+    cfg = W.CONFIGS[args.config]
+    x = W.positions(cfg["n"], cfg["dist"])
+    q = W.charges(cfg["n"], cfg["charges"])
+    best, rows = autotune(x, q, cfg["p"], cfg["theta"])
+    print("| ncrit | m2p_max | eval ms | P2P pairs | M2L entries | M2P entries | e_phi | e_grad |")
+    print("|---|---|---|---|---|---|---|---|")
+    for r in rows:
+        mark = " **(fastest)**" if r is best else ""
+        print("| %d | %d | %.3f%s | %d | %d | %d | %.2e | %.2e |" % (
+            r["ncrit"], r["m2p_max"], r["eval_ms"], mark, r["p2p_pairs"], r["m2l_entries"],
+            r["m2p_entries"], r["e_phi"], r["e_grad"]))
+    sys.stdout.flush()
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump(dict(best=best, rows=rows), f, indent=1)
+
+
+if __name__ == "__main__":
+    _main()

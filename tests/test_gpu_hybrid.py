@@ -60,3 +60,16 @@ def test_hybrid_accuracy_against_direct_sum():
                    _rel(g.double().cpu().numpy()[tg], dg))
     print("pure", errs[0], "hybrid", errs[16])
     assert errs[16][0] <= errs[0][0] * 1.05 and errs[16][1] <= errs[0][1] * 1.05
+
+
+def test_autotune_returns_the_fastest_option():
+    from paper_1209_3516_amd import tuning
+
+    x = W.uniform_cube(30_000, seed=61)
+    q = W.charges(30_000, seed=62)
+    best, rows = tuning.autotune(x, q, 4, 0.5, ncrits=(16, 64), m2p_values=(0, 4), reps=3,
+                                 n_targets=200)
+    assert len(rows) == 4 and best["eval_ms"] == min(r["eval_ms"] for r in rows)
+    for r in rows:
+        assert r["e_phi"] < 1e-2 and r["e_grad"] < 1e-2
+        assert (r["m2p_entries"] > 0) == (r["m2p_max"] > 0)
