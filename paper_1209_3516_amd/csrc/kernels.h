@@ -1,5 +1,5 @@
-// Host-side launchers of the gfx950 kernels (implemented in p2p.hip, far.hip
-// and misc.hip).
+// Host-side launchers of the gfx950 kernels (implemented in p2p.hip, far.hip,
+// misc.hip, tree_gpu.hip and plan_gpu.hip).
 // Plain pointers and sizes only; every launcher enqueues on `stream`
 // (a hipStream_t) and returns the hipError_t of the launch as an int.
 #pragma once
