@@ -915,9 +915,15 @@ int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists 
         delete l;
         return rc;
       }
+      if (std::getenv("FMM_LOG"))
+        std::fprintf(stderr, "[fmm] fmm_traverse_gpu: %.2f ms before the traversal\n",
+                     ms_since(t_call));
       const int rc = fmmlib::dev::dual_traverse_gpu(td.n_cells(), tt->dev.geo, tt->dev.child_begin,
                                                     tt->dev.n_child, theta,
                                                     (flags & FMM_LEAF_FIRST) != 0, stream, dl);
+      if (std::getenv("FMM_LOG"))
+        std::fprintf(stderr, "[fmm] fmm_traverse_gpu: %.2f ms after the traversal\n",
+                     ms_since(t_call));
       if (rc != 0) {
         free_dl();
         delete l;

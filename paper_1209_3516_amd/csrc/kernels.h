@@ -120,6 +120,17 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
 constexpr uint64_t kPoolKeepBytes = 4ull << 30;
 int keep_pool_memory();
 
+// Tree builds, traversals and plan builds run on one library-owned
+// non-blocking stream per device (default priority), made to wait for the
+// caller's stream `user` by an event; those calls synchronise it before they
+// return.  Scratch from the pool is then allocated and returned on it rather
+// than on the legacy null stream, whose stream-ordered frees synchronise.
+constexpr int kMaxDevices = 64;
+// The traversal keeps up to this much of its scratch on each device for the
+// next traversal instead of freeing it.
+constexpr size_t kKeepScratchBytes = size_t(2) << 30;
+int build_stream(void *user, void **out);  // *out: the hipStream_t
+
 // P2P work plan on the device (the layout of P2PPlan, see plan.cpp).
 struct PlanLayouts {
   int32_t cfg[65];  // tgt_cfg bits (n_tgt | R << 8 | L << 16 | K << 24) for n_tgt = 0..64

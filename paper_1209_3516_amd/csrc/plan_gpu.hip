@@ -168,7 +168,8 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
                        const int32_t *body_begin, const int32_t *n_body, const int64_t *p2p_ptr,
                        const int32_t *p2p_col, const PlanLayouts &layouts, void *stream,
                        DevicePlan &out) {
-  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipStream_t st;
+  if (int rc = build_stream(stream, reinterpret_cast<void **>(&st))) return rc;
   out = DevicePlan();
   if (n_cells <= 0 || n_leaves <= 0) return 0;
   int32_t *leaf_flag = nullptr, *leaf_of = nullptr, *nruns = nullptr, *nitems = nullptr,

@@ -9,11 +9,14 @@
 // The traversal is level-synchronous: every pair of the current frontier is
 // classified (M2L, P2P or split) independently; exclusive scans place the
 // child pairs of the next frontier and the emitted pairs.  The emitted pairs
-// are sorted as 64-bit keys (target << 32 | source), which is the canonical
-// CSR order (rows = targets, sources ascending).
+// are sorted as integer keys (target << kb | source), kb = bits of a cell
+// number, which is the canonical CSR order (rows = targets, sources
+// ascending); the radix sort looks at the 2 kb low bits only.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -77,14 +80,14 @@ __global__ void dtt_expand(int64_t nf, const int2 *__restrict__ frontier,
                            const int64_t *__restrict__ child_off,
                            const uint64_t *__restrict__ emit_off, int2 *__restrict__ next,
                            uint64_t *__restrict__ p2p_keys, int64_t p2p_base,
-                           uint64_t *__restrict__ m2l_keys, int64_t m2l_base) {
+                           uint64_t *__restrict__ m2l_keys, int64_t m2l_base, int kb) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nf) return;
   const int2 pr = frontier[i];
   const int a = pr.x, b = pr.y;
   int n;
   const int act = classify(a, b, geo, n_child, theta2, leaf_first != 0, &n);
-  const uint64_t key = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
+  const uint64_t key = ((uint64_t)(uint32_t)a << kb) | (uint32_t)b;
   if (act == kActM2L) {
     m2l_keys[m2l_base + (int64_t)(emit_off[i] >> 32)] = key;
   } else if (act == kActP2P) {
@@ -107,10 +110,10 @@ __global__ void dtt_expand(int64_t nf, const int2 *__restrict__ frontier,
 
 // CSR from sorted keys: row_ptr[r] = first key with target >= r.
 __global__ void csr_rows(int64_t n_rows, const uint64_t *__restrict__ keys, int64_t nnz,
-                         int64_t *__restrict__ row_ptr) {
+                         int kb, int64_t *__restrict__ row_ptr) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r > n_rows) return;
-  const uint64_t want = (uint64_t)r << 32;
+  const uint64_t want = (uint64_t)r << kb;
   int64_t lo = 0, hi = nnz;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
@@ -122,9 +125,10 @@ __global__ void csr_rows(int64_t n_rows, const uint64_t *__restrict__ keys, int6
   row_ptr[r] = lo;
 }
 
-__global__ void csr_cols(int64_t nnz, const uint64_t *__restrict__ keys, int32_t *__restrict__ col) {
+__global__ void csr_cols(int64_t nnz, const uint64_t *__restrict__ keys, int kb,
+                         int32_t *__restrict__ col) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nnz) col[i] = (int32_t)(keys[i] & 0xffffffffull);
+  if (i < nnz) col[i] = (int32_t)(keys[i] & ((1ull << kb) - 1));
 }
 
 // Growable scratch buffer from the device's stream-ordered memory pool:
@@ -168,6 +172,29 @@ struct Buf {
 
 }  // namespace
 
+int build_stream(void *user, void **out) {
+  static std::mutex mu;
+  static hipStream_t streams[kMaxDevices] = {};
+  static hipEvent_t events[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> guard(mu);
+  if (!streams[dev]) {
+    // default priority, not synchronised with the legacy null stream
+    e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+    if (e != hipSuccess) return (int)e;
+    e = hipEventCreateWithFlags(&events[dev], hipEventDisableTiming);
+    if (e != hipSuccess) return (int)e;
+  }
+  e = hipEventRecord(events[dev], S_(user));
+  if (e == hipSuccess) e = hipStreamWaitEvent(streams[dev], events[dev], 0);
+  if (e != hipSuccess) return (int)e;
+  *out = (void *)streams[dev];
+  return 0;
+}
+
 int keep_pool_memory() {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -181,18 +208,18 @@ int keep_pool_memory() {
 
 namespace {
 
-int sort_to_csr(uint64_t *keys, int64_t nnz, int64_t n_rows, hipStream_t st, Buf &alt,
+int sort_to_csr(uint64_t *keys, int64_t nnz, int64_t n_rows, int kb, hipStream_t st, Buf &alt,
                 Buf &temp, int64_t *row_ptr_dev, int32_t *col_dev) {
   if (nnz > 0) {
     TRY(alt.reserve(nnz * sizeof(uint64_t), st, false));
     hipcub::DoubleBuffer<uint64_t> db(keys, (uint64_t *)alt.p);
     size_t tb = 0;
-    TRY(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, db, (int)nnz, 0, 64, st));
+    TRY(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, db, (int)nnz, 0, 2 * kb, st));
     TRY(temp.reserve(tb, st, false));
-    TRY(hipcub::DeviceRadixSort::SortKeys(temp.p, tb, db, (int)nnz, 0, 64, st));
+    TRY(hipcub::DeviceRadixSort::SortKeys(temp.p, tb, db, (int)nnz, 0, 2 * kb, st));
     const uint64_t *sorted = db.Current();
-    csr_rows<<<blocks_for(n_rows + 1, 256), 256, 0, st>>>(n_rows, sorted, nnz, row_ptr_dev);
-    csr_cols<<<blocks_for(nnz, 256), 256, 0, st>>>(nnz, sorted, col_dev);
+    csr_rows<<<blocks_for(n_rows + 1, 256), 256, 0, st>>>(n_rows, sorted, nnz, kb, row_ptr_dev);
+    csr_cols<<<blocks_for(nnz, 256), 256, 0, st>>>(nnz, sorted, kb, col_dev);
   } else {
     TRY(hipMemsetAsync(row_ptr_dev, 0, (n_rows + 1) * sizeof(int64_t), st));
   }
@@ -496,17 +523,48 @@ __global__ void narrow_i64(int64_t n, const int64_t *__restrict__ in, int32_t *_
 int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_begin,
                       const int32_t *n_child, double theta, bool leaf_first, void *stream,
                       DeviceLists &out) {
-  if (int rc = keep_pool_memory()) return rc;
-  const hipStream_t st = S_(stream);
-  const bool log = std::getenv("FMM_LOG") != nullptr;
   auto now = [] { return std::chrono::steady_clock::now(); };
+  const auto t_entry = now();
+  if (int rc = keep_pool_memory()) return rc;
+  hipStream_t st;
+  if (int rc = build_stream(stream, reinterpret_cast<void **>(&st))) return rc;
+  const bool log = std::getenv("FMM_LOG") != nullptr;
   const auto t_start = now();
+  if (log)
+    std::fprintf(stderr, "[fmm] gpu traversal: set-up %.2f ms\n",
+                 std::chrono::duration<double, std::milli>(t_start - t_entry).count());
   int n_levels = 0;
   const double theta2 = theta * theta;
   const double4 *g = (const double4 *)geo;
   out = DeviceLists();
   out.n_rows = n_cells;
-  Buf front[2], counts, emit, coff, eoff, temp, p2p, m2l, alt;
+  // bits of a cell number: keys (target << kb | source) need 2 kb <= 64 bits
+  int kb = 1;
+  while (kb < 31 && (int64_t(1) << kb) < n_cells) ++kb;
+  // Scratch of the previous traversal on this device is reused (freeing
+  // large pool blocks costs milliseconds); at most kKeepScratchBytes are
+  // kept between calls.
+  struct Scratch {
+    Buf front[2], counts, emit, coff, eoff, temp, p2p, m2l, alt;
+    size_t bytes() const {
+      return front[0].bytes + front[1].bytes + counts.bytes + emit.bytes + coff.bytes +
+             eoff.bytes + temp.bytes + p2p.bytes + m2l.bytes + alt.bytes;
+    }
+  };
+  // (a heap array that is never destroyed: no HIP call at process exit)
+  static std::mutex cache_mu;
+  static std::unique_ptr<Scratch> *cache = new std::unique_ptr<Scratch>[kMaxDevices];
+  int dev = 0;
+  TRY(hipGetDevice(&dev));
+  std::unique_ptr<Scratch> sc;
+  {
+    std::lock_guard<std::mutex> guard(cache_mu);
+    if (dev >= 0 && dev < kMaxDevices) sc = std::move(cache[dev]);
+  }
+  if (!sc) sc.reset(new Scratch);
+  Buf(&front)[2] = sc->front;
+  Buf &counts = sc->counts, &emit = sc->emit, &coff = sc->coff, &eoff = sc->eoff,
+      &temp = sc->temp, &p2p = sc->p2p, &m2l = sc->m2l, &alt = sc->alt;
   int64_t nf = n_cells > 0 ? 1 : 0, n_p2p = 0, n_m2l = 0;
   TRY(front[0].reserve(sizeof(int2), st, false));
   if (nf) {
@@ -554,7 +612,7 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
     dtt_expand<<<blocks_for(nf, 256), 256, 0, st>>>(
         nf, (const int2 *)front[cur].p, g, n_child, child_begin, theta2, leaf_first,
         (const int64_t *)coff.p, (const uint64_t *)eoff.p, (int2 *)front[1 - cur].p,
-        (uint64_t *)p2p.p, n_p2p, (uint64_t *)m2l.p, n_m2l);
+        (uint64_t *)p2p.p, n_p2p, (uint64_t *)m2l.p, n_m2l, kb);
     TRY(hipGetLastError());
     n_p2p += add_p2p;
     n_m2l += add_m2l;
@@ -569,18 +627,24 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
   TRY(hipMalloc((void **)&out.m2l_col, (n_m2l > 0 ? n_m2l : 1) * sizeof(int32_t)));
   out.p2p_nnz = n_p2p;
   out.m2l_nnz = n_m2l;
-  if (int rc = sort_to_csr((uint64_t *)p2p.p, n_p2p, n_cells, st, alt, temp, out.p2p_ptr,
+  if (int rc = sort_to_csr((uint64_t *)p2p.p, n_p2p, n_cells, kb, st, alt, temp, out.p2p_ptr,
                            out.p2p_col))
     return rc;
-  if (int rc = sort_to_csr((uint64_t *)m2l.p, n_m2l, n_cells, st, alt, temp, out.m2l_ptr,
+  if (int rc = sort_to_csr((uint64_t *)m2l.p, n_m2l, n_cells, kb, st, alt, temp, out.m2l_ptr,
                            out.m2l_col))
     return rc;
   TRY(hipStreamSynchronize(st));
+  const auto t_end = now();
+  if (sc->bytes() <= kKeepScratchBytes && dev >= 0 && dev < kMaxDevices) {
+    std::lock_guard<std::mutex> guard(cache_mu);
+    if (!cache[dev]) cache[dev] = std::move(sc);
+  }
+  sc.reset();
   if (log) {
-    const auto t_end = now();
-    std::fprintf(stderr, "[fmm] gpu traversal: %d steps %.2f ms, sort+csr %.2f ms\n", n_levels,
+    std::fprintf(stderr, "[fmm] gpu traversal: %d steps %.2f ms, sort+csr %.2f ms, scratch release %.2f ms\n", n_levels,
                  std::chrono::duration<double, std::milli>(t_front - t_start).count(),
-                 std::chrono::duration<double, std::milli>(t_end - t_front).count());
+                 std::chrono::duration<double, std::milli>(t_end - t_front).count(),
+                 std::chrono::duration<double, std::milli>(now() - t_end).count());
   }
   return 0;
 }
@@ -598,7 +662,8 @@ int pack_positions(bool fp64, int64_t n, const double *pos, void *out, void *str
 int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, DeviceTree &out,
                    TreeData &t, std::string &err) {
   if (int rc = keep_pool_memory()) return rc;
-  const hipStream_t st = S_(stream);
+  hipStream_t st;
+  if (int rc = build_stream(stream, reinterpret_cast<void **>(&st))) return rc;
   out = DeviceTree();
   t = TreeData();
   t.n = n;
@@ -607,9 +672,40 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
     t.level_begin.assign(1, 0);
     return 0;
   }
+  // Scratch of the previous build on this device is reused (as the
+  // traversal does; freeing large pool blocks costs milliseconds).
+  struct TreeScratch {
+    Buf boxes, key, idx, key2, idx2, temp, bb, nbd, lv, par, cb, nc, nch, off, gcnt, goff, gtab,
+        gacc;
+    size_t bytes() const {
+      const Buf *all[] = {&boxes, &key, &idx, &key2, &idx2, &temp, &bb, &nbd, &lv,
+                          &par, &cb, &nc, &nch, &off, &gcnt, &goff, &gtab, &gacc};
+      size_t s = 0;
+      for (const Buf *b : all) s += b->bytes;
+      return s;
+    }
+  };
+  static std::mutex cache_mu;  // a heap array never destroyed: no HIP call at exit
+  static std::unique_ptr<TreeScratch> *cache = new std::unique_ptr<TreeScratch>[kMaxDevices];
+  int dev = 0;
+  TRY(hipGetDevice(&dev));
+  std::unique_ptr<TreeScratch> sc;
+  {
+    std::lock_guard<std::mutex> guard(cache_mu);
+    if (dev >= 0 && dev < kMaxDevices) sc = std::move(cache[dev]);
+  }
+  if (!sc) sc.reset(new TreeScratch);
+  auto keep = [&]() {
+    if (sc->bytes() <= kKeepScratchBytes && dev >= 0 && dev < kMaxDevices) {
+      std::lock_guard<std::mutex> guard(cache_mu);
+      if (!cache[dev]) cache[dev] = std::move(sc);
+    }
+  };
+  Buf &boxes = sc->boxes, &key = sc->key, &idx = sc->idx, &key2 = sc->key2, &idx2 = sc->idx2,
+      &temp = sc->temp, &bb = sc->bb, &nbd = sc->nbd, &lv = sc->lv, &par = sc->par, &cb = sc->cb,
+      &nc = sc->nc, &nch = sc->nch, &off = sc->off;
   // bounding box, finiteness, FP32 representability
   const int nblk = (int)std::min<int64_t>(1024, (n + 255) / 256);
-  Buf boxes;
   TRY(boxes.reserve(nblk * sizeof(Box), st, false));
   bbox_partial<<<nblk, 256, 0, st>>>(n, xyz, (Box *)boxes.p);
   TRY(hipGetLastError());
@@ -643,7 +739,6 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
   }
   t.root_half = h;
   // keys, stable sort of (key, index)
-  Buf key, idx, key2, idx2, temp;
   TRY(key.reserve(n * 8, st, false));
   TRY(idx.reserve(n * 4, st, false));
   TRY(key2.reserve(n * 8, st, false));
@@ -667,7 +762,6 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
   gather_positions<<<blocks_for(n, 256), 256, 0, st>>>(n, xyz, out.perm, out.pos);
   TRY(hipGetLastError());
   // levels
-  Buf bb, nbd, lv, par, cb, nc, nch, off;
   size_t cap = 1024;
   auto grow = [&](size_t want) -> hipError_t {
     if (want <= cap && bb.p) return hipSuccess;
@@ -730,7 +824,7 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
   // geometry
   TRY(hipMalloc((void **)&out.geo, ncells * 32));
   {
-    Buf gcnt, goff, gtab, gacc;
+    Buf &gcnt = sc->gcnt, &goff = sc->goff, &gtab = sc->gtab, &gacc = sc->gacc;
     TRY(gcnt.reserve(ncells * 4, st, false));
     TRY(goff.reserve(ncells * 4, st, false));
     TRY(gacc.reserve(ncells * 7 * 8, st, false));
@@ -806,6 +900,7 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
   }
   out.n = n;
   out.n_cells = ncells;
+  keep();  // the stream is idle: the scratch can serve the next build
   return 0;
 }
 
