@@ -113,6 +113,7 @@ EDGE = [
     ("all-coincident", np.tile([[0.25, 0.5, 0.75]], (100, 1)), 8),
     ("duplicates", "dup", 4),
     ("deep-big-leaf", "deep", 8),
+    ("big-leaf-small-tail", "tail", 8),
     ("not-fp32", "rand", 16),
     ("flat-line", "line", 4),
 ]
@@ -128,6 +129,9 @@ def _edge_points(spec):
         return np.concatenate([b, b[:150], b[:40]])
     if spec == "deep":  # 300 coincident bodies: a level-21 leaf, several target groups
         return np.concatenate([np.tile([[0.3, 0.3, 0.3]], (300, 1)), W.uniform_cube(700, seed=18)])
+    if spec == "tail":  # a level-21 leaf of 70 bodies: target groups of 64 and 6, the
+        # last one on one lane per source stream, with 70 self sources
+        return np.concatenate([np.tile([[0.6, 0.2, 0.4]], (70, 1)), W.uniform_cube(500, seed=25)])
     if spec == "rand":
         return np.random.default_rng(19).random((2000, 3))
     if spec == "line":  # canonical (FP32-representable) points on a segment
