@@ -89,6 +89,7 @@ struct DevLists {
   int p = 0, prec = -1;
   int64_t n_top = -1;
   void *M = nullptr, *L = nullptr, *Lstage = nullptr;
+  void *Mr = nullptr;  // multipoles folded for M2L (stride rstride(p))
   double *M64 = nullptr, *L64 = nullptr, *L64stage = nullptr;
   void *part_s = nullptr, *part_c = nullptr;
   void *tmp_phi = nullptr, *tmp_grad = nullptr;
@@ -101,11 +102,11 @@ struct DevLists {
   hipEvent_t ev[FMM_NUM_PHASES + 2] = {};
   bool have_events = false, timing_valid = false, timed_serial = false;
   void release_scratch() {
-    void *ptrs[] = {M, L, Lstage, M64, L64, L64stage, part_s, part_c, tmp_phi, tmp_grad,
+    void *ptrs[] = {M, Mr, L, Lstage, M64, L64, L64stage, part_s, part_c, tmp_phi, tmp_grad,
                     vec4, tmp_hv, m2p_buf};
     for (void *p2 : ptrs)
       if (p2) (void)hipFree(p2);
-    M = L = Lstage = part_s = part_c = tmp_phi = tmp_grad = vec4 = tmp_hv = m2p_buf = nullptr;
+    M = Mr = L = Lstage = part_s = part_c = tmp_phi = tmp_grad = vec4 = tmp_hv = m2p_buf = nullptr;
     M64 = L64 = L64stage = nullptr;
     p = 0;
     prec = -1;
@@ -414,6 +415,7 @@ int ensure_scratch(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o) {
   const size_t real = fp64 ? 8 : 4;
   const size_t coef = (size_t)nc * fmmlib::dev::stride(o->p);
   HIP_TRY(hipMalloc(&dv.M, coef * real));
+  HIP_TRY(hipMalloc(&dv.Mr, (size_t)nc * fmmlib::dev::rstride(o->p) * real));
   HIP_TRY(hipMalloc(&dv.L, coef * real));
   HIP_TRY(hipMalloc(&dv.Lstage, coef * real));
   if (n_top > 0) {
@@ -577,16 +579,18 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   }
   if (int rc = mark(3, s)) return rc;
   {
+    // M2L reads the multipoles folded onto their terms of z exponent <= 1.
+    LAUNCH_TRY(D::fold_multipoles(p, fp64, td.n_cells(), dv.M, dv.Mr, stream));
     // every cell is an M2L row (one without entries writes zeros); the top
     // n_top cells accumulate in FP64.  A target range takes, level by level,
     // the cells holding its bodies.
     auto m2l_cells = [&](int64_t c0, int64_t c1) -> int {
       const int64_t split = std::max(c0, std::min(n_top, c1));
       if (split > c0)
-        LAUNCH_TRY(D::m2l(p, fp64, c0, split, dv.m2l_ptr, dv.m2l_col, geo, dv.M, dv.L, dv.L64,
+        LAUNCH_TRY(D::m2l(p, fp64, c0, split, dv.m2l_ptr, dv.m2l_col, geo, dv.Mr, dv.L, dv.L64,
                           true, stream));
       if (c1 > split)
-        LAUNCH_TRY(D::m2l(p, fp64, split, c1, dv.m2l_ptr, dv.m2l_col, geo, dv.M, dv.L, dv.L64,
+        LAUNCH_TRY(D::m2l(p, fp64, split, c1, dv.m2l_ptr, dv.m2l_col, geo, dv.Mr, dv.L, dv.L64,
                           false, stream));
       return FMM_OK;
     };

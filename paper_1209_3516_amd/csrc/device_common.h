@@ -77,53 +77,92 @@ struct Basis {
 template <int P>
 inline constexpr Basis<P> kBasis{};
 
-// (k, n, s): s = term of n + k, for all |n| + |k| <= P-1.  C(P+5, 6) entries.
-constexpr int m2l_count(int p) {
-  long r = 1;
-  for (int i = 1; i <= 6; ++i) r = r * (p - 1 + i) / i;
-  return (int)r;
-}
-template <int P>
-struct M2LTable {
-  static constexpr int N = m2l_count(P);
-  int k[N], n[N], s[N];
-  constexpr M2LTable() : k(), n(), s() {
-    constexpr int T = nterms(P);
-    Basis<P> B{};
-    int i = 0;
-    for (int kk = 0; kk < T; ++kk)
-      for (int nn = 0; nn < T; ++nn) {
-        const int ss = term_index(P, B.ex[kk] + B.ex[nn], B.ey[kk] + B.ey[nn], B.ez[kk] + B.ez[nn]);
-        if (ss < 0) continue;
-        k[i] = kk;
-        n[i] = nn;
-        s[i] = ss;
-        ++i;
-      }
-  }
-};
-template <int P>
-inline constexpr M2LTable<P> kM2L{};
+// ----------------------------------------------------------------------------
+// Harmonic reduction of M2L.  G = 1/r is harmonic, so its derivatives obey
+// D^{m+2e_x} + D^{m+2e_y} + D^{m+2e_z} = 0; applied j times,
+//   D^{(a, b, c+2j)} = (-1)^j sum_{i=0..j} C(j,i) D^{(a+2i, b+2(j-i), c)}.
+// In L_k = sum_{|n| <= p-1-|k|} M_n D^{n+k} this gives two exact identities,
+// each keeping the degree of the index it rewrites:
+//  * source side: the terms with n_z >= 2 fold onto those with n_z <= 1,
+//      Mr_(a,b,c) = sum_{j,i} (-1)^j C(j,i) M_(a-2i, b-2(j-i), c+2j),  c <= 1,
+//    a multipole of p^2 terms whose M2L is that of M;
+//  * target side: L_(a,b,c+2j) = (-1)^j sum_i C(j,i) L_(a+2i, b+2(j-i), c).
+// M2L therefore contracts only the p^2 terms of z exponent <= 1 on both
+// sides, with derivatives of z exponent <= 2: sum_{a+b <= p-1} (2a+1)(2b+1)
+// products per pair (70 / 301 / 876 for p = 4 / 6 / 8, against
+// C(p+5, 6) = 84 / 462 / 1716 for the full contraction).
+// ----------------------------------------------------------------------------
+constexpr int rterms(int p) { return p * p; }
 
-// The same contraction ordered by source term n, so that each group of four
-// consecutive source terms (one 16-byte load of a multipole row) is used at
-// once: the entries of group g are [gbeg[g], gbeg[g + 1]).  For every target
-// term k the source terms still come in ascending order, as in M2LTable.
+// Reduced terms (z exponent 0 or 1) of degree < p, ordered by degree, then
+// by the z exponent, then by the y exponent.
+constexpr int rterm_index(int p, int a, int b, int c) {
+  if (a < 0 || b < 0 || c < 0 || c > 1) return -1;
+  const int d = a + b + c;
+  if (d > p - 1) return -1;
+  return d * d + c * (d + 1) + b;
+}
+
+constexpr int binom(int j, int i) {
+  int r = 1;
+  for (int t = 1; t <= i; ++t) r = r * (j - i + t) / t;
+  return r;
+}
+
+// f(t, r, w, first) for every full term t and each reduced term r it pairs
+// with in the identities above, with the integer weight w; `first` marks the
+// first pair of each t.  Pairs come in ascending t.
+template <int P, class F>
+__device__ __forceinline__ void harmonic_pairs(F &&f) {
+  static_for<nterms(P)>([&](auto I) {
+    constexpr int t = decltype(I)::value;
+    constexpr int a = kBasis<P>.ex[t], b = kBasis<P>.ey[t], c = kBasis<P>.ez[t];
+    constexpr int j = c / 2;
+    static_for<j + 1>([&](auto Ii) {
+      constexpr int i = decltype(Ii)::value;
+      constexpr int r = rterm_index(P, a + 2 * i, b + 2 * (j - i), c % 2);
+      constexpr int w = (j % 2 ? -1 : 1) * binom(j, i);
+      f(std::integral_constant<int, t>{}, std::integral_constant<int, r>{},
+        std::integral_constant<int, w>{}, std::integral_constant<bool, i == 0>{});
+    });
+  });
+}
+
+constexpr int m2l_reduced_count(int p) {
+  int c = 0;
+  for (int a = 0; a < p; ++a)
+    for (int b = 0; a + b < p; ++b) c += (2 * a + 1) * (2 * b + 1);
+  return c;
+}
+
+// The reduced contraction as (k, n, s): k and n reduced terms, s the full
+// term of n + k (z exponent <= 2), for all |n| + |k| <= P-1.  Ordered by
+// source term n, so that each group of four consecutive source terms (one
+// 16-byte load of a reduced multipole row) is used at once: the entries of
+// group g are [gbeg[g], gbeg[g + 1]).  For every target term k the source
+// terms come in ascending order.
 template <int P>
-struct M2LTableBySource {
-  static constexpr int N = m2l_count(P);
-  static constexpr int G = (nterms(P) + 3) / 4;
+struct M2LReduced {
+  static constexpr int TR = rterms(P);
+  static constexpr int N = m2l_reduced_count(P);
+  static constexpr int G = (TR + 3) / 4;
   int k[N], n[N], s[N], gbeg[G + 1];
-  constexpr M2LTableBySource() : k(), n(), s(), gbeg() {
-    constexpr int T = nterms(P);
-    Basis<P> B{};
+  constexpr M2LReduced() : k(), n(), s(), gbeg() {
+    int rx[TR] = {}, ry[TR] = {}, rz[TR] = {};
+    for (int d = 0; d < P; ++d)
+      for (int c = 0; c <= 1 && c <= d; ++c)
+        for (int b = 0; b <= d - c; ++b) {
+          const int r = rterm_index(P, d - b - c, b, c);
+          rx[r] = d - b - c;
+          ry[r] = b;
+          rz[r] = c;
+        }
     int i = 0;
     for (int g = 0; g < G; ++g) {
       gbeg[g] = i;
-      for (int nn = 4 * g; nn < 4 * g + 4 && nn < T; ++nn)
-        for (int kk = 0; kk < T; ++kk) {
-          const int ss =
-              term_index(P, B.ex[kk] + B.ex[nn], B.ey[kk] + B.ey[nn], B.ez[kk] + B.ez[nn]);
+      for (int nn = 4 * g; nn < 4 * g + 4 && nn < TR; ++nn)
+        for (int kk = 0; kk < TR; ++kk) {
+          const int ss = term_index(P, rx[kk] + rx[nn], ry[kk] + ry[nn], rz[kk] + rz[nn]);
           if (ss < 0) continue;
           k[i] = kk;
           n[i] = nn;
@@ -135,7 +174,7 @@ struct M2LTableBySource {
   }
 };
 template <int P>
-inline constexpr M2LTableBySource<P> kM2LS{};
+inline constexpr M2LReduced<P> kM2LR{};
 
 // (hi, lo, diff): lo <= hi componentwise, diff = term of hi - lo.
 constexpr int shift_count(int p) {
@@ -212,7 +251,9 @@ __device__ __forceinline__ void monomials(Real dx, Real dy, Real dz, Real (&mono
 // and, since 1/r is harmonic (sum_d D_{m'+2e_d} = 0), every term with
 // m_z >= 2 follows from two terms of the same degree with smaller m_z:
 //   D_m = -D_{m-2e_z+2e_x} - D_{m-2e_z+2e_y}.
-template <int P, typename Real>
+// With Z2, only the terms of z exponent <= 2 are computed (the others are
+// left unset): those are all that the reduced M2L reads.
+template <int P, typename Real, bool Z2 = false>
 __device__ __forceinline__ void derivatives(Real Rx, Real Ry, Real Rz, Real (&D)[nterms(P)]) {
   constexpr int T = nterms(P);
   const Real r2 = Rx * Rx + Ry * Ry + Rz * Rz;
@@ -225,7 +266,8 @@ __device__ __forceinline__ void derivatives(Real Rx, Real Ry, Real Rz, Real (&D)
     constexpr auto &B = kBasis<P>;
     constexpr int mx = B.ex[t], my = B.ey[t], mz = B.ez[t];
     constexpr int k = mx + my + mz;
-    if constexpr (mz >= 2) {
+    if constexpr (Z2 && mz > 2) {
+    } else if constexpr (mz >= 2) {
       constexpr int ia = term_index(P, mx + 2, my, mz - 2);
       constexpr int ib = term_index(P, mx, my + 2, mz - 2);
       D[t] = -D[ia] - D[ib];

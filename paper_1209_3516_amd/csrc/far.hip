@@ -101,11 +101,38 @@ __global__ __launch_bounds__(64) void m2m_kernel(int64_t c0, int64_t c1, const i
 }
 
 // ----------------------------------------------------------------------------
+// Harmonic fold of the multipoles for M2L (the identities are stated with
+// the reduced contraction table): one thread per cell, Mr[c] = the p^2
+// terms of z exponent <= 1, each a signed binomial sum of terms of M[c] of
+// the same degree, summed in FP64 and rounded once.
+// ----------------------------------------------------------------------------
+template <int P, typename Real>
+__global__ __launch_bounds__(64) void fold_kernel(int64_t n_cells, const Real *__restrict__ M,
+                                                  Real *__restrict__ Mr) {
+  constexpr int T = nterms(P), S = pad4(T), TR = rterms(P), SR = pad4(TR);
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  Real m[T];
+  load_row<T>(M + c * S, m);
+  double acc[TR];
+  static_for<TR>([&](auto I) { acc[decltype(I)::value] = 0.0; });
+  harmonic_pairs<P>([&](auto t, auto r, auto w, auto) {
+    acc[decltype(r)::value] += double(decltype(w)::value) * double(m[decltype(t)::value]);
+  });
+  static_for<SR>([&](auto I) {
+    constexpr int r = decltype(I)::value;
+    Mr[c * SR + r] = r < TR ? Real(acc[r < TR ? r : 0]) : Real(0);
+  });
+}
+
+// ----------------------------------------------------------------------------
 // M2L: one 64-lane wave per target cell (a cell without entries writes
 // zeros, so L needs no clearing before M2L); lane l takes the
-// entries l, l+64, ... of the row, computes D^m G(X_A - X_B) with the
-// recurrence and contracts it with the source multipole.  The 64 lane
-// partials are summed in LDS in a fixed order.
+// entries l, l+64, ... of the row, computes D^m G(X_A - X_B) (z exponent
+// <= 2) with the recurrence and contracts it with the folded source
+// multipole into the p^2 target terms of z exponent <= 1.  These are
+// expanded to all target terms, and the 64 lane partials are summed in LDS
+// in a fixed order.
 // ----------------------------------------------------------------------------
 // Terms per round of the final cross-lane sum of M2L.
 constexpr int m2l_red_terms(int T) { return T < 64 ? T : 64; }
@@ -114,39 +141,39 @@ template <int P, typename Real, typename Acc>
 __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ ptr,
                                         const int32_t *__restrict__ col,
                                         const double4 *__restrict__ geo,
-                                        const Real *__restrict__ M, Acc *__restrict__ Lout,
+                                        const Real *__restrict__ Mr, Acc *__restrict__ Lout,
                                         Acc *__restrict__ red) {
-  constexpr int T = nterms(P), S = pad4(T);
+  constexpr int T = nterms(P), S = pad4(T), TR = rterms(P), SR = pad4(TR);
   const int lane = threadIdx.x;
   const int A = (int)(r0 + xcd_remap(blockIdx.x, gridDim.x));
   const double4 ga = geo[A];
-  Acc acc[T];
-  static_for<T>([&](auto I) { acc[decltype(I)::value] = Acc(0); });
+  Acc acc[TR];
+  static_for<TR>([&](auto I) { acc[decltype(I)::value] = Acc(0); });
   const int64_t e1 = ptr[A + 1];
-  if constexpr (T <= 56) {
+  if constexpr (TR <= 36) {
     // Software pipeline with two register buffers: the centre and multipole
     // of the lane's next entry load while the current entry is computed.
-    auto contract = [&](const double4 &gb, const Real (&mb)[T]) {
+    auto contract = [&](const double4 &gb, const Real (&mb)[TR]) {
       Real D[T];
-      derivatives<P, Real>(Real(ga.x - gb.x), Real(ga.y - gb.y), Real(ga.z - gb.z), D);
-      static_for<kM2L<P>.N>([&](auto I) {
+      derivatives<P, Real, true>(Real(ga.x - gb.x), Real(ga.y - gb.y), Real(ga.z - gb.z), D);
+      static_for<kM2LR<P>.N>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        acc[kM2L<P>.k[i]] += Acc(mb[kM2L<P>.n[i]] * D[kM2L<P>.s[i]]);
+        acc[kM2LR<P>.k[i]] += Acc(mb[kM2LR<P>.n[i]] * D[kM2LR<P>.s[i]]);
       });
     };
     int64_t e = ptr[A] + lane;
     double4 g0 = ga, g1 = ga;
-    Real m0[T], m1[T];
+    Real m0[TR], m1[TR];
     if (e < e1) {
       const int B = col[e];
       g0 = geo[B];
-      load_row<T>(M + (int64_t)B * S, m0);
+      load_row<TR>(Mr + (int64_t)B * SR, m0);
     }
     int Bn = (e + 64 < e1) ? col[e + 64] : 0;
     while (e < e1) {
       if (e + 64 < e1) {
         g1 = geo[Bn];
-        load_row<T>(M + (int64_t)Bn * S, m1);
+        load_row<TR>(Mr + (int64_t)Bn * SR, m1);
         Bn = (e + 128 < e1) ? col[e + 128] : 0;
       }
       contract(g0, m0);
@@ -154,35 +181,44 @@ __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ 
       if (e >= e1) break;
       if (e + 64 < e1) {
         g0 = geo[Bn];
-        load_row<T>(M + (int64_t)Bn * S, m0);
+        load_row<TR>(Mr + (int64_t)Bn * SR, m0);
         Bn = (e + 128 < e1) ? col[e + 128] : 0;
       }
       contract(g1, m1);
       e += 64;
     }
   } else {
-    // High orders: the accumulators and the derivatives fill the registers,
-    // so the source multipole is streamed in groups of four terms, each used
-    // by all its contraction entries as soon as it arrives (same order of
-    // additions per target term as above).
-    constexpr int G = kM2LS<P>.G;
+    // High orders: the source multipole is streamed in groups of four
+    // terms, each used by all its contraction entries as soon as it arrives.
     for (int64_t e = ptr[A] + lane; e < e1; e += 64) {
       const int B = col[e];
       const double4 gb = geo[B];
       Real D[T];
-      derivatives<P, Real>(Real(ga.x - gb.x), Real(ga.y - gb.y), Real(ga.z - gb.z), D);
-      const Real *mrow = M + (int64_t)B * S;
-      static_for<G>([&](auto Gi) {
+      derivatives<P, Real, true>(Real(ga.x - gb.x), Real(ga.y - gb.y), Real(ga.z - gb.z), D);
+      const Real *mrow = Mr + (int64_t)B * SR;
+      static_for<kM2LR<P>.G>([&](auto Gi) {
         constexpr int g = decltype(Gi)::value;
         Real m4[4];
         load4(mrow + 4 * g, m4);
-        static_for<kM2LS<P>.gbeg[g + 1] - kM2LS<P>.gbeg[g]>([&](auto J) {
-          constexpr int i = kM2LS<P>.gbeg[g] + decltype(J)::value;
-          acc[kM2LS<P>.k[i]] += Acc(m4[kM2LS<P>.n[i] - 4 * g] * D[kM2LS<P>.s[i]]);
+        static_for<kM2LR<P>.gbeg[g + 1] - kM2LR<P>.gbeg[g]>([&](auto J) {
+          constexpr int i = kM2LR<P>.gbeg[g] + decltype(J)::value;
+          acc[kM2LR<P>.k[i]] += Acc(m4[kM2LR<P>.n[i] - 4 * g] * D[kM2LR<P>.s[i]]);
         });
       });
     }
   }
+  // All target terms from the reduced ones (a linear map, so it commutes
+  // with the sum over lanes).
+  Acc full[T];
+  harmonic_pairs<P>([&](auto t, auto r, auto w, auto first) {
+    constexpr int tt = decltype(t)::value, rr = decltype(r)::value, ww = decltype(w)::value;
+    Acc v;
+    if constexpr (ww == 1) v = acc[rr];
+    else if constexpr (ww == -1) v = -acc[rr];
+    else v = Acc(ww) * acc[rr];
+    if constexpr (decltype(first)::value) full[tt] = v;
+    else full[tt] += v;
+  });
   // Sum the 64 lane partials of each term in lane order, at most 64 terms at
   // a time (so that the LDS buffer does not limit how many waves a CU holds).
   constexpr int CH = m2l_red_terms(T);
@@ -192,7 +228,7 @@ __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ 
     if constexpr (c0 > 0) __syncthreads();
     static_for<nt>([&](auto I) {
       constexpr int j = decltype(I)::value;
-      red[lane * (CH + 1) + j] = acc[c0 + j];
+      red[lane * (CH + 1) + j] = full[c0 + j];
     });
     __syncthreads();
     if (lane < nt) {
@@ -207,9 +243,9 @@ template <int P, typename Real, typename Acc>
 __global__ __launch_bounds__(64) void m2l_kernel(int64_t r0, const int64_t *__restrict__ ptr,
                                                  const int32_t *__restrict__ col,
                                                  const double4 *__restrict__ geo,
-                                                 const Real *__restrict__ M, Acc *__restrict__ Lout) {
+                                                 const Real *__restrict__ Mr, Acc *__restrict__ Lout) {
   __shared__ Acc red[64 * (m2l_red_terms(nterms(P)) + 1)];
-  m2l_row<P, Real, Acc>(r0, ptr, col, geo, M, Lout, red);
+  m2l_row<P, Real, Acc>(r0, ptr, col, geo, Mr, Lout, red);
 }
 
 // The same for high orders in FP32, held to two waves per SIMD (at most 256
@@ -218,9 +254,9 @@ __global__ __launch_bounds__(64) void m2l_kernel(int64_t r0, const int64_t *__re
 template <int P, typename Real, typename Acc>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_kernel_w2(
     int64_t r0, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-    const double4 *__restrict__ geo, const Real *__restrict__ M, Acc *__restrict__ Lout) {
+    const double4 *__restrict__ geo, const Real *__restrict__ Mr, Acc *__restrict__ Lout) {
   __shared__ Acc red[64 * (m2l_red_terms(nterms(P)) + 1)];
-  m2l_row<P, Real, Acc>(r0, ptr, col, geo, M, Lout, red);
+  m2l_row<P, Real, Acc>(r0, ptr, col, geo, Mr, Lout, red);
 }
 
 // ----------------------------------------------------------------------------
@@ -484,8 +520,20 @@ int m2m(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *child_begin,
   });
 }
 
+int fold_multipoles(int p, bool fp64, int64_t n_cells, const void *M, void *Mr, void *stream) {
+  if (n_cells <= 0) return 0;
+  const unsigned nb = blocks_for(n_cells, 64);
+  return with_p(p, [&](auto PC) {
+    constexpr int PP = decltype(PC)::value;
+    if (fp64)
+      fold_kernel<PP, double><<<nb, 64, 0, S_(stream)>>>(n_cells, (const double *)M, (double *)Mr);
+    else
+      fold_kernel<PP, float><<<nb, 64, 0, S_(stream)>>>(n_cells, (const float *)M, (float *)Mr);
+  });
+}
+
 int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
-        const int32_t *col, const double *geo, const void *M, void *L, double *L64,
+        const int32_t *col, const double *geo, const void *Mr, void *L, double *L64,
         bool acc_fp64, void *stream) {
   if (r1 <= r0) return 0;
   const unsigned G = (unsigned)(r1 - r0);
@@ -494,16 +542,16 @@ int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
     constexpr int PP = decltype(PC)::value;
     if (fp64)
       m2l_kernel<PP, double, double><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
-                                                               (const double *)M, (double *)L);
+                                                               (const double *)Mr, (double *)L);
     else if (acc_fp64)
       m2l_kernel<PP, float, double><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
-                                                              (const float *)M, L64);
-    else if constexpr (nterms(PP) > 56)
+                                                              (const float *)Mr, L64);
+    else if constexpr (rterms(PP) > 36)
       m2l_kernel_w2<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
-                                                                (const float *)M, (float *)L);
+                                                                (const float *)Mr, (float *)L);
     else
       m2l_kernel<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
-                                                             (const float *)M, (float *)L);
+                                                             (const float *)Mr, (float *)L);
   });
 }
 

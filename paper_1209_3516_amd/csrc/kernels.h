@@ -16,6 +16,8 @@ namespace dev {
 // multiple of 4 (16-byte rows for FP32).
 inline int terms(int p) { return p * (p + 1) * (p + 2) / 6; }
 inline int stride(int p) { return (terms(p) + 3) & ~3; }
+// Multipoles folded for M2L keep the p^2 terms of z exponent <= 1.
+inline int rstride(int p) { return (p * p + 3) & ~3; }
 
 // bodies: [n] float4/double4 (x, y, z, q) in Morton order.
 int gather_charges(bool fp64, int64_t n, const int32_t *perm, const void *q_user, void *bodies,
@@ -49,10 +51,15 @@ int m2m(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *child_begin,
         const int32_t *n_child, const double *geo, void *M, double *M64, bool child_fp64,
         bool out_fp64, void *stream);
 
-// Target cells [r0, r1); acc_fp64: the row accumulates in FP64 into L64, else
-// into L (FP32 in mixed mode).
+// Mr[c] (stride rstride(p)): the multipole of cell c folded onto its terms
+// of z exponent <= 1, which is all that M2L needs of it (G = 1/r is
+// harmonic).  Cells [0, n_cells).
+int fold_multipoles(int p, bool fp64, int64_t n_cells, const void *M, void *Mr, void *stream);
+
+// Target cells [r0, r1) from the folded multipoles Mr; acc_fp64: the row
+// accumulates in FP64 into L64, else into L (FP32 in mixed mode).
 int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
-        const int32_t *col, const double *geo, const void *M, void *L, double *L64,
+        const int32_t *col, const double *geo, const void *Mr, void *L, double *L64,
         bool acc_fp64, void *stream);
 
 // Children are the cells [c0, c1) of one level.
