@@ -190,11 +190,24 @@ __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ 
   } else {
     // High orders: the source multipole is streamed in groups of four
     // terms, each used by all its contraction entries as soon as it arrives.
-    for (int64_t e = ptr[A] + lane; e < e1; e += 64) {
-      const int B = col[e];
-      const double4 gb = geo[B];
+    // The source cell of the entry after next and the centre of the next
+    // entry load while this entry is computed (indices past the row's end
+    // are clamped to its last entry); the empty asm at the end of the body
+    // keeps the compiler from moving those loads next to their use.
+    int64_t e = ptr[A] + lane;
+    const int64_t last = e1 - 1;
+    int Bc = col[e < last ? e : last];
+    int Bn = col[e + 64 < last ? e + 64 : last];
+    const double4 g0 = geo[Bc];
+    Real rx = Real(ga.x - g0.x), ry = Real(ga.y - g0.y), rz = Real(ga.z - g0.z);
+    for (; e < e1; e += 64) {
+      const int B = Bc;
+      const Real Rx = rx, Ry = ry, Rz = rz;
+      Bc = Bn;
+      const double4 gn = geo[Bc];
+      Bn = col[e + 128 < last ? e + 128 : last];
       Real D[T];
-      derivatives<P, Real, true>(Real(ga.x - gb.x), Real(ga.y - gb.y), Real(ga.z - gb.z), D);
+      derivatives<P, Real, true>(Rx, Ry, Rz, D);
       const Real *mrow = Mr + (int64_t)B * SR;
       static_for<kM2LR<P>.G>([&](auto Gi) {
         constexpr int g = decltype(Gi)::value;
@@ -205,6 +218,10 @@ __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ 
           acc[kM2LR<P>.k[i]] += Acc(m4[kM2LR<P>.n[i] - 4 * g] * D[kM2LR<P>.s[i]]);
         });
       });
+      rx = Real(ga.x - gn.x);
+      ry = Real(ga.y - gn.y);
+      rz = Real(ga.z - gn.z);
+      asm volatile("" : "+v"(rx), "+v"(ry), "+v"(rz), "+v"(Bc), "+v"(Bn));
     }
   }
   // All target terms from the reduced ones (a linear map, so it commutes
