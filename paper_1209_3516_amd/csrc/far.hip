@@ -137,7 +137,8 @@ __global__ __launch_bounds__(64) void fold_kernel(int64_t n_cells, const Real *_
 // Terms per round of the final cross-lane sum of M2L.
 constexpr int m2l_red_terms(int T) { return T < 64 ? T : 64; }
 
-template <int P, typename Real, typename Acc>
+template <int P, typename Real, typename Acc, int CH = m2l_red_terms(nterms(P)),
+          bool STREAM = (rterms(P) > 36)>
 __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ ptr,
                                         const int32_t *__restrict__ col,
                                         const double4 *__restrict__ geo,
@@ -150,7 +151,7 @@ __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ 
   Acc acc[TR];
   static_for<TR>([&](auto I) { acc[decltype(I)::value] = Acc(0); });
   const int64_t e1 = ptr[A + 1];
-  if constexpr (TR <= 36) {
+  if constexpr (!STREAM) {
     // Software pipeline with two register buffers: the centre and multipole
     // of the lane's next entry load while the current entry is computed.
     auto contract = [&](const double4 &gb, const Real (&mb)[TR]) {
@@ -188,7 +189,7 @@ __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ 
       e += 64;
     }
   } else {
-    // High orders: the source multipole is streamed in groups of four
+    // Streamed: the source multipole comes in groups of four
     // terms, each used by all its contraction entries as soon as it arrives.
     // The source cell of the entry after next and the centre of the next
     // entry load while this entry is computed (indices past the row's end
@@ -236,9 +237,8 @@ __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ 
     if constexpr (decltype(first)::value) full[tt] = v;
     else full[tt] += v;
   });
-  // Sum the 64 lane partials of each term in lane order, at most 64 terms at
+  // Sum the 64 lane partials of each term in lane order, at most CH terms at
   // a time (so that the LDS buffer does not limit how many waves a CU holds).
-  constexpr int CH = m2l_red_terms(T);
   static_for<(T + CH - 1) / CH>([&](auto Ci) {
     constexpr int c0 = decltype(Ci)::value * CH;
     constexpr int nt = T - c0 < CH ? T - c0 : CH;
@@ -274,6 +274,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const double4 *__restrict__ geo, const Real *__restrict__ Mr, Acc *__restrict__ Lout) {
   __shared__ Acc red[64 * (m2l_red_terms(nterms(P)) + 1)];
   m2l_row<P, Real, Acc>(r0, ptr, col, geo, Mr, Lout, red);
+}
+
+// Middle orders in FP32 at three waves per SIMD (at most 168 registers per
+// lane); the cross-lane sum goes 32 terms at a time to fit twelve waves' LDS.
+template <int P, typename Real, typename Acc>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void m2l_kernel_w3(
+    int64_t r0, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+    const double4 *__restrict__ geo, const Real *__restrict__ Mr, Acc *__restrict__ Lout) {
+  __shared__ Acc red[64 * (32 + 1)];
+  m2l_row<P, Real, Acc, 32, true>(r0, ptr, col, geo, Mr, Lout, red);
 }
 
 // ----------------------------------------------------------------------------
@@ -565,6 +575,9 @@ int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
                                                               (const float *)Mr, L64);
     else if constexpr (rterms(PP) > 36)
       m2l_kernel_w2<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
+                                                                (const float *)Mr, (float *)L);
+    else if constexpr (PP >= 5)
+      m2l_kernel_w3<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
                                                                 (const float *)Mr, (float *)L);
     else
       m2l_kernel<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
