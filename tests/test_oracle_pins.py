@@ -2,6 +2,10 @@
 
 * derivatives of 1/r: textbook closed forms (|m| <= 3), central finite
   differences, and harmonicity (the Laplacian of 1/r vanishes away from 0);
+* M2L and harmonicity: the local coefficients of one M2L are trace-free
+  (L_{k+2e_x} + L_{k+2e_y} + L_{k+2e_z} = 0), and a multipole whose terms with
+  n_z >= 2 are moved onto lower z (M_n -> -M at n-2e_z+2e_x and n-2e_z+2e_y)
+  has the same M2L, both exactly under the |n| + |k| <= p-1 truncation;
 * translations: M2M and L2L are exact re-centrings of polynomials, so
   M2M(P2M about the child) == P2M about the parent and L2P(L2L(L)) == L2P(L);
 * single-source exactness and the monopole case p = 1;
@@ -113,6 +117,46 @@ def test_derivatives_harmonic(p):
                 lap += D[ex.index(tuple(mm))]
             scale = math.factorial(sum(m) + 2) / np.linalg.norm(R) ** (sum(m) + 3)
             assert abs(lap) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("p", [3, 4, 6, 8])
+def test_m2l_harmonic_identities(p):
+    # Both identities keep the degree of the index they act on, so the
+    # truncation |n| + |k| <= p-1 cuts every term of them at the same place.
+    rng = np.random.default_rng(40 + p)
+    ex = [tuple(int(v) for v in m) for m in O.term_exponents(p)]
+    idx = {m: i for i, m in enumerate(ex)}
+    for _ in range(4):
+        XB = rng.uniform(-0.5, 0.5, 3)
+        XA = XB + rng.normal(size=3) * 2.0
+        M = rng.normal(size=len(ex))
+        L = O.m2l(p, XA, XB, M)
+        # trace-free locals
+        for k in ex:
+            if sum(k) > p - 3:
+                continue
+            terms = [L[idx[(k[0] + 2 * (d == 0), k[1] + 2 * (d == 1), k[2] + 2 * (d == 2))]]
+                     for d in range(3)]
+            assert abs(sum(terms)) <= 1e-12 * sum(abs(t) for t in terms) + 1e-300
+        # fold the z exponent of the multipole down to 0 or 1, one step at a time
+        F = M.copy()
+        for m in sorted(ex, key=lambda m: -m[2]):
+            if m[2] < 2:
+                continue
+            F[idx[(m[0] + 2, m[1], m[2] - 2)]] -= F[idx[m]]
+            F[idx[(m[0], m[1] + 2, m[2] - 2)]] -= F[idx[m]]
+            F[idx[m]] = 0.0
+        assert all(F[idx[m]] == 0.0 for m in ex if m[2] >= 2)
+        LF = O.m2l(p, XA, XB, F)
+        np.testing.assert_allclose(LF, L, rtol=0, atol=1e-11 * np.abs(L).max())
+        # and a multipole with terms of z exponent >= 2 does change M2L if they
+        # are simply dropped (the identity is not vacuous)
+        if p >= 3:
+            Z = M.copy()
+            for m in ex:
+                if m[2] >= 2:
+                    Z[idx[m]] = 0.0
+            assert np.abs(O.m2l(p, XA, XB, Z) - L).max() > 1e-6 * np.abs(L).max()
 
 
 @pytest.mark.parametrize("p", [1, 2, 4, 6, 8])
