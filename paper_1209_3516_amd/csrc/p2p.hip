@@ -261,14 +261,15 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
+        // Sums and compensations are added separately: a stream's value is
+        // S - C, and the log2(K) rounded additions of the tree are the only
+        // ones left uncompensated.
         const Real vs = lane_shuffle(S[r][c], from);
         if constexpr (KAHAN) {
           const Real vc = lane_shuffle(C[r][c], from);
           if (take) {
-            const Real y = (vs - vc) - C[r][c];
-            const Real t = S[r][c] + y;
-            C[r][c] = (t - S[r][c]) - y;
-            S[r][c] = t;
+            S[r][c] += vs;
+            C[r][c] += vc;
           }
         } else {
           if (take) S[r][c] += vs;
