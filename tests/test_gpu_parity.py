@@ -51,6 +51,7 @@ CASES = [
     ("uniform-2000-p1", "uniform", 2_000, "signed", 16, 0.5, 1),
     ("uniform-2500-p3", "uniform", 2_500, "signed", 5, 0.6, 3),
     ("plummer-4000-p5", "plummer", 4_000, "signed", 12, 0.45, 5),
+    ("uniform-3000-p7", "uniform", 3_000, "signed", 10, 0.35, 7),
 ]
 
 
@@ -77,7 +78,7 @@ def test_leaf_first_lists():
         assert rel(g, ref["grad"]) <= tol(prec, 4)
 
 
-@pytest.mark.parametrize("p", [2, 4, 6, 8])
+@pytest.mark.parametrize("p", [2, 4, 5, 6, 7, 8])
 def test_staged_expansions_match_oracle(p):
     """Multipoles after the upward pass, locals after M2L and after L2L (FP64)."""
     x = W.plummer(3000, seed=12)
