@@ -238,12 +238,21 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
     }
     if (lane == 0) rp[it.n_runs] = it.n_src;
     __syncthreads();
-    int ri = 0;
+    // Positions only grow, so the run of c is found by moving forward from
+    // the last one; its first position and body and the next run's first
+    // position stay in registers, so a lookup that stays in its run reads no
+    // LDS and each step forward reads two independent values.
+    int ri = 0, run_pos = rp[0], run_body0 = rb[0], next_pos = rp[1];
     p2p_phase<Real, MODE, R, KAHAN, MASK_ALL>(
         it.n_src,
         [&](int c) {
-          while (rp[ri + 1] <= c) ++ri;
-          return rb[ri] + (c - rp[ri]);
+          while (next_pos <= c) {
+            ++ri;
+            run_pos = next_pos;
+            run_body0 = rb[ri];
+            next_pos = rp[ri + 1];
+          }
+          return run_body0 + (c - run_pos);
         },
         bodies, vec, src, srcd, s, K, xi, yi, zi, vt, S, C);
   }
