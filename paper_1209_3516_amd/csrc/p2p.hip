@@ -236,21 +236,29 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
       rb[r] = run_body[it.run_begin + r];
       rp[r] = run_prefix[it.run_begin + r];
     }
-    if (lane == 0) rp[it.n_runs] = it.n_src;
+    // the prefixes end with n_src, twice (the lookup reads one run ahead)
+    if (lane < 2) rp[it.n_runs + lane] = it.n_src;
     __syncthreads();
     // Positions only grow, so the run of c is found by moving forward from
-    // the last one; its first position and body and the next run's first
-    // position stay in registers, so a lookup that stays in its run reads no
-    // LDS and each step forward reads two independent values.
-    int ri = 0, run_pos = rp[0], run_body0 = rb[0], next_pos = rp[1];
+    // the last one.  Its first position and body and the first positions of
+    // the next two runs stay in registers: a lookup that stays in its run
+    // reads no LDS, and each step forward (one or two runs) reads three
+    // independent values.
+    int ri = 0, run_pos = rp[0], run_body0 = rb[0], next_pos = rp[1], next2_pos = rp[2];
     p2p_phase<Real, MODE, R, KAHAN, MASK_ALL>(
         it.n_src,
         [&](int c) {
           while (next_pos <= c) {
-            ++ri;
-            run_pos = next_pos;
+            if (next2_pos <= c) {
+              ri += 2;
+              run_pos = next2_pos;
+            } else {
+              ri += 1;
+              run_pos = next_pos;
+            }
             run_body0 = rb[ri];
             next_pos = rp[ri + 1];
+            next2_pos = rp[ri + 2];
           }
           return run_body0 + (c - run_pos);
         },
@@ -311,7 +319,7 @@ __global__ __launch_bounds__(64) void p2p_kernel(const P2PItem *__restrict__ ite
   __shared__ V4 src[kNB + 64];
   __shared__ V4 srcd[MODE == kDipoles ? kNB + 64 : 1];
   __shared__ int32_t rb[kP2PMaxRuns];
-  __shared__ int32_t rp[kP2PMaxRuns + 1];
+  __shared__ int32_t rp[kP2PMaxRuns + 2];
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const P2PItem it = items[w];
   switch ((it.tgt_cfg >> 8) & 0xff) {
