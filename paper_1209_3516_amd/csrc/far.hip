@@ -195,12 +195,20 @@ __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ 
     // entry load while this entry is computed (indices past the row's end
     // are clamped to its last entry); the empty asm at the end of the body
     // keeps the compiler from moving those loads next to their use.
-    int64_t e = ptr[A] + lane;
-    const int64_t last = e1 - 1;
-    int Bc = col[e < last ? e : last];
-    int Bn = col[e + 64 < last ? e + 64 : last];
-    const double4 g0 = geo[Bc];
-    Real rx = Real(ga.x - g0.x), ry = Real(ga.y - g0.y), rz = Real(ga.z - g0.z);
+    // (An empty row has no last entry: it skips the loop and writes zeros.)
+    const int64_t e0 = ptr[A];
+    int64_t e = e0 + lane;
+    const int64_t last = e1 > e0 ? e1 - 1 : e0;
+    int Bc = 0, Bn = 0;
+    Real rx = Real(0), ry = Real(0), rz = Real(0);
+    if (e1 > e0) {
+      Bc = col[e < last ? e : last];
+      Bn = col[e + 64 < last ? e + 64 : last];
+      const double4 g0 = geo[Bc];
+      rx = Real(ga.x - g0.x);
+      ry = Real(ga.y - g0.y);
+      rz = Real(ga.z - g0.z);
+    }
     for (; e < e1; e += 64) {
       const int B = Bc;
       const Real Rx = rx, Ry = ry, Rz = rz;
