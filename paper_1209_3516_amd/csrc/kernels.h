@@ -124,7 +124,7 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
 // Scratch of the tree build, traversal and plan builder comes from the
 // device's default stream-ordered pool, which keeps up to this many freed
 // bytes for reuse instead of returning them to the driver.
-constexpr uint64_t kPoolKeepBytes = 4ull << 30;
+constexpr uint64_t kPoolKeepBytes = 16ull << 30;
 int keep_pool_memory();
 
 // Tree builds, traversals and plan builds run on one library-owned
@@ -134,8 +134,9 @@ int keep_pool_memory();
 // than on the legacy null stream, whose stream-ordered frees synchronise.
 constexpr int kMaxDevices = 64;
 // The traversal keeps up to this much of its scratch on each device for the
-// next traversal instead of freeing it.
-constexpr size_t kKeepScratchBytes = size_t(2) << 30;
+// next traversal instead of freeing it (a traversal of 10^7 bodies at
+// theta = 0.3 needs about 10 GB; a device has 288 GB).
+constexpr size_t kKeepScratchBytes = size_t(16) << 30;
 int build_stream(void *user, void **out);  // *out: the hipStream_t
 
 // P2P work plan on the device (the layout of P2PPlan, see plan.cpp).

@@ -4,8 +4,8 @@
 //
 // One thread per leaf walks the leaf's P2P row twice: a counting pass (runs,
 // chunks, source bodies, body pairs) and, after prefix sums give every leaf
-// its offsets, a writing pass.  Rows are short (tens of entries), so a
-// sequential walk per leaf is cheaper than anything that splits rows.
+// its offsets, a writing pass.  The walk is sequential (each chunk and run
+// depends on the ones before), with the row's entries loaded in batches.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -17,6 +17,8 @@ namespace fmmlib {
 namespace dev {
 
 namespace {
+
+constexpr int kWalkBatch = 8;
 
 struct Chunk {
   int32_t run_begin, n_runs, n_src;
@@ -37,34 +39,51 @@ __device__ int walk_row(int32_t a, int64_t bA, int64_t nA, const int64_t *__rest
   Chunk cur{run_base, 0, 0, false};
   int64_t last_end = -1;
   int64_t src = 0, pr = 0;
-  for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) {
-    const int32_t b = col[e];
-    const int64_t nb = n_body[b], bb = body_begin[b];
-    src += nb;
-    pr += nA * nb - (b == a ? nA : 0);
-    const bool contiguous = (b != a) && cur.n_runs > 0 && last_end == bb;
-    const bool full = (cur.n_src + (cur.self ? nA : 0) + nb > kP2PChunkSources &&
-                       (cur.n_src > 0 || cur.self)) ||
-                      (!contiguous && b != a && cur.n_runs >= kP2PMaxRuns);
-    if (full) {
-      on_chunk(nch++, cur);
-      cur = Chunk{run_base + runs, 0, 0, false};
-      last_end = -1;
+  // Entries are read eight at a time (the column, then the source leaf's
+  // bodies), so a long row costs two memory round trips per eight entries
+  // rather than per entry; they are then taken in order, as on the host.
+  const int64_t e_end = ptr[a + 1];
+  for (int64_t e0 = ptr[a]; e0 < e_end; e0 += kWalkBatch) {
+    int32_t bq[kWalkBatch];
+    int32_t nbq[kWalkBatch], bbq[kWalkBatch];
+#pragma unroll
+    for (int k = 0; k < kWalkBatch; ++k) bq[k] = e0 + k < e_end ? col[e0 + k] : 0;
+#pragma unroll
+    for (int k = 0; k < kWalkBatch; ++k) {
+      nbq[k] = e0 + k < e_end ? n_body[bq[k]] : 0;
+      bbq[k] = e0 + k < e_end ? body_begin[bq[k]] : 0;
     }
-    if (b == a) {
-      cur.self = true;
-      last_end = -1;
-      continue;
+#pragma unroll
+    for (int k = 0; k < kWalkBatch; ++k) {
+      if (e0 + k >= e_end) break;
+      const int32_t b = bq[k];
+      const int64_t nb = nbq[k], bb = bbq[k];
+      src += nb;
+      pr += nA * nb - (b == a ? nA : 0);
+      const bool contiguous = (b != a) && cur.n_runs > 0 && last_end == bb;
+      const bool full = (cur.n_src + (cur.self ? nA : 0) + nb > kP2PChunkSources &&
+                         (cur.n_src > 0 || cur.self)) ||
+                        (!contiguous && b != a && cur.n_runs >= kP2PMaxRuns);
+      if (full) {
+        on_chunk(nch++, cur);
+        cur = Chunk{run_base + runs, 0, 0, false};
+        last_end = -1;
+      }
+      if (b == a) {
+        cur.self = true;
+        last_end = -1;
+        continue;
+      }
+      if (cur.n_runs > 0 && last_end == bb) {
+        last_end = bb + nb;
+      } else {
+        on_run(runs, (int32_t)bb, cur.n_src);
+        ++runs;
+        cur.n_runs++;
+        last_end = bb + nb;
+      }
+      cur.n_src += (int32_t)nb;
     }
-    if (cur.n_runs > 0 && last_end == bb) {
-      last_end = bb + nb;
-    } else {
-      on_run(runs, (int32_t)bb, cur.n_src);
-      ++runs;
-      cur.n_runs++;
-      last_end = bb + nb;
-    }
-    cur.n_src += (int32_t)nb;
   }
   if (cur.n_src > 0 || cur.self || nch == 0) on_chunk(nch++, cur);
   *row_src = src;
