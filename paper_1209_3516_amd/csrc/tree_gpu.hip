@@ -61,6 +61,25 @@ __device__ __forceinline__ int classify(int a, int b, const double4 *__restrict_
 }
 
 // counts[i] = number of child pairs; emit[i] = (M2L count << 32) | P2P count.
+
+// off[m - 1] + cnt[m - 1]: the total of an exclusive scan of cnt.
+__global__ void scan_total_i32(int64_t m, const int32_t *__restrict__ off,
+                               const int32_t *__restrict__ cnt, int64_t *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = (int64_t)off[m - 1] + cnt[m - 1];
+}
+
+// The next frontier's size and the packed (M2L << 32 | P2P) count of one
+// level: last exclusive offset plus last count.
+__global__ void level_totals(int64_t nf, const int64_t *__restrict__ coff,
+                             const int64_t *__restrict__ counts,
+                             const uint64_t *__restrict__ eoff,
+                             const uint64_t *__restrict__ emit, int64_t *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = coff[nf - 1] + counts[nf - 1];
+    out[1] = (int64_t)(eoff[nf - 1] + emit[nf - 1]);
+  }
+}
+
 __global__ void dtt_count(int64_t nf, const int2 *__restrict__ frontier,
                           const double4 *__restrict__ geo, const int32_t *__restrict__ n_child,
                           double theta2, int leaf_first, int64_t *__restrict__ counts,
@@ -161,6 +180,18 @@ struct Buf {
   }
   ~Buf() {
     if (p) (void)hipFreeAsync(p, st);
+  }
+};
+
+// Two 64-bit values read back by the host: allocated pinned (once per owner)
+// so that one small device-to-host copy lands directly in them.
+struct Pinned {
+  int64_t *p = nullptr;
+  hipError_t get() {
+    return p ? hipSuccess : hipHostMalloc((void **)&p, 2 * sizeof(int64_t), hipHostMallocDefault);
+  }
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
   }
 };
 
@@ -545,10 +576,11 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
   // large pool blocks costs milliseconds); at most kKeepScratchBytes are
   // kept between calls.
   struct Scratch {
-    Buf front[2], counts, emit, coff, eoff, temp, p2p, m2l, alt;
+    Buf front[2], counts, emit, coff, eoff, temp, p2p, m2l, alt, tot;
+    Pinned host;  // the level totals, read back once per level
     size_t bytes() const {
       return front[0].bytes + front[1].bytes + counts.bytes + emit.bytes + coff.bytes +
-             eoff.bytes + temp.bytes + p2p.bytes + m2l.bytes + alt.bytes;
+             eoff.bytes + temp.bytes + p2p.bytes + m2l.bytes + alt.bytes + tot.bytes;
     }
   };
   // (a heap array that is never destroyed: no HIP call at process exit)
@@ -564,7 +596,7 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
   if (!sc) sc.reset(new Scratch);
   Buf(&front)[2] = sc->front;
   Buf &counts = sc->counts, &emit = sc->emit, &coff = sc->coff, &eoff = sc->eoff,
-      &temp = sc->temp, &p2p = sc->p2p, &m2l = sc->m2l, &alt = sc->alt;
+      &temp = sc->temp, &p2p = sc->p2p, &m2l = sc->m2l, &alt = sc->alt, &tot = sc->tot;
   int64_t nf = n_cells > 0 ? 1 : 0, n_p2p = 0, n_m2l = 0;
   TRY(front[0].reserve(sizeof(int2), st, false));
   if (nf) {
@@ -591,20 +623,17 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
                                          (int)nf, st));
     TRY(hipcub::DeviceScan::ExclusiveSum(temp.p, tb2, (uint64_t *)emit.p, (uint64_t *)eoff.p,
                                          (int)nf, st));
-    // totals = last offset + last count
-    int64_t last_c[2];
-    uint64_t last_e[2];
-    TRY(hipMemcpyAsync(&last_c[0], (int64_t *)coff.p + nf - 1, sizeof(int64_t),
-                       hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&last_c[1], (int64_t *)counts.p + nf - 1, sizeof(int64_t),
-                       hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&last_e[0], (uint64_t *)eoff.p + nf - 1, sizeof(uint64_t),
-                       hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&last_e[1], (uint64_t *)emit.p + nf - 1, sizeof(uint64_t),
-                       hipMemcpyDeviceToHost, st));
+    // totals = last offset + last count, both read back in one copy
+    TRY(tot.reserve(2 * sizeof(int64_t), st, false));
+    TRY(sc->host.get());
+    level_totals<<<1, 1, 0, st>>>(nf, (const int64_t *)coff.p, (const int64_t *)counts.p,
+                                  (const uint64_t *)eoff.p, (const uint64_t *)emit.p,
+                                  (int64_t *)tot.p);
+    TRY(hipGetLastError());
+    TRY(hipMemcpyAsync(sc->host.p, tot.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     TRY(hipStreamSynchronize(st));
-    const int64_t n_next = last_c[0] + last_c[1];
-    const uint64_t e_tot = last_e[0] + last_e[1];
+    const int64_t n_next = sc->host.p[0];
+    const uint64_t e_tot = (uint64_t)sc->host.p[1];
     const int64_t add_p2p = (int64_t)(e_tot & 0xffffffffull), add_m2l = (int64_t)(e_tot >> 32);
     TRY(front[1 - cur].reserve((n_next > 0 ? n_next : 1) * sizeof(int2), st, false));
     TRY(p2p.reserve((n_p2p + add_p2p + 1) * sizeof(uint64_t), st, true));
@@ -676,10 +705,11 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
   // traversal does; freeing large pool blocks costs milliseconds).
   struct TreeScratch {
     Buf boxes, key, idx, key2, idx2, temp, bb, nbd, lv, par, cb, nc, nch, off, gcnt, goff, gtab,
-        gacc;
+        gacc, tot;
+    Pinned host;  // scan totals read back by the host
     size_t bytes() const {
       const Buf *all[] = {&boxes, &key, &idx, &key2, &idx2, &temp, &bb, &nbd, &lv,
-                          &par, &cb, &nc, &nch, &off, &gcnt, &goff, &gtab, &gacc};
+                          &par, &cb, &nc, &nch, &off, &gcnt, &goff, &gtab, &gacc, &tot};
       size_t s = 0;
       for (const Buf *b : all) s += b->bytes;
       return s;
@@ -695,6 +725,18 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
     if (dev >= 0 && dev < kMaxDevices) sc = std::move(cache[dev]);
   }
   if (!sc) sc.reset(new TreeScratch);
+  // total of an exclusive scan (last offset + last count), one small copy
+  // into pinned memory
+  auto scan_total = [&](const int32_t *offs, const int32_t *cnts, int64_t m, int64_t *res) -> int {
+    TRY(sc->tot.reserve(sizeof(int64_t), st, false));
+    TRY(sc->host.get());
+    scan_total_i32<<<1, 1, 0, st>>>(m, offs, cnts, (int64_t *)sc->tot.p);
+    TRY(hipGetLastError());
+    TRY(hipMemcpyAsync(sc->host.p, sc->tot.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    *res = sc->host.p[0];
+    return 0;
+  };
   auto keep = [&]() {
     if (sc->bytes() <= kKeepScratchBytes && dev >= 0 && dev < kMaxDevices) {
       std::lock_guard<std::mutex> guard(cache_mu);
@@ -802,11 +844,8 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
     TRY(temp.reserve(tsb, st, false));
     TRY(hipcub::DeviceScan::ExclusiveSum(temp.p, tsb, (int32_t *)nch.p, (int32_t *)off.p, (int)m,
                                          st));
-    int32_t last[2];
-    TRY(hipMemcpyAsync(&last[0], (int32_t *)off.p + m - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&last[1], (int32_t *)nch.p + m - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
-    const int64_t added = (int64_t)last[0] + last[1];
+    int64_t added = 0;
+    if (int rc = scan_total((const int32_t *)off.p, (const int32_t *)nch.p, m, &added)) return rc;
     TRY(grow(c1 + added));
     write_children<<<blocks_for(m, 256), 256, 0, st>>>(
         c0, c1, level, skeys, (const int32_t *)nch.p, (const int32_t *)off.p, c1,
@@ -837,11 +876,9 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
     TRY(temp.reserve(tsb, st, false));
     TRY(hipcub::DeviceScan::ExclusiveSum(temp.p, tsb, (int32_t *)gcnt.p, (int32_t *)goff.p,
                                          (int)ncells, st));
-    int32_t last[2];
-    TRY(hipMemcpyAsync(&last[0], (int32_t *)goff.p + ncells - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&last[1], (int32_t *)gcnt.p + ncells - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
-    const int64_t nchunks = (int64_t)last[0] + last[1];
+    int64_t nchunks = 0;
+    if (int rc = scan_total((const int32_t *)goff.p, (const int32_t *)gcnt.p, ncells, &nchunks))
+      return rc;
     TRY(gtab.reserve(nchunks * 8, st, false));
     geo_chunk_fill<<<gb, 256, 0, st>>>(ncells, (const int32_t *)gcnt.p, (const int32_t *)goff.p,
                                        (uint64_t *)gtab.p, (uint64_t *)gacc.p);
