@@ -2,10 +2,9 @@
 // the same chunking, run merging, item order and partial-slot layout as the
 // host builder, so both give the same plan entry for entry.
 //
-// One thread per leaf walks the leaf's P2P row twice: a counting pass (runs,
-// chunks, source bodies, body pairs) and, after prefix sums give every leaf
-// its offsets, a writing pass.  The walk is sequential (each chunk and run
-// depends on the ones before), with the row's entries loaded in batches.
+// One 64-lane wave per leaf walks the leaf's P2P row twice: a counting pass
+// (runs, chunks, source bodies, body pairs) and, after prefix sums give every
+// leaf its offsets, a writing pass.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -18,76 +17,118 @@ namespace dev {
 
 namespace {
 
-constexpr int kWalkBatch = 8;
-
 struct Chunk {
   int32_t run_begin, n_runs, n_src;
   bool self;
 };
 
-// Walk row `a` (leaf with nA bodies starting at bA).  on_run(body, prefix)
-// is called for each new run, on_chunk(index, chunk) for each finished chunk.
-// Returns the number of chunks; *row_src and *pairs get the source bodies and
-// body pairs of the row.
-template <class OnRun, class OnChunk>
-__device__ int walk_row(int32_t a, int64_t bA, int64_t nA, const int64_t *__restrict__ ptr,
-                        const int32_t *__restrict__ col, const int32_t *__restrict__ body_begin,
-                        const int32_t *__restrict__ n_body, int32_t run_base, int64_t *row_src,
-                        int64_t *pairs, OnRun on_run, OnChunk on_chunk) {
-  int nch = 0;
-  int32_t runs = 0;  // runs of this row so far
-  Chunk cur{run_base, 0, 0, false};
-  int64_t last_end = -1;
-  int64_t src = 0, pr = 0;
-  // Entries are read eight at a time (the column, then the source leaf's
-  // bodies), so a long row costs two memory round trips per eight entries
-  // rather than per entry; they are then taken in order, as on the host.
-  const int64_t e_end = ptr[a + 1];
-  for (int64_t e0 = ptr[a]; e0 < e_end; e0 += kWalkBatch) {
-    int32_t bq[kWalkBatch];
-    int32_t nbq[kWalkBatch], bbq[kWalkBatch];
+// Inclusive sum over the 64 lanes of a wave, in lane order.
+__device__ __forceinline__ int wave_incl_sum(int v) {
+  const int lane = threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < kWalkBatch; ++k) bq[k] = e0 + k < e_end ? col[e0 + k] : 0;
-#pragma unroll
-    for (int k = 0; k < kWalkBatch; ++k) {
-      nbq[k] = e0 + k < e_end ? n_body[bq[k]] : 0;
-      bbq[k] = e0 + k < e_end ? body_begin[bq[k]] : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < kWalkBatch; ++k) {
-      if (e0 + k >= e_end) break;
-      const int32_t b = bq[k];
-      const int64_t nb = nbq[k], bb = bbq[k];
-      src += nb;
-      pr += nA * nb - (b == a ? nA : 0);
-      const bool contiguous = (b != a) && cur.n_runs > 0 && last_end == bb;
-      const bool full = (cur.n_src + (cur.self ? nA : 0) + nb > kP2PChunkSources &&
-                         (cur.n_src > 0 || cur.self)) ||
-                        (!contiguous && b != a && cur.n_runs >= kP2PMaxRuns);
-      if (full) {
-        on_chunk(nch++, cur);
-        cur = Chunk{run_base + runs, 0, 0, false};
-        last_end = -1;
-      }
-      if (b == a) {
-        cur.self = true;
-        last_end = -1;
-        continue;
-      }
-      if (cur.n_runs > 0 && last_end == bb) {
-        last_end = bb + nb;
-      } else {
-        on_run(runs, (int32_t)bb, cur.n_src);
-        ++runs;
-        cur.n_runs++;
-        last_end = bb + nb;
-      }
-      cur.n_src += (int32_t)nb;
-    }
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(v, d);
+    if (lane >= d) v += u;
   }
-  if (cur.n_src > 0 || cur.self || nch == 0) on_chunk(nch++, cur);
-  *row_src = src;
-  *pairs = pr;
+  return v;
+}
+
+__device__ __forceinline__ long long wave_sum(long long v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+// Walk row `a` (leaf with nA bodies) with one 64-lane wave; every lane calls
+// this with the same arguments.  The host builder's rule, taken entry by
+// entry in row order: an entry extends the current run when its bodies
+// follow the previous entry's in memory (neither being the leaf itself), else
+// starts a run; the chunk is closed before an entry when its sources would
+// pass kP2PChunkSources (the leaf's own bodies count if it is in the chunk)
+// or when it would start run kP2PMaxRuns + 1.  Here the row is taken 64
+// entries at a time: scans over the lanes give each entry the chunk's
+// sources, self flag and runs before it, a ballot finds the first entry that
+// closes the chunk, and the scans restart there (a chunk's first entry never
+// closes it, so every pass moves forward).  on_run(k, body, prefix) is called
+// (by the lanes holding them, in no particular order) for each run k of the
+// row; on_chunk(c, chunk) by all lanes for each chunk, in order.  Returns
+// the number of chunks; *row_src and *pairs (on every lane) get the row's
+// source bodies and body pairs.
+template <class OnRun, class OnChunk>
+__device__ int walk_row(int32_t a, int64_t nA, const int64_t *__restrict__ ptr,
+                        const int32_t *__restrict__ col, const int32_t *__restrict__ body_begin,
+                        const int32_t *__restrict__ n_body, int32_t run_base, int32_t *row_runs,
+                        int64_t *row_src, int64_t *pairs, OnRun on_run, OnChunk on_chunk) {
+  const int lane = threadIdx.x;
+  const int64_t e_beg = ptr[a], E = ptr[a + 1] - e_beg;
+  int64_t s = 0;                    // first entry of the current chunk (row order)
+  int src_acc = 0, runs_acc = 0;    // the chunk's sources and runs before this segment
+  bool self_acc = false;            // ... and whether it holds the leaf itself
+  int32_t runs_row = 0;             // runs of the row before the current chunk
+  int nch = 0;
+  bool prev_self = true;            // the entry before the segment (none: no adjacency)
+  int64_t prev_end = -1;
+  long long my_src = 0, my_pairs = 0;
+  for (int64_t seg = 0; seg < E; seg += 64) {
+    const int64_t e = seg + lane;
+    const bool valid = e < E;
+    // lanes past the row's end read entry 0 and the leaf itself (E >= 1 here)
+    // and then count as empty
+    const int32_t bcol = col[e_beg + (valid ? e : 0)];
+    const int32_t b = valid ? bcol : a;
+    const int nb = valid ? n_body[b] : 0;
+    const int bb = valid ? body_begin[b] : 0;
+    const bool self = valid && b == a;
+    my_src += nb;
+    my_pairs += (long long)nA * nb - (self ? nA : 0);
+    const int up_self = __shfl_up(self ? 1 : 0, 1);
+    const int up_end = __shfl_up(bb + nb, 1);
+    const bool p_self = lane == 0 ? prev_self : up_self != 0;
+    const int64_t p_end = lane == 0 ? prev_end : (int64_t)up_end;
+    const int last = (int)(E - 1 - seg < 63 ? E - 1 - seg : 63);
+    for (;;) {
+      const bool in = valid && e >= s;
+      const bool adj = in && e > s && !self && !p_self && p_end == (int64_t)bb;
+      const bool newrun = in && !self && !adj;
+      const int c_src = in && !self ? nb : 0;
+      const int i_src = wave_incl_sum(c_src);
+      const int i_self = wave_incl_sum(in && self ? 1 : 0);
+      const int i_runs = wave_incl_sum(newrun ? 1 : 0);
+      const int src_before = src_acc + i_src - c_src;
+      const bool self_before = self_acc || i_self - (in && self ? 1 : 0) > 0;
+      const int runs_before = runs_acc + i_runs - (newrun ? 1 : 0);
+      const bool full =
+          in && (((int64_t)src_before + (self_before ? nA : 0) + nb > kP2PChunkSources &&
+                  (src_before > 0 || self_before)) ||
+                 (!adj && !self && runs_before >= kP2PMaxRuns));
+      const unsigned long long fm = __ballot(full);
+      const int stop = fm ? __ffsll((long long)fm) - 1 : 64;
+      if (newrun && lane < stop) on_run(runs_row + runs_before, bb, src_before);
+      if (fm == 0) {  // the chunk goes on past this segment
+        src_acc += __shfl(i_src, last);
+        self_acc = self_acc || __shfl(i_self, last) > 0;
+        runs_acc += __shfl(i_runs, last);
+        break;
+      }
+      const Chunk ch{run_base + runs_row, __shfl(runs_before, stop), __shfl(src_before, stop),
+                     __shfl(self_before ? 1 : 0, stop) != 0};
+      on_chunk(nch++, ch);
+      runs_row += ch.n_runs;
+      s = seg + stop;
+      src_acc = 0;
+      runs_acc = 0;
+      self_acc = false;
+    }
+    prev_self = __shfl(self ? 1 : 0, last) != 0;
+    prev_end = __shfl(bb + nb, last);
+  }
+  if (src_acc > 0 || self_acc || nch == 0) {
+    on_chunk(nch++, Chunk{run_base + runs_row, runs_acc, src_acc, self_acc});
+    runs_row += runs_acc;
+  }
+  *row_runs = runs_row;
+  *row_src = wave_sum(my_src);
+  *pairs = wave_sum(my_pairs);
   return nch;
 }
 
@@ -97,60 +138,94 @@ __global__ void leaf_flags(int64_t nc, const int32_t *__restrict__ n_child,
   if (c < nc) flag[c] = n_child[c] == 0;
 }
 
-// Per leaf: cell, run count, item count, partial slots, chunks; row maxima
-// and pair totals by integer atomics (order-independent).
-__global__ void plan_count(int64_t nc, const int32_t *__restrict__ n_child,
-                           const int32_t *__restrict__ leaf_of, const int64_t *__restrict__ ptr,
-                           const int32_t *__restrict__ col, const int32_t *__restrict__ body_begin,
-                           const int32_t *__restrict__ n_body, int32_t *__restrict__ leaf_cell,
-                           int32_t *__restrict__ nruns, int32_t *__restrict__ nitems,
-                           int32_t *__restrict__ nparts, int32_t *__restrict__ nchunk,
-                           unsigned long long *__restrict__ totals) {
-  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Per leaf (one 64-lane wave per cell; other cells return): cell, run
+// count, item count, partial slots, chunks, row sources and body pairs.
+__global__ __launch_bounds__(64) void plan_count(
+    int64_t nc, const int32_t *__restrict__ n_child, const int32_t *__restrict__ leaf_of,
+    const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ body_begin, const int32_t *__restrict__ n_body,
+    int32_t *__restrict__ leaf_cell, int32_t *__restrict__ nruns, int32_t *__restrict__ nitems,
+    int32_t *__restrict__ nparts, int32_t *__restrict__ nchunk, int64_t *__restrict__ lsrc,
+    int64_t *__restrict__ lpairs) {
+  const int64_t a = blockIdx.x;
   if (a >= nc || n_child[a] != 0) return;
   const int32_t leaf = leaf_of[a];
-  const int64_t nA = n_body[a], bA = body_begin[a];
+  const int64_t nA = n_body[a];
   int32_t runs = 0;
   int64_t src, pairs;
   const int nch = walk_row(
-      (int32_t)a, bA, nA, ptr, col, body_begin, n_body, 0, &src, &pairs,
-      [&](int32_t, int32_t, int32_t) { ++runs; }, [&](int, const Chunk &) {});
+      (int32_t)a, nA, ptr, col, body_begin, n_body, 0, &runs, &src, &pairs,
+      [&](int32_t, int32_t, int32_t) {}, [&](int, const Chunk &) {});
+  if (threadIdx.x != 0) return;
   leaf_cell[leaf] = (int32_t)a;
   nruns[leaf] = runs;
   nitems[leaf] = (int32_t)((nA + 63) / 64) * nch;
   nparts[leaf] = (int32_t)(nch * nA);
   nchunk[leaf] = nch;
-  atomicMax(&totals[0], (unsigned long long)src);
-  atomicAdd(&totals[1], (unsigned long long)pairs);
-  atomicAdd(&totals[2], (unsigned long long)runs);
-  atomicAdd(&totals[3], (unsigned long long)((nA + 63) / 64) * nch);
-  atomicAdd(&totals[4], (unsigned long long)nch * nA);
+  lsrc[leaf] = src;
+  lpairs[leaf] = pairs;
 }
 
-__global__ void plan_write(int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
-                           const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                           const int32_t *__restrict__ body_begin,
-                           const int32_t *__restrict__ n_body, const int32_t *__restrict__ run_off,
-                           const int32_t *__restrict__ item_off,
-                           const int32_t *__restrict__ pbase, const int32_t *__restrict__ nchunk,
-                           PlanLayouts layouts, P2PItem *__restrict__ items,
-                           int32_t *__restrict__ run_body, int32_t *__restrict__ run_prefix,
-                           int32_t *__restrict__ body_leaf) {
-  const int64_t leaf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// totals: [0] max row sources, [1] body pairs, [2] runs, [3] items, [4]
+// partial slots.  One block; each thread takes leaves t, t + 1024, ... and
+// the block sums in a fixed tree.
+__global__ __launch_bounds__(1024) void plan_totals(
+    int64_t n_leaves, const int64_t *__restrict__ lsrc, const int64_t *__restrict__ lpairs,
+    const int32_t *__restrict__ nruns, const int32_t *__restrict__ nitems,
+    const int32_t *__restrict__ nparts, unsigned long long *__restrict__ totals) {
+  __shared__ unsigned long long red[5][1024];
+  const int t = threadIdx.x;
+  unsigned long long v[5] = {0, 0, 0, 0, 0};
+  for (int64_t l = t; l < n_leaves; l += 1024) {
+    v[0] = v[0] > (unsigned long long)lsrc[l] ? v[0] : (unsigned long long)lsrc[l];
+    v[1] += (unsigned long long)lpairs[l];
+    v[2] += (unsigned long long)nruns[l];
+    v[3] += (unsigned long long)nitems[l];
+    v[4] += (unsigned long long)nparts[l];
+  }
+  for (int k = 0; k < 5; ++k) red[k][t] = v[k];
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (t < h) {
+      red[0][t] = red[0][t] > red[0][t + h] ? red[0][t] : red[0][t + h];
+      for (int k = 1; k < 5; ++k) red[k][t] += red[k][t + h];
+    }
+    __syncthreads();
+  }
+  if (t < 5) totals[t] = red[t][0];
+}
+
+// The plan entries of each leaf (one 64-lane wave per leaf), at the offsets
+// the counts gave.  Runs and chunks beyond the counted ones are not written.
+__global__ __launch_bounds__(64) void plan_write(
+    int64_t n_leaves, const int32_t *__restrict__ leaf_cell, const int64_t *__restrict__ ptr,
+    const int32_t *__restrict__ col, const int32_t *__restrict__ body_begin,
+    const int32_t *__restrict__ n_body, const int32_t *__restrict__ nruns,
+    const int32_t *__restrict__ run_off, const int32_t *__restrict__ item_off,
+    const int32_t *__restrict__ pbase, const int32_t *__restrict__ nchunk, PlanLayouts layouts,
+    P2PItem *__restrict__ items, int32_t *__restrict__ run_body,
+    int32_t *__restrict__ run_prefix, int32_t *__restrict__ body_leaf) {
+  const int64_t leaf = blockIdx.x;
   if (leaf >= n_leaves) return;
+  const int lane = threadIdx.x;
   const int32_t a = leaf_cell[leaf];
   const int64_t nA = n_body[a], bA = body_begin[a];
   const int32_t r0 = run_off[leaf], i0 = item_off[leaf], pb = pbase[leaf], nch = nchunk[leaf];
+  const int32_t run_cap = nruns[leaf];
   const int64_t ng = (nA + 63) / 64;
+  int32_t runs = 0;
   int64_t src, pairs;
   walk_row(
-      a, bA, nA, ptr, col, body_begin, n_body, r0, &src, &pairs,
+      a, nA, ptr, col, body_begin, n_body, r0, &runs, &src, &pairs,
       [&](int32_t k, int32_t body, int32_t prefix) {
-        run_body[r0 + k] = body;
-        run_prefix[r0 + k] = prefix;
+        if (k < run_cap) {
+          run_body[r0 + k] = body;
+          run_prefix[r0 + k] = prefix;
+        }
       },
       [&](int c, const Chunk &ch) {
-        for (int64_t gi = 0; gi < ng; ++gi) {
+        if (c >= nch) return;
+        for (int64_t gi = lane; gi < ng; gi += 64) {
           const int64_t g = 64 * gi;
           const int nt = (int)(nA - g < 64 ? nA - g : 64);
           P2PItem it;
@@ -165,12 +240,9 @@ __global__ void plan_write(int64_t n_leaves, const int32_t *__restrict__ leaf_ce
           items[i0 + gi * nch + c] = it;
         }
       });
-  for (int64_t i = bA; i < bA + nA; ++i) body_leaf[i] = (int32_t)leaf;
+  for (int64_t i = bA + lane; i < bA + nA; i += 64) body_leaf[i] = (int32_t)leaf;
 }
 
-__global__ void plan_zero_totals(unsigned long long *__restrict__ totals) {
-  if (threadIdx.x < 8) totals[threadIdx.x] = 0;
-}
 
 }  // namespace
 
@@ -194,14 +266,17 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
   int32_t *leaf_flag = nullptr, *leaf_of = nullptr, *nruns = nullptr, *nitems = nullptr,
           *nparts = nullptr, *run_off = nullptr, *item_off = nullptr;
   unsigned long long *totals = nullptr;
+  int64_t *lsrc = nullptr, *lpairs = nullptr;
   void *scan_tmp = nullptr;
   // temporaries from the stream-ordered pool, freed in stream order
   auto free_temps = [&]() {
-    void *ps[] = {leaf_flag, leaf_of, nruns, nitems, nparts, run_off, item_off, totals, scan_tmp};
+    void *ps[] = {leaf_flag, leaf_of, nruns,  nitems,   nparts, run_off,
+                  item_off,  totals,  lsrc,   lpairs,   scan_tmp};
     for (void *p : ps)
       if (p) (void)hipFreeAsync(p, st);
     leaf_flag = leaf_of = nruns = nitems = nparts = run_off = item_off = nullptr;
     totals = nullptr;
+    lsrc = lpairs = nullptr;
     scan_tmp = nullptr;
   };
   auto release = [&]() {
@@ -218,6 +293,8 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
   PTRY(hipMallocAsync((void **)&run_off, nl * 4, st));
   PTRY(hipMallocAsync((void **)&item_off, nl * 4, st));
   PTRY(hipMallocAsync((void **)&totals, 8 * sizeof(unsigned long long), st));
+  PTRY(hipMallocAsync((void **)&lsrc, nl * 8, st));
+  PTRY(hipMallocAsync((void **)&lpairs, nl * 8, st));
   PTRY(hipMalloc(&out.leaf_cell, nl * 4));
   PTRY(hipMalloc(&out.leaf_pbase, nl * 4));
   PTRY(hipMalloc(&out.leaf_nchunk, nl * 4));
@@ -229,21 +306,20 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
   tb = tb > tb2 ? tb : tb2;
   PTRY(hipMallocAsync(&scan_tmp, tb > 0 ? tb : 1, st));
 
-  const unsigned bc = (unsigned)((nc + 255) / 256), bl = (unsigned)((nl + 255) / 256);
+  const unsigned bc = (unsigned)((nc + 255) / 256);
   leaf_flags<<<bc, 256, 0, st>>>((int64_t)nc, n_child, leaf_flag);
   PTRY(hipGetLastError());
   tb2 = tb;
   PTRY(hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb2, leaf_flag, leaf_of, (int)nc, st));
-  // totals: [0] max row sources, [1] body pairs, [2] runs, [3] items, [4] partial
-  // slots, all by 64-bit integer atomics
-  plan_zero_totals<<<1, 8, 0, st>>>(totals);
+  plan_count<<<(unsigned)nc, 64, 0, st>>>((int64_t)nc, n_child, leaf_of, p2p_ptr, p2p_col,
+                                           body_begin, n_body, out.leaf_cell, nruns, nitems,
+                                           nparts, out.leaf_nchunk, lsrc, lpairs);
   PTRY(hipGetLastError());
-  plan_count<<<bc, 256, 0, st>>>((int64_t)nc, n_child, leaf_of, p2p_ptr, p2p_col, body_begin,
-                                  n_body, out.leaf_cell, nruns, nitems, nparts, out.leaf_nchunk,
-                                  totals);
+  plan_totals<<<1, 1024, 0, st>>>((int64_t)nl, lsrc, lpairs, nruns, nitems, nparts, totals);
   PTRY(hipGetLastError());
   unsigned long long host_tot[8] = {};
-  PTRY(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, st));
+  PTRY(hipMemcpyAsync(host_tot, totals, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                      st));
   PTRY(hipStreamSynchronize(st));
   out.n_leaves = (int64_t)nl;
   out.max_row_sources = (int64_t)host_tot[0];
@@ -265,9 +341,10 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
   PTRY(hipMalloc(&out.items, (size_t)(out.n_items > 0 ? out.n_items : 1) * sizeof(P2PItem)));
   PTRY(hipMalloc(&out.run_body, (size_t)(out.n_runs > 0 ? out.n_runs : 1) * 4));
   PTRY(hipMalloc(&out.run_prefix, (size_t)(out.n_runs > 0 ? out.n_runs : 1) * 4));
-  plan_write<<<bl, 256, 0, st>>>((int64_t)nl, out.leaf_cell, p2p_ptr, p2p_col, body_begin, n_body,
-                                 run_off, item_off, out.leaf_pbase, out.leaf_nchunk, layouts,
-                                 out.items, out.run_body, out.run_prefix, out.body_leaf);
+  plan_write<<<(unsigned)nl, 64, 0, st>>>((int64_t)nl, out.leaf_cell, p2p_ptr, p2p_col,
+                                           body_begin, n_body, nruns, run_off, item_off,
+                                           out.leaf_pbase, out.leaf_nchunk, layouts, out.items,
+                                           out.run_body, out.run_prefix, out.body_leaf);
   PTRY(hipGetLastError());
   free_temps();
   PTRY(hipStreamSynchronize(st));
