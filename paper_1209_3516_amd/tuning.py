@@ -55,9 +55,12 @@ class Problem:
         if tree is None:
             tree = fmm.Tree.from_device(xd, ncrit) if device else fmm.Tree(self.x, ncrit)
         t1 = time.perf_counter()
-        # timed runs report the median of three list builds
+        # timed runs report the median of three list builds (each previous
+        # one freed before the next is timed)
         builds = []
+        lists = None
         for _ in range(3 if timed else 1):
+            lists = None
             tb = time.perf_counter()
             lists = fmm.Lists(tree, theta, device=device)
             builds.append(time.perf_counter() - tb)
