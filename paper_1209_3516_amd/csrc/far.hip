@@ -11,7 +11,11 @@
 // The derivatives D^m G come from the recurrence for a_m = D^m G / m!:
 //   |m| r^2 a_m = -(2|m|-1) sum_d R_d a_{m-e_d} - (|m|-1) sum_d a_{m-2e_d}.
 // Translations are computed on the fly per pair rather than loaded as
-// precomputed matrices (section 3.1: bytes per flop keep falling).
+// precomputed matrices (section 3.1: bytes per flop keep falling).  M2L works
+// on harmonic-reduced terms: since G is harmonic, the multipole is first
+// folded onto its p^2 terms of z exponent <= 1 and only the p^2 local terms
+// of z exponent <= 1 are contracted; the others follow exactly (the
+// identities are stated with the reduced contraction table).
 //
 // All index arithmetic over multi-indices is resolved at compile time: the
 // kernels are templated on p and every loop over coefficients is unrolled
