@@ -204,7 +204,9 @@ int fmm_traverse_hybrid(const fmm_tree *t, double theta, unsigned flags, int m2p
  * the first evaluation uploads nothing.  The host copy of the lists is made
  * by the first fmm_lists_view on the handle (a blocking copy; do not call it
  * concurrently with other calls on the same handle).  Errors as
- * fmm_traverse, plus FMM_EDEVICE.
+ * fmm_traverse, plus FMM_EDEVICE, and FMM_EINVAL when a list or one level of
+ * the traversal would hold 2^31 or more cell pairs (the device sort counts in
+ * 32 bits; fmm_traverse has no such limit).
  */
 int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out,
                      void *stream);

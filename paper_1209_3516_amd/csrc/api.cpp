@@ -928,6 +928,13 @@ int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists 
       if (std::getenv("FMM_LOG"))
         std::fprintf(stderr, "[fmm] fmm_traverse_gpu: %.2f ms after the traversal\n",
                      ms_since(t_call));
+      if (rc == fmmlib::dev::kTraverseTooLarge) {
+        free_dl();
+        delete l;
+        set_error("fmm_traverse_gpu: a list or a traversal level would hold 2^31 or more cell "
+                  "pairs; fmm_traverse (host) builds lists of that size");
+        return FMM_EINVAL;
+      }
       if (rc != 0) {
         free_dl();
         delete l;

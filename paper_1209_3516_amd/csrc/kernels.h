@@ -100,6 +100,9 @@ struct DeviceLists {
 
 // Dual tree traversal on the GPU with the rules of the host traversal.
 // geo: [n_cells] double4 (centre, radius); synchronises `stream`.
+// Returns kTraverseTooLarge (no HIP error) when a frontier or a list would
+// reach 2^31 entries (the device sort and scans count in 32 bits).
+constexpr int kTraverseTooLarge = -2;
 int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_begin,
                       const int32_t *n_child, double theta, bool leaf_first, void *stream,
                       DeviceLists &out);

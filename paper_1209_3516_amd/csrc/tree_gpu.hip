@@ -14,6 +14,7 @@
 // ascending); the radix sort looks at the 2 kb low bits only.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <memory>
 #include <mutex>
@@ -603,8 +604,16 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
     const int2 root = make_int2(0, 0);
     TRY(hipMemcpyAsync(front[0].p, &root, sizeof(int2), hipMemcpyHostToDevice, st));
   }
+  // Counts stay below 2^31 (the sort and the scans take 32-bit sizes);
+  // FMM_TRAVERSE_LIMIT lowers the limit so that the failure path can be tested.
+  int64_t limit = INT32_MAX;
+  if (const char *lim = std::getenv("FMM_TRAVERSE_LIMIT")) {
+    const long long v = std::atoll(lim);
+    if (v > 0 && v < limit) limit = v;
+  }
   int cur = 0;
   while (nf > 0) {
+    if (nf > limit) return kTraverseTooLarge;
     TRY(counts.reserve(nf * sizeof(int64_t), st, false));
     TRY(emit.reserve(nf * sizeof(uint64_t), st, false));
     TRY(coff.reserve(nf * sizeof(int64_t), st, false));
@@ -635,6 +644,7 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
     const int64_t n_next = sc->host.p[0];
     const uint64_t e_tot = (uint64_t)sc->host.p[1];
     const int64_t add_p2p = (int64_t)(e_tot & 0xffffffffull), add_m2l = (int64_t)(e_tot >> 32);
+    if (n_p2p + add_p2p > limit || n_m2l + add_m2l > limit) return kTraverseTooLarge;
     TRY(front[1 - cur].reserve((n_next > 0 ? n_next : 1) * sizeof(int2), st, false));
     TRY(p2p.reserve((n_p2p + add_p2p + 1) * sizeof(uint64_t), st, true));
     TRY(m2l.reserve((n_m2l + add_m2l + 1) * sizeof(uint64_t), st, true));

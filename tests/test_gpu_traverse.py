@@ -222,3 +222,22 @@ def test_target_ranges_reassemble_the_full_evaluation(kind, n, ncrit, theta, p, 
     expect = np.zeros(m, bool)
     expect[perm[b0:b1]] = True
     np.testing.assert_array_equal(written, expect)
+
+
+def test_gpu_traversal_size_limit(monkeypatch):
+    """Lists or levels of 2^31 cell pairs or more are refused with a message
+    (forced here with a lowered limit); the next traversal works."""
+    x = W.uniform_cube(20_000, seed=96)
+    t = fmm.Tree(x, 16)
+    monkeypatch.setenv("FMM_TRAVERSE_LIMIT", "1000")
+    with pytest.raises(fmm.FMMError) as e:
+        fmm.Lists(t, 0.4, device=True)
+    assert e.value.code == fmm.FMM_EINVAL and "2^31" in str(e.value)
+    monkeypatch.delenv("FMM_TRAVERSE_LIMIT")
+    gpu = fmm.Lists(t, 0.4, device=True)
+    host = fmm.Lists(t, 0.4)
+    for k in (fmm.FMM_P2P, fmm.FMM_M2L):
+        hp, hc = host.csr(k)
+        gp, gc = gpu.csr(k)
+        np.testing.assert_array_equal(hp, gp)
+        np.testing.assert_array_equal(hc, gc)
