@@ -58,7 +58,6 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
   using V4 = typename Vec<Real>::V4;
   const int lane = threadIdx.x;
   const Real far = Vec<Real>::kFar;
-  constexpr int NQ = kNB / 64 + 1;  // staged positions per lane (the last 64 are padding)
   // The plain partial of a stream is added into (S, C) every `kb` batches, so
   // that it covers at least 64 sources when a stream's share of one batch is
   // smaller (kb = ceil(K / 8)).
@@ -66,6 +65,22 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
   Real p[R][4];
 #pragma unroll
   for (int r = 0; r < R; ++r) p[r][0] = p[r][1] = p[r][2] = p[r][3] = Real(0);
+  // Far-away zero-charge bodies for the positions past a batch.  The row
+  // after the kNB staged positions never holds a source, so it is padded once.
+  auto pad = [&](int slot) {
+    V4 fb;
+    fb.x = far;
+    fb.y = far;
+    fb.z = far;
+    fb.w = Real(0);
+    src[slot] = fb;
+    if constexpr (MODE == kDipoles) {
+      V4 z;
+      z.x = z.y = z.z = z.w = Real(0);
+      srcd[slot] = z;
+    }
+  };
+  pad(kNB + lane);
   int batch = 0;
   for (int off = 0; off < nsrc; off += kNB, ++batch) {
     const int nb = min(kNB, nsrc - off);
@@ -106,21 +121,10 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
         for (int q = 0; q < NL; ++q) srcd[q * 64 + lane] = v[q];
       }
     }
+    if (nb < kNB) {  // a partial batch: pad its rows past nb
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      if (q * 64 + lane >= nb) {
-        V4 fb;
-        fb.x = far;
-        fb.y = far;
-        fb.z = far;
-        fb.w = Real(0);
-        src[q * 64 + lane] = fb;
-        if constexpr (MODE == kDipoles) {
-          V4 z;
-          z.x = z.y = z.z = z.w = Real(0);
-          srcd[q * 64 + lane] = z;
-        }
-      }
+      for (int q = 0; q < NL; ++q)
+        if (q * 64 + lane >= nb) pad(q * 64 + lane);
     }
     __syncthreads();
     const int iters = (nb + K - 1) / K;
