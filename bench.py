@@ -80,8 +80,9 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU sharding of "
-              "the evaluation is a design note, not an implemented path", file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus 1); sharding the evaluation over several "
+              "GPUs is not implemented (one GPU's share is timed with --share-gpus)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -8,8 +8,9 @@ reference is the library's FP64 direct sum on the GPU, the error is taken over
 a set of target bodies, and the search is a coarse scan of theta followed by
 bisection inside the bracketing step.
 
-Errors (R12 of the design notes): e_phi, e_grad, and the paper's force error
-e_F with F_i = -q_i grad_i.
+Errors: relative L2 norms over the sampled targets against the FP64 direct
+sum, of phi (e_phi), of grad phi (e_grad) and of the paper's force
+F_i = -q_i grad_i (e_F).
 """
 import time
 
