@@ -123,8 +123,7 @@ typedef struct fmm_lists_stats_t {
   int64_t p2p_entries; /* leaf pairs in the P2P list */
   int64_t m2l_entries; /* cell pairs in the M2L list */
   int64_t p2p_pairs;   /* body-body interactions: sum over entries n_A*n_B, minus n_A for (A,A) */
-  int64_t p2p_work_items; /* GPU work items of the P2P kernel (host-built lists: 0 before
-                             the first evaluation) */
+  int64_t p2p_work_items; /* GPU work items of the P2P kernel (one wave each) */
   int64_t p2p_max_row_sources; /* largest number of source bodies of one target leaf */
   int64_t m2p_entries; /* cell pairs in the M2P list (hybrid lists; else 0) */
 } fmm_lists_stats_t;
@@ -173,7 +172,12 @@ void fmm_tree_free(fmm_tree *t);
  * of children; otherwise the cell with the larger radius is split (equal radii:
  * the lower-numbered one), never a leaf.  The lists are symmetric.
  * flags: FMM_MAC_FIRST (default) or FMM_LEAF_FIRST.
- * Output: two CSR lists (P2P, M2L), one row per target cell, sources ascending.
+ * Output: two CSR lists (P2P, M2L), one row per target cell, sources ascending,
+ * and the work plan of the P2P kernel (targets in groups of at most 64 per
+ * leaf, sources in chunks of contiguous runs), which the first evaluation
+ * uploads.  FMM_EINVAL when that plan would hold 2^31 or more runs, work
+ * items or partial sums (it indexes them with 32-bit integers; the
+ * environment variable FMM_PLAN_LIMIT=K lowers the limit, for tests).
  * Host only: no GPU is touched.
  */
 int fmm_traverse(const fmm_tree *t, double theta, unsigned flags, fmm_lists **out);
@@ -222,7 +226,15 @@ int fmm_lists_stats(const fmm_lists *l, fmm_lists_stats_t *s);
 void fmm_lists_free(fmm_lists *l);
 
 /*
- * Forward evaluation (all of P2M, M2M, M2L, L2L, L2P and P2P) on one GPU.
+ * Forward evaluation on one GPU: the evaluation phase of the method, i.e. the
+ * kernels the paper names (section 3.3 and the list of kernels timed with
+ * Table 4): P2M on every leaf and M2M up the tree (upward pass), M2L over the
+ * M2L list and P2P over the P2P list (the pairs the dual tree traversal of
+ * Algorithms 3 and 4 produced), L2L down the tree and L2P at every body, with
+ * the near (P2P) and far (L2P) fields added per body.  The expansions are the
+ * Cartesian Taylor series of section 3.1 (Table 2) truncated at total degree
+ * p - 1, so an accepted pair's error falls as theta^p (section 3.2).  P2P is
+ * the direct sum of section 3.4 (potential and gradient of q_j / r).
  *   q_dev    device, [n] charges in user order (float for FMM_MIXED, double for FMM_FP64)
  *   phi_dev  device, [n] potentials out (same dtype)
  *   grad_dev device, [n][3] gradients out (same dtype), or NULL
@@ -271,7 +283,9 @@ int fmm_partition_targets(const fmm_tree *t, const fmm_lists *l, int n_parts, do
 
 /*
  * Backward of L = sum_i w_i phi_i + sum_i v_i . grad_i for the forward above,
- * with the tree, lists, centres and radii held fixed.  The method is linear in
+ * with the tree, lists, centres and radii held fixed.  (The paper evaluates
+ * the forward only; this is the adjoint of the discrete method of sections
+ * 3.1 to 3.4 with the traversal's output frozen.)  The method is linear in
  * q and its far-field operator is symmetric (the lists are symmetric), so
  *   dL/dq_j = Phi_j           Phi: potential of charges w plus dipoles -v
  *                             (a dipole s at x_j has potential s.(x_j - y)/|x_j - y|^3)
@@ -294,7 +308,9 @@ int fmm_evaluate_backward(const fmm_tree *t, const fmm_lists *l, const fmm_eval_
 
 /*
  * Direct O(N) sum per target in FP64 on the GPU (zero-distance pairs skipped),
- * the reference the method approximates; used to report accuracy.
+ * the reference the method approximates; used to report accuracy as the
+ * relative L2 error against direct summation (the error measure of Table 4
+ * and section 3.5).
  *   xyz_dev     device, double [n][3] positions (user order)
  *   q_dev       device, double [n] charges
  *   targets_dev device, int64 [m] target indices in [0, n)

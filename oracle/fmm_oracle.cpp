@@ -429,6 +429,12 @@ struct Traversal {
   bool leaf_first;
   int m2p_max;
   std::vector<std::pair<int32_t, int32_t>> p2p, m2l, m2p;
+  // Restricted traversal (empty = the whole one): wanted[c] marks the cells on
+  // the paths from the root to chosen leaves.  Every pair that visit(a, b)
+  // produces has its target inside a's subtree, so skipping the visits whose
+  // target cell is off those paths drops exactly the rows of the other
+  // targets and leaves the rows of the marked cells as they are.
+  std::vector<char> wanted;
 
   void accepted(int a, int b) {
     if (leaf(a) && tr.cells[a].n_body <= m2p_max) m2p.emplace_back(a, b);
@@ -444,6 +450,7 @@ struct Traversal {
     return (theta * theta) * d2 > s * s;
   }
   void visit(int a, int b) {
+    if (!wanted.empty() && !wanted[a]) return;
     if (leaf_first) {
       if (leaf(a) && leaf(b)) { p2p.emplace_back(a, b); return; }
       if (mac(a, b)) { accepted(a, b); return; }
@@ -480,9 +487,15 @@ void to_csr(std::vector<std::pair<int32_t, int32_t>> &pairs, int64_t n_rows,
   for (int64_t r = 0; r < n_rows; ++r) ptr[r + 1] += ptr[r];
 }
 
-void traverse(const Tree &tr, double theta, bool leaf_first, int m2p_max, Lists &ls) {
+void traverse(const Tree &tr, double theta, bool leaf_first, int m2p_max, Lists &ls,
+              const int32_t *leaves = nullptr, int64_t n_leaves = 0) {
   ls.n_rows = (int64_t)tr.cells.size();
-  Traversal tv{tr, theta, leaf_first, m2p_max, {}, {}, {}};
+  Traversal tv{tr, theta, leaf_first, m2p_max, {}, {}, {}, {}};
+  if (leaves) {
+    tv.wanted.assign(tr.cells.size(), 0);
+    for (int64_t k = 0; k < n_leaves; ++k)
+      for (int c = leaves[k]; c >= 0; c = tr.cells[c].parent) tv.wanted[c] = 1;
+  }
   if (!tr.cells.empty()) tv.visit(0, 0);
   to_csr(tv.p2p, ls.n_rows, ls.p2p_ptr, ls.p2p_col);
   to_csr(tv.m2l, ls.n_rows, ls.m2l_ptr, ls.m2l_col);
@@ -547,6 +560,32 @@ int oracle_build_hybrid(const double *xyz, int64_t n, int ncrit, double theta, i
   build_tree(xyz, n, ncrit, o->tree);
   traverse(o->tree, theta, leaf_first != 0, m2p_max, o->lists);
   *out = o;
+  return 0;
+}
+
+// The tree alone; oracle_traverse makes the lists.
+int oracle_build_tree(const double *xyz, int64_t n, int ncrit, oracle_fmm **out) {
+  if (n < 0 || ncrit < 1) return -1;
+  oracle_fmm *o = new oracle_fmm;
+  build_tree(xyz, n, ncrit, o->tree);
+  o->lists = Lists();
+  o->lists.n_rows = (int64_t)o->tree.cells.size();
+  *out = o;
+  return 0;
+}
+
+// (Re)make the lists of a tree.  leaves == NULL: the whole traversal, as
+// oracle_build.  Otherwise the restricted traversal: only the rows of the
+// given leaves and of their ancestors (each row equal to the whole
+// traversal's), every other row empty; enough for oracle_evaluate_leaves on
+// those leaves at sizes where the whole lists are large.
+int oracle_traverse(oracle_fmm *o, double theta, int leaf_first, int m2p_max,
+                    const int32_t *leaves, int64_t n_leaves) {
+  if (!(theta > 0.0) || m2p_max < 0 || n_leaves < 0) return -1;
+  for (int64_t k = 0; leaves && k < n_leaves; ++k)
+    if (leaves[k] < 0 || leaves[k] >= (int64_t)o->tree.cells.size()) return -1;
+  o->lists = Lists();
+  traverse(o->tree, theta, leaf_first != 0, m2p_max, o->lists, leaves, n_leaves);
   return 0;
 }
 

@@ -30,6 +30,10 @@ def _load():
     lib.oracle_build.restype = i32
     lib.oracle_build_hybrid.argtypes = [vp, i64, i32, dbl, i32, i32, ctypes.POINTER(vp)]
     lib.oracle_build_hybrid.restype = i32
+    lib.oracle_build_tree.argtypes = [vp, i64, i32, ctypes.POINTER(vp)]
+    lib.oracle_build_tree.restype = i32
+    lib.oracle_traverse.argtypes = [vp, dbl, i32, i32, vp, i64]
+    lib.oracle_traverse.restype = i32
     lib.oracle_free.argtypes = [vp]
     lib.oracle_free.restype = None
     lib.oracle_num_cells.argtypes = [vp]
@@ -101,12 +105,27 @@ class OracleFMM:
     m2p_max > 0: the treecode/FMM hybrid lists (accepted pairs whose target is
     a leaf of at most m2p_max bodies go to the M2P list, kind 2)."""
 
-    def __init__(self, xyz, ncrit, theta, leaf_first=False, m2p_max=0):
+    def __init__(self, xyz, ncrit, theta, leaf_first=False, m2p_max=0, select_leaves=None):
+        """select_leaves: None for the whole traversal, or a function of the
+        tree (the dict of tree()) returning leaf cells; the lists then hold only
+        the rows of those leaves and of their ancestors (the restricted
+        traversal), enough for evaluate_leaves on them."""
         lib = _load()
         self.xyz = _f64(xyz, (-1, 3))
         self.n = self.xyz.shape[0]
         h = ctypes.c_void_p()
-        if m2p_max:
+        self.restricted_to = None
+        if select_leaves is not None:
+            if lib.oracle_build_tree(_p(self.xyz), self.n, int(ncrit), ctypes.byref(h)) != 0:
+                raise ValueError("oracle_build_tree failed")
+            self._h = h
+            leaves = np.ascontiguousarray(select_leaves(self.tree()), dtype=np.int32)
+            if lib.oracle_traverse(h, float(theta), 1 if leaf_first else 0, int(m2p_max),
+                                   _p(leaves), leaves.shape[0]) != 0:
+                raise ValueError("oracle_traverse failed")
+            self.restricted_to = leaves
+            rc = 0
+        elif m2p_max:
             rc = lib.oracle_build_hybrid(_p(self.xyz), self.n, int(ncrit), float(theta),
                                          1 if leaf_first else 0, int(m2p_max), ctypes.byref(h))
         else:
@@ -150,6 +169,8 @@ class OracleFMM:
     def evaluate(self, q, p, staged=False):
         """Returns dict(phi[n], grad[n,3]) in user order; with staged=True also
         near/far fields (sorted order) and the M, L_m2l, L arrays (cell order)."""
+        if self.restricted_to is not None:
+            raise ValueError("restricted lists: use evaluate_leaves on the chosen leaves")
         q = _f64(q, (-1,))
         n, nc, T = self.n, self.num_cells, num_terms(p)
         out = dict(phi=np.zeros(n), grad=np.zeros((n, 3)))
@@ -229,6 +250,8 @@ def evaluate_leaves(o, q, p, leaves):
     lib = _load()
     q = _f64(q, (-1,))
     leaves = np.ascontiguousarray(leaves, dtype=np.int32)
+    if o.restricted_to is not None and not np.all(np.isin(leaves, o.restricted_to)):
+        raise ValueError("leaves outside the restricted traversal")
     t = o.tree()
     nb = int(t["n_body"][leaves].sum())
     idx = np.zeros(nb, np.int64)

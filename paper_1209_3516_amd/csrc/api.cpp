@@ -140,6 +140,9 @@ struct fmm_tree {
 struct fmm_lists {
   fmmlib::ListData data;
   DevLists dev;
+  // P2P work plan of host-built lists, made by the traversal and released
+  // once the first evaluation has uploaded it
+  fmmlib::P2PPlan host_plan;
 };
 
 namespace fmmlib {
@@ -300,10 +303,8 @@ int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
     return FMM_OK;
   }
   const auto t0 = std::chrono::steady_clock::now();
-  const fmmlib::TreeData &td = t->data;
   const fmmlib::ListData &ld = l->data;
-  fmmlib::P2PPlan pl;
-  fmmlib::build_p2p_plan(td, ld, pl);
+  const fmmlib::P2PPlan &pl = l->host_plan;
   auto &dp = dv.plan;
   dp.release();
   if (int rc = dev_upload(&dv.m2l_ptr, ld.m2l_ptr.data(), ld.m2l_ptr.size())) return rc;
@@ -334,8 +335,9 @@ int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
   dv.leaf_nchunk_host = pl.leaf_nchunk;
   dv.device = t->dev.device;
   dv.uploaded = true;
+  l->host_plan = fmmlib::P2PPlan();  // the device holds it now
   if (std::getenv("FMM_LOG"))
-    std::fprintf(stderr, "[fmm] host work plan + upload: %.2f ms (%lld items, %lld runs)\n",
+    std::fprintf(stderr, "[fmm] work plan upload: %.2f ms (%lld items, %lld runs)\n",
                  ms_since(t0), (long long)dp.n_items, (long long)dp.n_runs);
   return FMM_OK;
 }
@@ -855,6 +857,12 @@ int traverse_host(const fmm_tree *t, double theta, unsigned flags, int m2p_max, 
   try {
     l = new fmm_lists();
     fmmlib::dual_traverse(t->data, theta, (flags & FMM_LEAF_FIRST) != 0, m2p_max, l->data);
+    std::string err;
+    if (fmmlib::build_p2p_plan(t->data, l->data, l->host_plan, err) != FMM_OK) {
+      delete l;
+      set_error(std::string(fn) + ": " + err);
+      return FMM_EINVAL;
+    }
   } catch (const std::bad_alloc &) {
     delete l;
     set_error(std::string(fn) + ": out of host memory");
@@ -1015,7 +1023,7 @@ int fmm_lists_stats(const fmm_lists *l, fmm_lists_stats_t *s) {
   s->p2p_entries = host ? (int64_t)l->data.p2p_col.size() : l->dev.p2p_nnz;
   s->m2l_entries = host ? (int64_t)l->data.m2l_col.size() : l->dev.m2l_nnz;
   s->p2p_pairs = l->data.p2p_pairs;
-  s->p2p_work_items = l->dev.plan.n_items;
+  s->p2p_work_items = l->dev.uploaded ? l->dev.plan.n_items : (int64_t)l->host_plan.items.size();
   s->m2p_entries = (int64_t)l->data.m2p_col.size();
   s->p2p_max_row_sources = l->data.max_row_sources;
   return FMM_OK;

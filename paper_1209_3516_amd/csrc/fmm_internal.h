@@ -94,6 +94,12 @@ int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string
 void dual_traverse(const TreeData &t, double theta, bool leaf_first, int m2p_max, ListData &l);
 // p2p_pairs and max_row_sources of finished lists.
 void list_statistics(const TreeData &t, ListData &l);
-void build_p2p_plan(const TreeData &t, const ListData &l, P2PPlan &plan);
+// The plan stores run, work-item and partial-slot numbers as 32-bit
+// integers: the largest count a plan may hold (INT32_MAX; the environment
+// variable FMM_PLAN_LIMIT=K lowers it, to test the refusal).
+int64_t plan_index_limit();
+// Builds the plan of finished lists.  FMM_OK, or FMM_EINVAL with `err` set
+// when its runs, work items or partial slots exceed plan_index_limit().
+int build_p2p_plan(const TreeData &t, const ListData &l, P2PPlan &plan, std::string &err);
 
 }  // namespace fmmlib

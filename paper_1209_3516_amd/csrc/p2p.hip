@@ -156,12 +156,17 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
           p[r][2] += t * dy - dj.y * inv3;
           p[r][3] += t * dz - dj.z * inv3;
         } else {
+          // q/r^5 scales (d.v) and r^2 before they meet d and v: a padded
+          // source (zero charge, far away) then gives exact zeros, where
+          // (3 d.v) d - r^2 v alone would overflow to infinity and 0 * inf
+          // would be NaN.
           const Real inv2 = inv * inv;
           const Real q5 = sj.w * (inv * inv2) * inv2;
-          const Real dv3 = Real(3) * (dx * vt[r][0] + dy * vt[r][1] + dz * vt[r][2]);
-          p[r][1] += q5 * (dv3 * dx - r2 * vt[r][0]);
-          p[r][2] += q5 * (dv3 * dy - r2 * vt[r][1]);
-          p[r][3] += q5 * (dv3 * dz - r2 * vt[r][2]);
+          const Real a = q5 * (Real(3) * (dx * vt[r][0] + dy * vt[r][1] + dz * vt[r][2]));
+          const Real b = q5 * r2;
+          p[r][1] += a * dx - b * vt[r][0];
+          p[r][2] += a * dy - b * vt[r][1];
+          p[r][3] += a * dz - b * vt[r][2];
         }
       }
     }

@@ -1,9 +1,20 @@
 // Work plan of the GPU P2P kernel, built once per (tree, lists) on the host.
+#include <climits>
 #include <cmath>
+#include <cstdlib>
 
 #include "fmm_internal.h"
 
 namespace fmmlib {
+
+int64_t plan_index_limit() {
+  int64_t lim = INT32_MAX;
+  if (const char *s = std::getenv("FMM_PLAN_LIMIT")) {
+    const long long v = std::atoll(s);
+    if (v > 0 && v < lim) lim = v;
+  }
+  return lim;
+}
 
 // Lane layout for a work item of nt <= 64 targets on one 64-lane wave:
 // K source streams of L lanes; lane (s, u) holds targets u, u+L, ..., u+(R-1)L
@@ -30,8 +41,9 @@ void p2p_lane_layout(int nt, int *R, int *L, int *K) {
   *K = bK;
 }
 
-void build_p2p_plan(const TreeData &t, const ListData &l, P2PPlan &plan) {
+int build_p2p_plan(const TreeData &t, const ListData &l, P2PPlan &plan, std::string &err) {
   plan = P2PPlan();
+  const int64_t limit = plan_index_limit();
   const int64_t nc = t.n_cells();
   plan.body_leaf.assign(t.n, 0);
   int64_t pbase = 0;
@@ -106,8 +118,17 @@ void build_p2p_plan(const TreeData &t, const ListData &l, P2PPlan &plan) {
       }
     }
     pbase += (int64_t)nch * nA;
+    // Offsets are stored in 32 bits: stop before any of them could wrap.
+    if (pbase > limit || (int64_t)plan.items.size() > limit ||
+        (int64_t)plan.run_body.size() > limit) {
+      err = "P2P work plan too large: more than " + std::to_string(limit) +
+            " runs, work items or partial slots (32-bit offsets)";
+      plan = P2PPlan();
+      return FMM_EINVAL;
+    }
   }
   plan.n_partials = pbase;
+  return FMM_OK;
 }
 
 }  // namespace fmmlib

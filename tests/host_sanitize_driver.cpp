@@ -30,7 +30,7 @@ static int run_case(const std::vector<double> &xyz, int ncrit, double theta, boo
   reset_alloc_checkpoints();
   dual_traverse(t, theta, leaf_first, 0, l);
   P2PPlan plan;
-  build_p2p_plan(t, l, plan);
+  if (build_p2p_plan(t, l, plan, err) != 0) return 5;
   // every body has exactly one leaf; every item covers valid ranges
   for (const auto &it : plan.items) {
     const int nt = it.tgt_cfg & 0xff;

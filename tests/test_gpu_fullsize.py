@@ -3,12 +3,17 @@
 
 * uniform N = 10^6, p = 4: the whole oracle evaluation (all bodies) and the FP64
   direct sum on 1000 sampled targets;
-* Plummer N = 10^6, p = 6, theta = 0.35, ncrit = 32: the oracle's per-leaf
-  evaluation (identical arithmetic to its full evaluation) on sampled leaves,
-  including the leaves with the longest P2P rows and the deepest leaves;
-* uniform N = 10^7, p = 8, theta = 0.3: the FP64 direct sum on 1000 sampled
-  targets (a property that holds at any size: the error is within the
-  theta^p bound of an accepted pair, and no worse than at small N).
+* Plummer N = 10^6, p = 6, theta = 0.35, ncrit = 32, and uniform N = 10^7,
+  p = 8, theta = 0.3 (FP64 multipoles and locals at levels <= 3): the oracle's
+  per-leaf evaluation (identical arithmetic to its full evaluation) on sampled
+  leaves, including the leaves with the longest P2P rows, the longest chains
+  of M2L rows and the deepest leaves.  The oracle builds its own tree (equal
+  to the library's, array for array) and a restricted traversal that makes
+  exactly the rows of those leaves and their ancestors; each such row must
+  equal the library's bit for bit.  At 10^7 the backward of
+  L = sum w phi is checked on the same leaves, and the FP64 direct sum on
+  1000 sampled targets bounds the error by the oracle's own plus 3e-5.
+Every comparison with the oracle also holds a per-body bound (tests/bounds.py).
 """
 import time
 
@@ -18,22 +23,25 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import oracle as O  # noqa: E402
+from tests.bounds import assert_close, rel  # noqa: E402
 from paper_1209_3516_amd import fmm  # noqa: E402
 from paper_1209_3516_amd import workloads as W  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
+TREE_KEYS = ("perm", "keys", "level", "parent", "n_child", "body_begin", "n_body", "center",
+             "radius")
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+def log(*a):
+    print(*a, flush=True)
 
 
 def run_gpu(x, q, cfg, precision="mixed"):
     t0 = time.perf_counter()
     tree = fmm.Tree(x, cfg["ncrit"])
     lists = fmm.Lists(tree, cfg["theta"])
-    print("gpu tree+lists %.1fs" % (time.perf_counter() - t0), flush=True)
+    log("gpu tree+lists %.1fs" % (time.perf_counter() - t0))
     dt = torch.float64 if precision == "fp64" else torch.float32
     phi, g = fmm.evaluate(tree, lists, torch.tensor(q, dtype=dt, device=DEV), cfg["p"],
                           precision)
@@ -48,12 +56,12 @@ def test_uniform_1e6_p4_all_bodies():
     t0 = time.perf_counter()
     o = O.OracleFMM(x, cfg["ncrit"], cfg["theta"])
     ref = o.evaluate(q, cfg["p"])
-    print("oracle %.1fs" % (time.perf_counter() - t0), flush=True)
+    log("oracle %.1fs" % (time.perf_counter() - t0))
     for precision, tol in (("mixed", 1e-5), ("fp64", 1e-12)):
         _, lists, phi, g = run_gpu(x, q, cfg, precision)
-        print(precision, "e_phi", rel(phi, ref["phi"]), "e_grad", rel(g, ref["grad"]), flush=True)
-        assert rel(phi, ref["phi"]) <= tol
-        assert rel(g, ref["grad"]) <= tol
+        log(precision, "e_phi", rel(phi, ref["phi"]), "e_grad", rel(g, ref["grad"]))
+        assert_close(phi, ref["phi"], tol, precision + " phi")
+        assert_close(g, ref["grad"], tol, precision + " grad")
     tg = W.sample_targets(cfg["n"], 1000)
     dphi, dg = O.direct(x, q, tg)
     e_or = max(rel(ref["phi"][tg], dphi), rel(ref["grad"][tg], dg))
@@ -62,45 +70,127 @@ def test_uniform_1e6_p4_all_bodies():
     assert rel(g[tg], dg) <= e_or + 1e-5
 
 
-def _sample_leaves(t, ptr, nb_of, k, seed):
-    leaves = np.nonzero(t["n_child"] == 0)[0]
+def _row_sums(ptr, vals):
+    cs = np.concatenate([[0], np.cumsum(vals, dtype=np.int64)])
+    return cs[ptr[1:]] - cs[ptr[:-1]]
+
+
+def _choose_leaves(v, p2p_ptr, p2p_col, m2l_ptr, k, seed, targets=None):
+    """k random leaves, the 8 with the longest P2P rows (source bodies), the 8
+    with the most M2L entries along their chain of ancestors, the 8 deepest,
+    and the leaves holding the given target bodies (user indices)."""
+    leaves = np.nonzero(v["n_child"] == 0)[0]
     rng = np.random.default_rng(seed)
     pick = set(rng.choice(leaves, k, replace=False).tolist())
-    rows = np.array([nb_of[ptr[a]:ptr[a + 1]].sum() for a in leaves])
-    pick.update(leaves[np.argsort(rows)[-8:]].tolist())          # longest P2P rows
-    pick.update(leaves[np.argsort(t["level"][leaves])[-8:]].tolist())  # deepest leaves
+    rows = _row_sums(p2p_ptr, v["n_body"][p2p_col])[leaves]
+    pick.update(leaves[np.argsort(rows, kind="stable")[-8:]].tolist())
+    chain = np.diff(m2l_ptr).astype(np.int64)  # cells are breadth first: parents first
+    for c in range(1, len(chain)):
+        chain[c] += chain[v["parent"][c]]
+    pick.update(leaves[np.argsort(chain[leaves], kind="stable")[-8:]].tolist())
+    pick.update(leaves[np.argsort(v["level"][leaves], kind="stable")[-8:]].tolist())
+    if targets is not None:
+        pos = np.empty(v["n"], np.int64)
+        pos[v["perm"]] = np.arange(v["n"])
+        lb = v["body_begin"][leaves]
+        order = np.argsort(lb)
+        at = np.searchsorted(lb[order], pos[targets], side="right") - 1
+        pick.update(leaves[order[at]].tolist())
     return np.array(sorted(pick), dtype=np.int32)
+
+
+def _oracle_on_leaves(x, cfg, tree, lists, k, seed, targets=None):
+    """The oracle's tree (checked equal to the library's) and its restricted
+    traversal for the chosen leaves (rows checked equal to the library's)."""
+    v = tree.view()
+    p2p = lists.csr(fmm.FMM_P2P)
+    m2l = lists.csr(fmm.FMM_M2L)
+    leaves = _choose_leaves(v, p2p[0], p2p[1], m2l[0], k, seed, targets)
+    t0 = time.perf_counter()
+    o = O.OracleFMM(x, cfg["ncrit"], cfg["theta"], select_leaves=lambda t: leaves)
+    log("oracle tree + restricted traversal for %d leaves: %.1fs" % (len(leaves),
+                                                                      time.perf_counter() - t0))
+    ot = o.tree()
+    for key in TREE_KEYS:
+        np.testing.assert_array_equal(np.asarray(ot[key]), np.asarray(v[key]), err_msg=key)
+    on_path = set()
+    for c in leaves.tolist():
+        while c >= 0 and c not in on_path:
+            on_path.add(c)
+            c = int(v["parent"][c])
+    for kind, (lp, lc) in ((O.P2P, p2p), (O.M2L, m2l)):
+        op, oc = o.lists(kind)
+        for c in on_path:
+            np.testing.assert_array_equal(oc[op[c]:op[c + 1]], lc[lp[c]:lp[c + 1]],
+                                          err_msg="row %d of list %d" % (c, kind))
+    log("tree equal; %d rows of each list equal" % len(on_path))
+    return o, leaves, p2p
 
 
 def test_plummer_1e6_p6_sampled_leaves():
     cfg = W.CONFIGS["plummer-1e6-p6"]
     x = W.positions(cfg["n"], cfg["dist"])
     q = W.charges(cfg["n"], cfg["charges"])
-    t0 = time.perf_counter()
-    o = O.OracleFMM(x, cfg["ncrit"], cfg["theta"])
-    t = o.tree()
-    ptr, col = o.lists(O.P2P)
-    leaves = _sample_leaves(t, ptr, t["n_body"][col], 48, seed=40)
-    idx, rphi, rg = O.evaluate_leaves(o, q, cfg["p"], leaves)
-    print("oracle sampled %d bodies in %.1fs" % (len(idx), time.perf_counter() - t0), flush=True)
-    _, lists, phi, g = run_gpu(x, q, cfg, "mixed")
+    tree, lists, phi, g = run_gpu(x, q, cfg, "mixed")
     assert lists.stats()["p2p_max_row_sources"] > 8192  # rows split into several chunks
-    print("e_phi", rel(phi[idx], rphi), "e_grad", rel(g[idx], rg), flush=True)
-    assert rel(phi[idx], rphi) <= 1e-5
-    assert rel(g[idx], rg) <= 1e-5
+    o, leaves, _ = _oracle_on_leaves(x, cfg, tree, lists, 48, seed=40)
+    t0 = time.perf_counter()
+    idx, rphi, rg = O.evaluate_leaves(o, q, cfg["p"], leaves)
+    log("oracle sampled %d bodies in %.1fs" % (len(idx), time.perf_counter() - t0))
+    log("e_phi", rel(phi[idx], rphi), "e_grad", rel(g[idx], rg))
+    assert_close(phi[idx], rphi, 1e-5, "phi")
+    assert_close(g[idx], rg, 1e-5, "grad")
 
 
-def test_uniform_1e7_p8_direct_sum_sample():
+def test_uniform_1e7_p8_sampled_leaves_forward_and_backward():
     cfg = W.CONFIGS["uniform-1e7-p8"]
-    x = W.positions(cfg["n"], cfg["dist"])
-    q = W.charges(cfg["n"], cfg["charges"])
-    _, lists, phi, g = run_gpu(x, q, cfg, "mixed")
-    tg = W.sample_targets(cfg["n"], 1000)
+    n, p = cfg["n"], cfg["p"]
+    x = W.positions(n, cfg["dist"])
+    q = W.charges(n, cfg["charges"])
+    w = W.weights(n)
+    t0 = time.perf_counter()
+    tree = fmm.Tree(x, cfg["ncrit"])
+    lists = fmm.Lists(tree, cfg["theta"])
+    log("library tree + lists %.1fs" % (time.perf_counter() - t0), lists.stats())
+    qt = torch.tensor(q, dtype=torch.float32, device=DEV)
+    wt = torch.tensor(w, dtype=torch.float32, device=DEV)
+    # the default: FP64 multipoles and locals at levels <= 3 (p >= 8)
+    phi_t, g_t = fmm.evaluate(tree, lists, qt, p)
+    dq_t, dx_t = fmm.evaluate_backward(tree, lists, qt, g_t, wt, p)
+    torch.cuda.synchronize()
+    phi, g = phi_t.double().cpu().numpy(), g_t.double().cpu().numpy()
+    dq, dx = dq_t.double().cpu().numpy(), dx_t.double().cpu().numpy()
+    del phi_t, g_t, dq_t, dx_t
+    log("gpu forward + backward done")
+    assert np.all(np.isfinite(phi)) and np.all(np.isfinite(g))
+    assert np.all(np.isfinite(dq)) and np.all(np.isfinite(dx))
+
+    tg = W.sample_targets(n, 1000)
+    o, leaves, _ = _oracle_on_leaves(x, cfg, tree, lists, 48, seed=41, targets=tg)
+    del lists, tree
+    t0 = time.perf_counter()
+    idx, rphi, rg = O.evaluate_leaves(o, q, p, leaves)
+    idx_w, rphi_w, rg_w = O.evaluate_leaves(o, w, p, leaves)
+    assert np.array_equal(idx, idx_w)
+    log("oracle: %d bodies of %d leaves, charges q and w, in %.1fs"
+        % (len(idx), len(leaves), time.perf_counter() - t0))
+    log("forward e_phi %.3e e_grad %.3e" % (rel(phi[idx], rphi), rel(g[idx], rg)))
+    assert_close(phi[idx], rphi, 3e-5, "phi")
+    assert_close(g[idx], rg, 3e-5, "grad")
+    # backward of L = sum w phi: dL/dq = phi[w], dL/dx = w grad[q] + q grad[w]
+    want_dx = w[idx, None] * rg + q[idx, None] * rg_w
+    log("backward e_dq %.3e e_dx %.3e" % (rel(dq[idx], rphi_w), rel(dx[idx], want_dx)))
+    assert_close(dq[idx], rphi_w, 3e-5, "dq")
+    assert_close(dx[idx], want_dx, 3e-5, "dx")
+
+    # against the FP64 direct sum on 1000 sampled targets: no worse than the
+    # oracle's own truncation error there, plus the arithmetic tolerance
     t0 = time.perf_counter()
     dphi, dg = O.direct(x, q, tg)
-    print("direct sum %.1fs" % (time.perf_counter() - t0), flush=True)
+    log("direct sum %.1fs" % (time.perf_counter() - t0))
+    where = {int(u): k for k, u in enumerate(idx)}
+    at = np.array([where[int(u)] for u in tg])
+    e_or = max(rel(rphi[at], dphi), rel(rg[at], dg))
     e_phi, e_grad = rel(phi[tg], dphi), rel(g[tg], dg)
-    print("e_phi", e_phi, "e_grad", e_grad, lists.stats(), flush=True)
-    bound = cfg["theta"] ** cfg["p"]
-    assert e_phi <= bound and e_grad <= bound
-    assert np.all(np.isfinite(phi)) and np.all(np.isfinite(g))
+    log("vs direct sum: oracle %.3e, gpu e_phi %.3e e_grad %.3e" % (e_or, e_phi, e_grad))
+    assert e_phi <= e_or + 3e-5 and e_grad <= e_or + 3e-5

@@ -1,6 +1,7 @@
 """GPU parity: the HIP evaluation against the FP64 oracle on identical inputs.
 
-Tolerances (relative L2 over all bodies, potential and gradient separately):
+Tolerances (relative L2 over all bodies, potential and gradient separately,
+plus a per-body bound of ten times the tolerance, see tests/bounds.py):
   * FP64 mode vs oracle: 1e-12 (same method, different summation order);
   * mixed mode (FP32 P2P/M2L with Kahan-compensated P2P sums) vs oracle:
     1e-5 for p <= 6, 3e-5 for p = 8.
@@ -12,19 +13,13 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import oracle as O  # noqa: E402
+from tests.bounds import assert_close, rel  # noqa: E402
 from paper_1209_3516_amd import fmm  # noqa: E402
 from paper_1209_3516_amd import workloads as W  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-
-
-def rel(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def gpu_eval(x, q, ncrit, theta, p, precision, leaf_first=False, **kw):
@@ -64,8 +59,8 @@ def test_full_evaluation_matches_oracle(case, precision):
     q = W.charges(n, ch)
     ref = O.OracleFMM(x, ncrit, theta).evaluate(q, p)
     _, _, phi, g = gpu_eval(x, q, ncrit, theta, p, precision)
-    assert rel(phi, ref["phi"]) <= tol(precision, p)
-    assert rel(g, ref["grad"]) <= tol(precision, p)
+    assert_close(phi, ref["phi"], tol(precision, p), "phi")
+    assert_close(g, ref["grad"], tol(precision, p), "grad")
 
 
 def test_leaf_first_lists():
@@ -74,8 +69,8 @@ def test_leaf_first_lists():
     ref = O.OracleFMM(x, 16, 0.4, leaf_first=True).evaluate(q, 4)
     for prec in ("fp64", "mixed"):
         _, _, phi, g = gpu_eval(x, q, 16, 0.4, 4, prec, leaf_first=True)
-        assert rel(phi, ref["phi"]) <= tol(prec, 4)
-        assert rel(g, ref["grad"]) <= tol(prec, 4)
+        assert_close(phi, ref["phi"], tol(prec, 4), "phi")
+        assert_close(g, ref["grad"], tol(prec, 4), "grad")
 
 
 @pytest.mark.parametrize("p", [2, 4, 5, 6, 7, 8])
@@ -103,8 +98,8 @@ def test_fp64_top_levels_p8():
     ref = O.OracleFMM(x, 32, 0.3).evaluate(q, 8)
     for top in (-1, -2, 5):
         _, _, phi, g = gpu_eval(x, q, 32, 0.3, 8, "mixed", fp64_top_levels=top)
-        assert rel(phi, ref["phi"]) <= 3e-5, top
-        assert rel(g, ref["grad"]) <= 3e-5, top
+        assert_close(phi, ref["phi"], 3e-5, "phi top=%d" % top)
+        assert_close(g, ref["grad"], 3e-5, "grad top=%d" % top)
 
 
 EDGE = [
@@ -152,8 +147,8 @@ def test_edge_cases(name, spec, ncrit, precision):
     if np.linalg.norm(ref["phi"]) == 0:
         assert np.all(phi == 0) and np.all(g == 0)
         return
-    assert rel(phi, ref["phi"]) <= tol(precision, 4)
-    assert rel(g, ref["grad"]) <= tol(precision, 4)
+    assert_close(phi, ref["phi"], tol(precision, 4), "phi")
+    assert_close(g, ref["grad"], tol(precision, 4), "grad")
 
 
 def test_long_rows_are_chunked():
@@ -165,8 +160,8 @@ def test_long_rows_are_chunked():
     for prec in ("fp64", "mixed"):
         _, lst, phi, g = gpu_eval(x, q, 2000, 0.4, 4, prec)
         assert lst.stats()["p2p_max_row_sources"] > 8192
-        assert rel(phi, ref["phi"]) <= tol(prec, 4)
-        assert rel(g, ref["grad"]) <= tol(prec, 4)
+        assert_close(phi, ref["phi"], tol(prec, 4), "phi")
+        assert_close(g, ref["grad"], tol(prec, 4), "grad")
 
 
 def test_repeat_is_bitwise_identical():
@@ -191,8 +186,8 @@ def test_switching_order_and_precision_on_one_lists():
         dt = torch.float64 if prec == "fp64" else torch.float32
         phi, g = fmm.evaluate(t, lst, torch.tensor(q, dtype=dt, device=DEV), p, prec)
         ref = o.evaluate(q, p)
-        assert rel(phi.double().cpu().numpy(), ref["phi"]) <= tol(prec, p)
-        assert rel(g.double().cpu().numpy(), ref["grad"]) <= tol(prec, p)
+        assert_close(phi.double().cpu().numpy(), ref["phi"], tol(prec, p), "phi")
+        assert_close(g.double().cpu().numpy(), ref["grad"], tol(prec, p), "grad")
 
 
 def test_direct_sum_kernel_matches_oracle():
@@ -202,8 +197,8 @@ def test_direct_sum_kernel_matches_oracle():
     phi, g = fmm.direct(torch.tensor(x, device=DEV), torch.tensor(q, device=DEV),
                         torch.tensor(tg, device=DEV))
     rphi, rg = O.direct(x, q, tg)
-    assert rel(phi.cpu().numpy(), rphi) <= 1e-13
-    assert rel(g.cpu().numpy(), rg) <= 1e-13
+    assert_close(phi.cpu().numpy(), rphi, 1e-13, "phi")
+    assert_close(g.cpu().numpy(), rg, 1e-13, "grad")
 
 
 def test_timings_are_reported():

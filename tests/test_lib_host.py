@@ -207,3 +207,35 @@ def test_log_output(capfd, monkeypatch):
     fmm.Lists(t, 0.4)
     err = capfd.readouterr().err
     assert "[fmm] tree: n=500" in err and "[fmm] lists: theta=0.4" in err
+
+
+def test_plan_too_large_is_refused(monkeypatch):
+    """The P2P work plan indexes runs, work items and partial sums with 32-bit
+    integers; the traversal refuses lists whose plan would not fit (the limit
+    is lowered through the environment to reach that path at a small size)."""
+    x = W.uniform_cube(3000, seed=72)
+    t = fmm.Tree(x, 16)
+    items = fmm.Lists(t, 0.4).stats()["p2p_work_items"]
+    assert items > 1
+    monkeypatch.setenv("FMM_PLAN_LIMIT", str(items - 1))
+    with pytest.raises(fmm.FMMError) as e:
+        fmm.Lists(t, 0.4)
+    assert e.value.code == fmm.FMM_EINVAL
+    assert b"plan too large" in fmm.lib().fmm_last_error()
+    monkeypatch.setenv("FMM_PLAN_LIMIT", str(10 ** 12))  # above 2^31 - 1: no effect
+    assert fmm.Lists(t, 0.4).stats()["p2p_work_items"] == items
+
+
+@pytest.mark.parametrize("config,leaf_first", [("uniform-1e6-p4", False),
+                                               ("uniform-1e6-p4", True),
+                                               ("plummer-1e6-p6", False)])
+def test_tree_and_lists_match_oracle_at_benchmark_sizes(config, leaf_first):
+    """The headline workload (uniform 10^6, ncrit 64, theta 0.4) in both
+    traversal orders and the adaptive one (Plummer 10^6, ncrit 32, theta 0.35):
+    tree arrays and both lists equal the oracle's bit for bit."""
+    c = W.CONFIGS[config]
+    x = W.positions(c["n"], c["dist"])
+    _, _, lst = _compare(x, c["ncrit"], c["theta"], leaf_first)
+    s = lst.stats()
+    print(config, "leaf-first" if leaf_first else "mac-first", s)
+    assert s["p2p_entries"] > 0 and s["m2l_entries"] > 0

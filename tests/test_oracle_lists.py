@@ -123,3 +123,36 @@ def test_leaf_first_has_more_p2p():
     a = O.OracleFMM(x, 16, 0.4, leaf_first=False)
     b = O.OracleFMM(x, 16, 0.4, leaf_first=True)
     assert len(b.lists(O.P2P)[1]) > len(a.lists(O.P2P)[1])
+
+
+@pytest.mark.parametrize("dist,leaf_first", [("plummer", False), ("uniform", True),
+                                             ("uniform", False)])
+def test_restricted_traversal_keeps_the_rows_of_the_chosen_paths(dist, leaf_first):
+    """The restricted traversal (used for per-leaf checks at sizes where the
+    whole lists are large) gives, for every chosen leaf and each of its
+    ancestors, the whole traversal's row, and no other rows; the per-leaf
+    evaluation on it is identical."""
+    x = W.positions(20_000, dist)
+    q = W.charges(20_000)
+    full = O.OracleFMM(x, 16, 0.4, leaf_first=leaf_first)
+    t = full.tree()
+    leaves = np.nonzero(t["n_child"] == 0)[0]
+    pick = np.sort(np.random.default_rng(5).choice(leaves, 25, replace=False)).astype(np.int32)
+    part = O.OracleFMM(x, 16, 0.4, leaf_first=leaf_first, select_leaves=lambda tt: pick)
+    on_path = np.zeros(full.num_cells, bool)
+    for c in pick:
+        while c >= 0:
+            on_path[c] = True
+            c = t["parent"][c]
+    for kind in (O.P2P, O.M2L):
+        fp, fc = full.lists(kind)
+        rp, rc = part.lists(kind)
+        for c in range(full.num_cells):
+            want = fc[fp[c]:fp[c + 1]] if on_path[c] else fc[:0]
+            np.testing.assert_array_equal(rc[rp[c]:rp[c + 1]], want)
+    a = O.evaluate_leaves(full, q, 5, pick)
+    b = O.evaluate_leaves(part, q, 5, pick)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+    with pytest.raises(ValueError):
+        part.evaluate(q, 5)
