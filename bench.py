@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--config", default="uniform-1e6-p4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-cpu-one-thread", action="store_true",
+                    help="skip the single-thread evaluation of the CPU baseline")
     ap.add_argument("--share-gpus", type=int, default=8,
                     help="also time one GPU's share of the targets when they are split into "
                          "this many Morton ranges (0: skip)")
@@ -221,7 +223,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(x, q, ncrit, theta, p)
+        cpu = cpu_baseline(x, q, ncrit, theta, p, one_thread=not args.no_cpu_one_thread)
 
     line = {
         "metric": "FMM evals/s at N=1e6 p=4 (P2P Gpairs/s, % FP32 peak); fwd+bwd/fwd time",
@@ -259,25 +261,60 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(x, q, ncrit, theta, p, min_seconds=10.0, max_evals=20):
+def cpu_model():
+    """The host CPU's model name and the processors it offers."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name
+
+
+def cpu_baseline(x, q, ncrit, theta, p, min_seconds=10.0, max_evals=20, one_thread=True):
     """The FP64 oracle evaluating the same workload on this host's cores:
-    full evaluations repeated until at least `min_seconds` have passed."""
+    full evaluations repeated until at least `min_seconds` have passed, with
+    the oracle's own phase times (median over the evaluations) and the
+    wall-clock times of its tree build and traversal; then, unless disabled,
+    one full evaluation on a single thread."""
     from oracle import oracle as O
 
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    O.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
+    cores = O.get_threads()
     o = O.OracleFMM(x, ncrit, theta)
+    t_tree, t_dtt = o.build_seconds
     k = 0
+    phases = []
     t0 = time.perf_counter()
     while k < max_evals:
         o.evaluate(q, p)
+        phases.append(O.last_phase_seconds())
         k += 1
         if time.perf_counter() - t0 >= min_seconds:
             break
     t = time.perf_counter() - t0
-    return {"value": k / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": "%d full FP64 evaluations of the same workload (N=%d, p=%d), %.1f s; "
-                      "tree and lists built beforehand, not timed" % (k, x.shape[0], p, t),
-            "seconds": t}
+    med = {ph: float(np.median([d[ph] for d in phases])) for ph in O.PHASES}
+    out = {"value": k / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
+           "cpu_model": cpu_model(), "host_processors": os.cpu_count(),
+           "sample": "%d full FP64 evaluations of the same workload (N=%d, p=%d), %.1f s; "
+                     "tree and lists built beforehand, timed separately"
+                     % (k, x.shape[0], p, t),
+           "seconds": t,
+           "phase_s": dict(tree=t_tree, traversal=t_dtt, **med)}
+    if one_thread:
+        O.set_threads(1)
+        t0 = time.perf_counter()
+        o.evaluate(q, p)
+        t1 = time.perf_counter() - t0
+        O.set_threads(cores)
+        out["one_thread"] = {"value": 1.0 / t1, "unit": "evals/s", "cores": 1,
+                             "sample": "one full FP64 evaluation of the same workload",
+                             "phase_s": O.last_phase_seconds()}
+    return out
 
 
 if __name__ == "__main__":

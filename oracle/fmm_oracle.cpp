@@ -15,7 +15,10 @@
 // Build: g++ -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math), so
 // that the tree and the multipole acceptance test are reproducible bit for bit.
 
+#include <omp.h>
+
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -530,6 +533,20 @@ void upward_pass(const Tree &tr, const Terms &T, const std::vector<double> &qs,
   }
 }
 
+// Wall-clock seconds of the phases of the last full evaluation (timing only;
+// no effect on the arithmetic): upward pass, M2L, downward pass, L2P (with
+// M2P for hybrid lists), P2P.
+double g_phase_seconds[5] = {0, 0, 0, 0, 0};
+
+struct PhaseClock {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  void lap(int k) {
+    const auto t1 = std::chrono::steady_clock::now();
+    g_phase_seconds[k] = std::chrono::duration<double>(t1 - t0).count();
+    t0 = t1;
+  }
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -590,6 +607,17 @@ int oracle_traverse(oracle_fmm *o, double theta, int leaf_first, int m2p_max,
 }
 
 void oracle_free(oracle_fmm *o) { delete o; }
+
+// OpenMP threads for the calls that follow (n <= 0: all processors).
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
+
+int oracle_get_threads(void) { return omp_get_max_threads(); }
+
+// Phase times of the last oracle_evaluate on this process (seconds): upward
+// pass, M2L, downward pass, L2P, P2P.
+void oracle_last_phase_seconds(double *out) {
+  for (int k = 0; k < 5; ++k) out[k] = g_phase_seconds[k];
+}
 
 int64_t oracle_num_cells(const oracle_fmm *o) { return (int64_t)o->tree.cells.size(); }
 
@@ -654,12 +682,14 @@ int oracle_evaluate(const oracle_fmm *o, int p, const double *q, double *phi, do
   if (n == 0) return 0;
   Terms T(p);
   const int nt = T.count();
+  PhaseClock clock;
   std::vector<double> qs(n);
   for (int64_t i = 0; i < n; ++i) qs[i] = q[tr.perm[i]];
 
   // Upward pass: P2M on leaves, then M2M from the deepest level upwards.
   std::vector<double> M;
   upward_pass(tr, T, qs, M);
+  clock.lap(0);
   int max_level = 0;
   for (const auto &c : tr.cells) max_level = std::max(max_level, c.level);
   // M2L over the M2L list, one target row at a time.
@@ -670,6 +700,7 @@ int oracle_evaluate(const oracle_fmm *o, int p, const double *q, double *phi, do
       int b = ls.m2l_col[e];
       m2l(T, tr.cells[a].X, tr.cells[b].X, &M[b * nt], &L[a * nt]);
     }
+  clock.lap(1);
   if (Lm2l_out) std::copy(L.begin(), L.end(), Lm2l_out);
 
   // Downward pass: L2L from the root's children downwards.
@@ -681,8 +712,9 @@ int oracle_evaluate(const oracle_fmm *o, int p, const double *q, double *phi, do
       l2l(T, tr.cells[C.parent].X, C.X, &L[C.parent * nt], &L[c * nt]);
     }
   }
+  clock.lap(2);
 
-  // L2P (far field) and P2P (near field) on every target leaf.
+  // L2P (far field) on every target leaf; the near field (P2P) separately.
   std::vector<double> fphi(n, 0.0), fg(3 * n, 0.0), nphi(n, 0.0), ng(3 * n, 0.0);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t a = 0; a < nc; ++a) {
@@ -695,6 +727,15 @@ int oracle_evaluate(const oracle_fmm *o, int p, const double *q, double *phi, do
         const int b = ls.m2p_col[e];
         m2p(T, tr.cells[b].X, &M[b * nt], xi, &fphi[i], &fg[3 * i]);
       }
+    }
+  }
+  clock.lap(3);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t a = 0; a < nc; ++a) {
+    const Cell &A = tr.cells[a];
+    if (A.n_child != 0) continue;
+    for (int64_t i = A.body_begin; i < A.body_begin + A.n_body; ++i) {
+      const double xi[3] = {tr.xs[i], tr.ys[i], tr.zs[i]};
       for (int64_t e = ls.p2p_ptr[a]; e < ls.p2p_ptr[a + 1]; ++e) {
         const Cell &B = tr.cells[ls.p2p_col[e]];
         int64_t b = B.body_begin;
@@ -702,6 +743,7 @@ int oracle_evaluate(const oracle_fmm *o, int p, const double *q, double *phi, do
       }
     }
   }
+  clock.lap(4);
 
   for (int64_t i = 0; i < n; ++i) {
     int64_t u = tr.perm[i];

@@ -4,6 +4,7 @@ Test infrastructure only.  Inputs and outputs are numpy float64 / int arrays.
 """
 import ctypes
 import os
+import time
 
 import numpy as np
 
@@ -34,6 +35,12 @@ def _load():
     lib.oracle_build_tree.restype = i32
     lib.oracle_traverse.argtypes = [vp, dbl, i32, i32, vp, i64]
     lib.oracle_traverse.restype = i32
+    lib.oracle_set_threads.argtypes = [i32]
+    lib.oracle_set_threads.restype = None
+    lib.oracle_get_threads.argtypes = []
+    lib.oracle_get_threads.restype = i32
+    lib.oracle_last_phase_seconds.argtypes = [vp]
+    lib.oracle_last_phase_seconds.restype = None
     lib.oracle_free.argtypes = [vp]
     lib.oracle_free.restype = None
     lib.oracle_num_cells.argtypes = [vp]
@@ -115,24 +122,22 @@ class OracleFMM:
         self.n = self.xyz.shape[0]
         h = ctypes.c_void_p()
         self.restricted_to = None
+        t0 = time.perf_counter()
+        if lib.oracle_build_tree(_p(self.xyz), self.n, int(ncrit), ctypes.byref(h)) != 0:
+            raise ValueError("oracle_build_tree failed")
+        t1 = time.perf_counter()
+        self._h = h
+        leaves, n_leaves = None, 0
         if select_leaves is not None:
-            if lib.oracle_build_tree(_p(self.xyz), self.n, int(ncrit), ctypes.byref(h)) != 0:
-                raise ValueError("oracle_build_tree failed")
-            self._h = h
             leaves = np.ascontiguousarray(select_leaves(self.tree()), dtype=np.int32)
-            if lib.oracle_traverse(h, float(theta), 1 if leaf_first else 0, int(m2p_max),
-                                   _p(leaves), leaves.shape[0]) != 0:
-                raise ValueError("oracle_traverse failed")
+            n_leaves = leaves.shape[0]
             self.restricted_to = leaves
-            rc = 0
-        elif m2p_max:
-            rc = lib.oracle_build_hybrid(_p(self.xyz), self.n, int(ncrit), float(theta),
-                                         1 if leaf_first else 0, int(m2p_max), ctypes.byref(h))
-        else:
-            rc = lib.oracle_build(_p(self.xyz), self.n, int(ncrit), float(theta),
-                                  1 if leaf_first else 0, ctypes.byref(h))
-        if rc != 0:
-            raise ValueError("oracle_build failed")
+        t1b = time.perf_counter()
+        if lib.oracle_traverse(h, float(theta), 1 if leaf_first else 0, int(m2p_max),
+                               _p(leaves), n_leaves) != 0:
+            raise ValueError("oracle_traverse failed")
+        # wall-clock seconds of the tree build and of the traversal
+        self.build_seconds = (t1 - t0, time.perf_counter() - t1b)
         self._h = h
         self.ncrit = ncrit
         self.theta = theta
@@ -185,6 +190,26 @@ class OracleFMM:
         if rc != 0:
             raise ValueError("oracle_evaluate failed")
         return out
+
+
+PHASES = ("upward", "m2l", "downward", "l2p", "p2p")
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's later calls (n <= 0: all processors)."""
+    _load().oracle_set_threads(int(n))
+
+
+def get_threads():
+    return _load().oracle_get_threads()
+
+
+def last_phase_seconds():
+    """Wall-clock seconds of the phases of the last full evaluation in this
+    process: dict over PHASES."""
+    out = np.zeros(5)
+    _load().oracle_last_phase_seconds(_p(out))
+    return dict(zip(PHASES, out.tolist()))
 
 
 def set_positions(o, xyz):
