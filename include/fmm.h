@@ -37,6 +37,7 @@
 #ifndef PAPER_1209_3516_AMD_FMM_H
 #define PAPER_1209_3516_AMD_FMM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -249,6 +250,39 @@ void fmm_lists_free(fmm_lists *l);
  */
 int fmm_evaluate(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o, const void *q_dev,
                  void *phi_dev, void *grad_dev, void *stream);
+
+/*
+ * fmm_evaluate for callers that cannot allocate device memory: code under
+ * stream capture, tight serving loops, harnesses that forbid allocation.
+ * Computes exactly what fmm_evaluate computes (the same kernels; results
+ * identical bit for bit) with every device buffer of the evaluation
+ * (multipoles, locals, FP64 top levels, P2P partial sums) taken from one
+ * fixed array of FMM_NOALLOC_SCRATCH_BYTES of device memory that the library
+ * holds on each GPU it runs on until the process ends.  The call makes no
+ * hipMalloc, hipFree, stream or event; the near field runs on `stream`
+ * (as with FMM_EVAL_SERIAL).
+ *   t, l, o, q_dev, phi_dev, grad_dev, stream  as fmm_evaluate; o->flags may
+ *            hold only FMM_EVAL_SERIAL.
+ * Preconditions: the tree, lists and work plan are already on the current
+ * device for o->precision (one fmm_evaluate with the same precision on this
+ * device puts them there, as do fmm_tree_build_gpu + fmm_traverse_gpu
+ * followed by such a call); otherwise FMM_ESTATE.
+ * Errors: FMM_EINVAL when the evaluation needs more than
+ * FMM_NOALLOC_SCRATCH_BYTES (the message gives both sizes; 10^6 uniform
+ * bodies at p = 4 need about 41 MB), for FMM_EVAL_TIMING or
+ * FMM_EVAL_KEEP_STAGES, and for hybrid (M2P) lists; the argument errors of
+ * fmm_evaluate.  Every buffer of the array is written before it is read
+ * within one call, so nothing needs clearing between calls.  All calls on
+ * one GPU share its array: calls that overlap in time on one GPU (two host
+ * threads, or two streams not ordered by events) race and give undefined
+ * results.  fmm_copy_expansions and fmm_last_timings keep describing the
+ * last fmm_evaluate.
+ */
+#define FMM_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int fmm_evaluate_noalloc(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o,
+                         const void *q_dev, void *phi_dev, void *grad_dev, void *stream);
+/* Size of that array in bytes (FMM_NOALLOC_SCRATCH_BYTES). */
+size_t fmm_noalloc_scratch_bytes(void);
 
 /*
  * Evaluation for the targets of one range of leaves in Morton order: the

@@ -480,20 +480,46 @@ int check_pair(const fmm_tree *t, const fmm_lists *l) {
   return FMM_OK;
 }
 
+// Device buffers of one evaluation besides its inputs, outputs, tree and
+// lists: multipoles (M, folded Mr), locals L, the FP64 top levels, the P2P
+// partial sums, the gathered per-body vectors and the M2P results.
+struct EvalScratch {
+  void *M = nullptr, *Mr = nullptr, *L = nullptr;
+  double *M64 = nullptr, *L64 = nullptr;
+  void *part_s = nullptr, *part_c = nullptr;
+  void *vec4 = nullptr;
+  void *m2p_buf = nullptr;
+};
+
+EvalScratch scratch_of(const DevLists &dv) {
+  EvalScratch sc;
+  sc.M = dv.M;
+  sc.Mr = dv.Mr;
+  sc.L = dv.L;
+  sc.M64 = dv.M64;
+  sc.L64 = dv.L64;
+  sc.part_s = dv.part_s;
+  sc.part_c = dv.part_c;
+  sc.vec4 = dv.vec4;
+  sc.m2p_buf = dv.m2p_buf;
+  return sc;
+}
+
 // Enqueue one evaluation; outputs in user order.  mode kCharges: charges q ->
 // (phi, grad).  kDipoles: charges q plus dipoles -v_user (v_user [n][3]) ->
 // (phi, grad).  kHessVec: charges q; grad receives H[q] v_user.
 // rb0 <= rb1 (rb1 >= 0): only the targets of Morton positions [rb0, rb1),
 // which start and end on leaf boundaries; rb1 < 0: all targets.
-int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void *q, void *phi,
-                  void *grad, void *stream, int mode = fmmlib::dev::kCharges,
-                  const void *v_user = nullptr, int64_t rb0 = 0, int64_t rb1 = -1) {
+// The tree, lists and plan must be on the device and `sc` sized for
+// (p, precision); with fixed_scratch the call creates nothing (no stream,
+// no events), so the caller must have excluded timing, kept stages and the
+// side stream.
+int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const EvalScratch &sc,
+                       bool fixed_scratch, const void *q, void *phi, void *grad, void *stream,
+                       int mode, const void *v_user, int64_t rb0, int64_t rb1) {
   namespace D = fmmlib::dev;
   const fmmlib::TreeData &td = t->data;
   const bool fp64 = o->precision == FMM_FP64;
-  if (int rc = ensure_tree_device(t, fp64, stream)) return rc;
-  if (int rc = ensure_lists_device(t, l)) return rc;
-  if (int rc = ensure_scratch(t, l, o)) return rc;
   const bool ranged = rb1 >= 0;
   fmmlib::RangeCells rcells;
   if (ranged) {
@@ -504,7 +530,11 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   DevTree &dt = t->dev;
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool timing = (o->flags & FMM_EVAL_TIMING) != 0;
-  const bool overlap = (o->flags & FMM_EVAL_SERIAL) == 0;
+  const bool overlap = (o->flags & FMM_EVAL_SERIAL) == 0 && !fixed_scratch;
+  if (fixed_scratch && (timing || (o->flags & FMM_EVAL_KEEP_STAGES))) {
+    set_error("internal error: timing or kept stages with a fixed scratch buffer");
+    return FMM_EINVAL;
+  }
   if (timing && !dv.have_events) {
     for (auto &e : dv.ev) HIP_TRY(hipEventCreate(&e));
     dv.have_events = true;
@@ -525,7 +555,7 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   const int S = D::stride(p);
   void *bodies = fp64 ? dt.b64 : dt.b32;
   const auto &pl = dv.plan;
-  const int64_t n_top = dv.n_top;
+  const int64_t n_top = top_cells(td, o);
   const int max_level = td.max_level;
   const double *geo = dt.geo;
   const size_t real = fp64 ? 8 : 4;
@@ -539,8 +569,8 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   const void *vec = nullptr;
   if (mode != D::kCharges) {
     LAUNCH_TRY(D::gather_vectors(fp64, td.n, dt.perm, v_user, mode == D::kDipoles ? -1.0 : 1.0,
-                                 dv.vec4, stream));
-    vec = dv.vec4;
+                                 sc.vec4, stream));
+    vec = sc.vec4;
   }
   if (int rc = mark(1, s)) return rc;
 
@@ -553,7 +583,7 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   if (int rc = mark(8, ns)) return rc;
   if (!ranged) {
     LAUNCH_TRY(D::p2p(fp64, mode, mask_all, pl.n_items, pl.items, pl.run_body, pl.run_prefix,
-                      bodies, vec, dv.part_s, dv.part_c, ns));
+                      bodies, vec, sc.part_s, sc.part_c, ns));
   } else {
     // the items of the range's leaves: one contiguous run per level
     for (int lev = 0; lev <= max_level; ++lev) {
@@ -561,7 +591,7 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
       const int64_t i1 = dv.leaf_item_host[rcells.leaf_hi[lev]];
       if (i1 > i0)
         LAUNCH_TRY(D::p2p(fp64, mode, mask_all, i1 - i0, pl.items + i0, pl.run_body,
-                          pl.run_prefix, bodies, vec, dv.part_s, dv.part_c, ns));
+                          pl.run_prefix, bodies, vec, sc.part_s, sc.part_c, ns));
     }
   }
   if (int rc = mark(9, ns)) return rc;
@@ -569,30 +599,30 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
 
   // Far field on the caller's stream.
   LAUNCH_TRY(D::p2m(p, fp64, pl.n_leaves, pl.leaf_cell, dt.body_begin, dt.n_body,
-                    geo, bodies, mode == D::kDipoles ? vec : nullptr, dv.M, dv.M64, n_top,
+                    geo, bodies, mode == D::kDipoles ? vec : nullptr, sc.M, sc.M64, n_top,
                     stream));
   if (int rc = mark(2, s)) return rc;
   for (int lev = max_level - 1; lev >= 0; --lev) {
     const int64_t c0 = td.level_begin[lev], c1 = td.level_begin[lev + 1];
     const bool out64 = c1 <= n_top;        // this level is kept in FP64
     const bool child64 = td.level_begin[lev + 2] <= n_top;
-    LAUNCH_TRY(D::m2m(p, fp64, c0, c1, dt.child_begin, dt.n_child, geo, dv.M, dv.M64, child64,
+    LAUNCH_TRY(D::m2m(p, fp64, c0, c1, dt.child_begin, dt.n_child, geo, sc.M, sc.M64, child64,
                       out64, stream));
   }
   if (int rc = mark(3, s)) return rc;
   {
     // M2L reads the multipoles folded onto their terms of z exponent <= 1.
-    LAUNCH_TRY(D::fold_multipoles(p, fp64, td.n_cells(), dv.M, dv.Mr, stream));
+    LAUNCH_TRY(D::fold_multipoles(p, fp64, td.n_cells(), sc.M, sc.Mr, stream));
     // every cell is an M2L row (one without entries writes zeros); the top
     // n_top cells accumulate in FP64.  A target range takes, level by level,
     // the cells holding its bodies.
     auto m2l_cells = [&](int64_t c0, int64_t c1) -> int {
       const int64_t split = std::max(c0, std::min(n_top, c1));
       if (split > c0)
-        LAUNCH_TRY(D::m2l(p, fp64, c0, split, dv.m2l_ptr, dv.m2l_col, geo, dv.Mr, dv.L, dv.L64,
+        LAUNCH_TRY(D::m2l(p, fp64, c0, split, dv.m2l_ptr, dv.m2l_col, geo, sc.Mr, sc.L, sc.L64,
                           true, stream));
       if (c1 > split)
-        LAUNCH_TRY(D::m2l(p, fp64, split, c1, dv.m2l_ptr, dv.m2l_col, geo, dv.Mr, dv.L, dv.L64,
+        LAUNCH_TRY(D::m2l(p, fp64, split, c1, dv.m2l_ptr, dv.m2l_col, geo, sc.Mr, sc.L, sc.L64,
                           false, stream));
       return FMM_OK;
     };
@@ -605,12 +635,12 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   }
   if (dv.n_m2p_rows > 0)
     LAUNCH_TRY(D::m2p(p, fp64, dv.n_m2p_rows, dv.m2p_rows, dv.m2p_ptr, dv.m2p_col, dt.body_begin,
-                      dt.n_body, geo, dv.M, bodies, dv.m2p_buf, stream));
+                      dt.n_body, geo, sc.M, bodies, sc.m2p_buf, stream));
   if (o->flags & FMM_EVAL_KEEP_STAGES) {
-    HIP_TRY(hipMemcpyAsync(dv.Lstage, dv.L, (size_t)td.n_cells() * S * real,
+    HIP_TRY(hipMemcpyAsync(dv.Lstage, sc.L, (size_t)td.n_cells() * S * real,
                            hipMemcpyDeviceToDevice, s));
     if (n_top > 0)
-      HIP_TRY(hipMemcpyAsync(dv.L64stage, dv.L64, (size_t)n_top * S * 8, hipMemcpyDeviceToDevice,
+      HIP_TRY(hipMemcpyAsync(dv.L64stage, sc.L64, (size_t)n_top * S * 8, hipMemcpyDeviceToDevice,
                              s));
     dv.stage_valid = true;
   } else {
@@ -623,21 +653,65 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
     const bool child64 = c1 <= n_top;
     const int64_t r0 = ranged ? rcells.cell_lo[lev] : c0, r1 = ranged ? rcells.cell_hi[lev] : c1;
     if (r1 > r0)
-      LAUNCH_TRY(D::l2l(p, fp64, r0, r1, dt.parent, geo, dv.L, dv.L64, parent64, child64,
+      LAUNCH_TRY(D::l2l(p, fp64, r0, r1, dt.parent, geo, sc.L, sc.L64, parent64, child64,
                         stream));
   }
-  if (n_top > 0) LAUNCH_TRY(D::copy_top_locals(p, n_top, dv.L64, (float *)dv.L, stream));
+  if (n_top > 0) LAUNCH_TRY(D::copy_top_locals(p, n_top, sc.L64, (float *)sc.L, stream));
   if (int rc = mark(5, s)) return rc;
   if (overlap) HIP_TRY(hipStreamWaitEvent(s, dv.join, 0));
   if (int rc = mark(6, s)) return rc;
   LAUNCH_TRY(D::l2p_combine(p, fp64, mode, ranged ? rb0 : 0, ranged ? rb1 : td.n, pl.body_leaf, pl.leaf_cell, pl.leaf_pbase,
-                            pl.leaf_nchunk, dt.body_begin, dt.n_body, geo, dv.L, bodies, vec,
-                            dv.part_s, dv.part_c, dv.n_m2p_rows > 0 ? dv.m2p_buf : nullptr,
+                            pl.leaf_nchunk, dt.body_begin, dt.n_body, geo, sc.L, bodies, vec,
+                            sc.part_s, sc.part_c, dv.n_m2p_rows > 0 ? sc.m2p_buf : nullptr,
                             dt.perm, phi, grad, stream));
   if (int rc = mark(7, s)) return rc;
   dv.timed_serial = !overlap;
   dv.timing_valid = timing;
   return FMM_OK;
+}
+
+// The allocating path: uploads the tree, lists and plan on first use and
+// sizes the lists' own scratch for (p, precision).
+int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void *q, void *phi,
+                  void *grad, void *stream, int mode = fmmlib::dev::kCharges,
+                  const void *v_user = nullptr, int64_t rb0 = 0, int64_t rb1 = -1) {
+  const bool fp64 = o->precision == FMM_FP64;
+  if (int rc = ensure_tree_device(t, fp64, stream)) return rc;
+  if (int rc = ensure_lists_device(t, l)) return rc;
+  if (int rc = ensure_scratch(t, l, o)) return rc;
+  return enqueue_evaluation(t, l, o, scratch_of(l->dev), false, q, phi, grad, stream, mode,
+                            v_user, rb0, rb1);
+}
+
+// Carves the buffers of one evaluation out of [base, base + cap), each
+// aligned to 256 bytes; the bytes needed go to *need (more than cap: nothing
+// is carved).
+void carve_scratch(const fmmlib::TreeData &td, const DevLists &dv, const fmm_eval_opts *o,
+                   char *base, size_t cap, EvalScratch *sc, size_t *need) {
+  const bool fp64 = o->precision == FMM_FP64;
+  const size_t real = fp64 ? 8 : 4;
+  const size_t nc = (size_t)td.n_cells();
+  const size_t n_top = (size_t)top_cells(td, o);
+  const size_t S = (size_t)fmmlib::dev::stride(o->p);
+  const size_t np = (size_t)std::max<int64_t>(1, dv.plan.n_partials);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char * {
+    const size_t at = off;
+    off += (bytes + 255) & ~size_t(255);
+    return base + at;
+  };
+  EvalScratch c;
+  c.M = take(nc * S * real);
+  c.Mr = take(nc * (size_t)fmmlib::dev::rstride(o->p) * real);
+  c.L = take(nc * S * real);
+  if (n_top > 0) {
+    c.M64 = (double *)take(n_top * S * 8);
+    c.L64 = (double *)take(n_top * S * 8);
+  }
+  c.part_s = take(np * 4 * real);
+  if (!fp64) c.part_c = take(np * 4 * real);
+  *need = off;
+  if (off <= cap) *sc = c;
 }
 
 // Library ordering of expansion terms: by degree, then z exponent, then y.
@@ -1253,3 +1327,61 @@ int fmm_copy_expansions(const fmm_lists *l, int kind, double *dst) {
 }
 
 }  // extern "C"
+
+namespace fmmlib {
+
+int evaluate_fixed_scratch(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o,
+                           const void *q_dev, void *phi_dev, void *grad_dev, void *stream,
+                           int (*scratch_address)(void **), size_t scratch_bytes) {
+  if (int rc = check_pair(t, l)) return rc;
+  if (int rc = check_opts(o)) return rc;
+  if (o->flags & ~FMM_EVAL_SERIAL) {
+    set_error("fmm_evaluate_noalloc: timing and kept stages need fmm_evaluate");
+    return FMM_EINVAL;
+  }
+  if (!l->data.m2p_col.empty()) {
+    set_error("fmm_evaluate_noalloc: hybrid (M2P) lists need fmm_evaluate");
+    return FMM_EINVAL;
+  }
+  if (t->data.n == 0) return FMM_OK;
+  if (!q_dev || !phi_dev) {
+    set_error("fmm_evaluate_noalloc: q and phi must not be NULL");
+    return FMM_EINVAL;
+  }
+  fmm_tree *tt = const_cast<fmm_tree *>(t);
+  fmm_lists *ll = const_cast<fmm_lists *>(l);
+  const bool fp64 = o->precision == FMM_FP64;
+  const DevTree &dt = t->dev;
+  const DevLists &dv = l->dev;
+  int dev;
+  if (int rc = current_device(&dev)) return rc;
+  const uint64_t have = fp64 ? dt.pos_version_64 : dt.pos_version_32;
+  if (dt.device != dev || !dv.uploaded || dv.device != dev || have != t->data.pos_version ||
+      !(fp64 ? dt.b64 : dt.b32)) {
+    set_error("fmm_evaluate_noalloc: the tree, lists and work plan are not on this device for "
+              "this precision; one fmm_evaluate with the same precision on this device puts "
+              "them there");
+    return FMM_ESTATE;
+  }
+  void *scratch = nullptr;
+  if (int rc = scratch_address(&scratch)) return rc;
+  EvalScratch sc;
+  size_t need = 0;
+  carve_scratch(t->data, dv, o, static_cast<char *>(scratch), scratch_bytes, &sc, &need);
+  if (need > scratch_bytes) {
+    set_error("fmm_evaluate_noalloc: this evaluation needs " + std::to_string(need) +
+              " bytes of scratch; the fixed buffer holds " + std::to_string(scratch_bytes));
+    return FMM_EINVAL;
+  }
+  try {
+    return enqueue_evaluation(tt, ll, o, sc, true, q_dev, phi_dev, grad_dev, stream,
+                              fmmlib::dev::kCharges, nullptr, 0, -1);
+  } catch (const std::bad_alloc &) {
+    set_error("fmm_evaluate_noalloc: out of host memory");
+    return FMM_ENOMEM;
+  }
+}
+
+void set_last_error(const char *msg) { set_error(msg); }
+
+}  // namespace fmmlib

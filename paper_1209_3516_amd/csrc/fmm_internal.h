@@ -102,4 +102,17 @@ int64_t plan_index_limit();
 // when its runs, work items or partial slots exceed plan_index_limit().
 int build_p2p_plan(const TreeData &t, const ListData &l, P2PPlan &plan, std::string &err);
 
+// fmm_evaluate with every device buffer of the evaluation carved out of a
+// fixed device buffer of scratch_bytes, whose address on the current device
+// scratch_address gives (called after the arguments are checked): no
+// allocation, no stream or event creation.  The tree, lists and plan must
+// already be on the current device for o->precision (FMM_ESTATE otherwise);
+// FMM_EINVAL if the buffer is too small, for timing or kept-stage flags and
+// for hybrid lists.
+int evaluate_fixed_scratch(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opts *o,
+                           const void *q_dev, void *phi_dev, void *grad_dev, void *stream,
+                           int (*scratch_address)(void **), size_t scratch_bytes);
+// Sets the thread's fmm_last_error message.
+void set_last_error(const char *msg);
+
 }  // namespace fmmlib

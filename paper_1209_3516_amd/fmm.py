@@ -60,7 +60,8 @@ EXPORTS = ("fmm_tree_build", "fmm_tree_set_positions", "fmm_tree_view", "fmm_tre
            "fmm_evaluate", "fmm_evaluate_backward", "fmm_direct", "fmm_last_timings",
            "fmm_last_error", "fmm_num_terms", "fmm_copy_expansions", "fmm_term_exponents",
            "fmm_traverse_gpu", "fmm_tree_build_gpu", "fmm_evaluate_range",
-           "fmm_partition_targets", "fmm_traverse_hybrid")
+           "fmm_partition_targets", "fmm_traverse_hybrid", "fmm_evaluate_noalloc",
+           "fmm_noalloc_scratch_bytes")
 
 _lib = None
 
@@ -91,6 +92,8 @@ def lib():
         "fmm_lists_stats": ([vp, ctypes.POINTER(_ListStats)], i32),
         "fmm_lists_free": ([vp], None),
         "fmm_evaluate": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp], i32),
+        "fmm_evaluate_noalloc": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp], i32),
+        "fmm_noalloc_scratch_bytes": ([], ctypes.c_size_t),
         "fmm_evaluate_range": ([vp, vp, ctypes.POINTER(_EvalOpts), i64, i64, vp, vp, vp, vp],
                                i32),
         "fmm_partition_targets": ([vp, vp, i32, dbl, vp], i32),
@@ -302,6 +305,27 @@ def evaluate(tree, lists, q, p, precision="mixed", grad=True, timing=False, keep
         _check(lib().fmm_evaluate_range(tree._h, lists._h, ctypes.byref(o), b0, b1, _t_ptr(q),
                                         _t_ptr(phi), _t_ptr(g), _stream()))
     return phi, g
+
+
+def evaluate_noalloc(tree, lists, q, phi, grad, p, precision="mixed", fp64_top_levels=-1):
+    """fmm_evaluate_noalloc: the evaluation into the given output tensors (phi
+    [n], grad [n,3] or None) with no device allocation by the library; the
+    tree and lists must already be on the device for this precision (one
+    evaluate() call puts them there).  Returns (phi, grad)."""
+    dt = _dtype(precision)
+    _check_tensor(q, tree.n, dt, "q")
+    _check_tensor(phi, tree.n, dt, "phi")
+    if grad is not None:
+        _check_tensor(grad, tree.n, dt, "grad", 3)
+    o = _opts(p, precision, 0, fp64_top_levels)
+    _check(lib().fmm_evaluate_noalloc(tree._h, lists._h, ctypes.byref(o), _t_ptr(q),
+                                      _t_ptr(phi), _t_ptr(grad), _stream()))
+    return phi, grad
+
+
+def noalloc_scratch_bytes():
+    """Size of the fixed device array fmm_evaluate_noalloc works in."""
+    return int(lib().fmm_noalloc_scratch_bytes())
 
 
 def m2l_weight(p):

@@ -99,7 +99,8 @@ def test_p2p_pair_count():
 
 def test_header_symbols_are_exported():
     hdr = open(os.path.join(ROOT, "include", "fmm.h")).read()
-    declared = set(re.findall(r"^\s*(?:int|void|const char \*)\s*(fmm_\w+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^\s*(?:int|void|size_t|const char \*)\s*(fmm_\w+)\s*\(", hdr,
+                              re.M))
     assert declared == set(fmm.EXPORTS)
     L = fmm.lib()
     for name in declared:
@@ -150,6 +151,34 @@ def test_invalid_arguments_are_rejected_without_gpu():
     assert L.fmm_last_timings(lst._h, (ctypes.c_double * 8)()) == fmm.FMM_ESTATE
     assert L.fmm_copy_expansions(lst._h, 0, dummy) == fmm.FMM_ESTATE
     assert L.fmm_num_terms(0) == -1 and L.fmm_num_terms(4) == 20 and L.fmm_num_terms(8) == 120
+
+
+def test_noalloc_entry_point_rejects_without_gpu():
+    """fmm_evaluate_noalloc checks its arguments before it touches the GPU."""
+    L = fmm.lib()
+    assert L.fmm_noalloc_scratch_bytes() == 128 << 20
+    x = np.ascontiguousarray(W.uniform_cube(300))
+    t = fmm.Tree(x, 16)
+    lst = fmm.Lists(t, 0.5)
+    dummy = ctypes.c_void_p(16)
+    for flags in (fmm.FMM_EVAL_TIMING, fmm.FMM_EVAL_KEEP_STAGES, 8):
+        o = fmm._EvalOpts(4, 0, -1, flags)
+        assert L.fmm_evaluate_noalloc(t._h, lst._h, ctypes.byref(o), dummy, dummy, None,
+                                      None) == fmm.FMM_EINVAL
+    o = fmm._EvalOpts(4, 0, -1, 0)
+    assert L.fmm_evaluate_noalloc(t._h, lst._h, ctypes.byref(o), None, dummy, None,
+                                  None) == fmm.FMM_EINVAL
+    assert L.fmm_evaluate_noalloc(t._h, lst._h, ctypes.byref(o), dummy, None, None,
+                                  None) == fmm.FMM_EINVAL
+    assert L.fmm_evaluate_noalloc(fmm.Tree(x, 16)._h, lst._h, ctypes.byref(o), dummy, dummy,
+                                  None, None) == fmm.FMM_ESTATE
+    hyb = fmm.Lists(t, 0.5, m2p_max=4)
+    assert L.fmm_evaluate_noalloc(t._h, hyb._h, ctypes.byref(o), dummy, dummy, None,
+                                  None) == fmm.FMM_EINVAL
+    assert b"hybrid" in L.fmm_last_error()
+    e = fmm.Tree(np.zeros((0, 3)), 4)
+    assert L.fmm_evaluate_noalloc(e._h, fmm.Lists(e, 0.4)._h, ctypes.byref(o), None, None, None,
+                                  None) == fmm.FMM_OK
 
 
 def test_empty_tree_evaluation_is_a_noop():
