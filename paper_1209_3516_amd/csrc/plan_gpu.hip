@@ -8,9 +8,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <hipcub/hipcub.hpp>
 
 #include "kernels.h"
+#include "prims.h"
 
 namespace fmmlib {
 namespace dev {
@@ -300,17 +300,19 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
   PTRY(hipMalloc(&out.leaf_nchunk, nl * 4));
   PTRY(hipMalloc(&out.body_leaf, (size_t)(n > 0 ? n : 1) * 4));
 
-  size_t tb = 0, tb2 = 0;
-  PTRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, leaf_flag, leaf_of, (int)nc, st));
-  PTRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, nruns, run_off, (int)nl, st));
-  tb = tb > tb2 ? tb : tb2;
-  PTRY(hipMallocAsync(&scan_tmp, tb > 0 ? tb : 1, st));
+  // scratch of the scans (tile partials), for the larger of the two lengths
+  PTRY(hipMallocAsync(&scan_tmp, prims::scan_scratch_bytes<int64_t>((int64_t)(nc > nl ? nc : nl)),
+                      st));
+  auto scan = [&](const int32_t *in, int32_t *out_off, size_t m) -> hipError_t {
+    return prims::exclusive_scan<int64_t>((int64_t)m, prims::LoadArray<int64_t, int32_t>{in},
+                                          prims::StoreArray<int64_t, int32_t>{out_off},
+                                          (int64_t *)scan_tmp, (int64_t *)nullptr, st);
+  };
 
   const unsigned bc = (unsigned)((nc + 255) / 256);
   leaf_flags<<<bc, 256, 0, st>>>((int64_t)nc, n_child, leaf_flag);
   PTRY(hipGetLastError());
-  tb2 = tb;
-  PTRY(hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb2, leaf_flag, leaf_of, (int)nc, st));
+  PTRY(scan(leaf_flag, leaf_of, nc));
   plan_count<<<(unsigned)nc, 64, 0, st>>>((int64_t)nc, n_child, leaf_of, p2p_ptr, p2p_col,
                                            body_begin, n_body, out.leaf_cell, nruns, nitems,
                                            nparts, out.leaf_nchunk, lsrc, lpairs);
@@ -332,12 +334,9 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
     release();
     return (int)hipErrorInvalidValue;
   }
-  tb2 = tb;
-  PTRY(hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb2, nruns, run_off, (int)nl, st));
-  tb2 = tb;
-  PTRY(hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb2, nitems, item_off, (int)nl, st));
-  tb2 = tb;
-  PTRY(hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb2, nparts, out.leaf_pbase, (int)nl, st));
+  PTRY(scan(nruns, run_off, nl));
+  PTRY(scan(nitems, item_off, nl));
+  PTRY(scan(nparts, out.leaf_pbase, nl));
   PTRY(hipMalloc(&out.items, (size_t)(out.n_items > 0 ? out.n_items : 1) * sizeof(P2PItem)));
   PTRY(hipMalloc(&out.run_body, (size_t)(out.n_runs > 0 ? out.n_runs : 1) * 4));
   PTRY(hipMalloc(&out.run_prefix, (size_t)(out.n_runs > 0 ? out.n_runs : 1) * 4));

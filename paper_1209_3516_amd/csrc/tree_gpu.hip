@@ -11,7 +11,8 @@
 // child pairs of the next frontier and the emitted pairs.  The emitted pairs
 // are sorted as integer keys (target << kb | source), kb = bits of a cell
 // number, which is the canonical CSR order (rows = targets, sources
-// ascending); the radix sort looks at the 2 kb low bits only.
+// ascending); the radix sort looks at the 2 kb low bits only, and the keys
+// are 32-bit when 2 kb <= 32.  Scans and sorts are the ones of prims.h.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -22,11 +23,11 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
-#include <hipcub/hipcub.hpp>
 #include <string>
 #include <vector>
 
 #include "kernels.h"
+#include "prims.h"
 
 namespace fmmlib {
 namespace dev {
@@ -61,79 +62,82 @@ __device__ __forceinline__ int classify(int a, int b, const double4 *__restrict_
   return split_a ? kActSplitA : kActSplitB;
 }
 
-// counts[i] = number of child pairs; emit[i] = (M2L count << 32) | P2P count.
-
-// off[m - 1] + cnt[m - 1]: the total of an exclusive scan of cnt.
-__global__ void scan_total_i32(int64_t m, const int32_t *__restrict__ off,
-                               const int32_t *__restrict__ cnt, int64_t *__restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = (int64_t)off[m - 1] + cnt[m - 1];
-}
-
-// The next frontier's size and the packed (M2L << 32 | P2P) count of one
-// level: last exclusive offset plus last count.
-__global__ void level_totals(int64_t nf, const int64_t *__restrict__ coff,
-                             const int64_t *__restrict__ counts,
-                             const uint64_t *__restrict__ eoff,
-                             const uint64_t *__restrict__ emit, int64_t *__restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    out[0] = coff[nf - 1] + counts[nf - 1];
-    out[1] = (int64_t)(eoff[nf - 1] + emit[nf - 1]);
+// Per frontier pair: child pairs it creates, emitted lists ((M2L << 32) |
+// P2P, one of them 1 or both 0) and its action.  The scan of a level sums the
+// first two over the frontier (the action field's sum means nothing).
+struct PairCount {
+  int64_t children;
+  uint64_t emit;
+  int64_t act;
+  __device__ PairCount operator+(const PairCount &o) const {
+    return PairCount{children + o.children, emit + o.emit, act + o.act};
   }
-}
+};
 
-__global__ void dtt_count(int64_t nf, const int2 *__restrict__ frontier,
-                          const double4 *__restrict__ geo, const int32_t *__restrict__ n_child,
-                          double theta2, int leaf_first, int64_t *__restrict__ counts,
-                          uint64_t *__restrict__ emit) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nf) return;
-  const int2 pr = frontier[i];
-  int n;
-  const int act = classify(pr.x, pr.y, geo, n_child, theta2, leaf_first != 0, &n);
-  counts[i] = n;
-  emit[i] = act == kActM2L ? (1ull << 32) : (act == kActP2P ? 1ull : 0ull);
-}
+static_assert(sizeof(PairCount) <= 4 * sizeof(int64_t), "level totals fit the pinned block");
 
-__global__ void dtt_expand(int64_t nf, const int2 *__restrict__ frontier,
-                           const double4 *__restrict__ geo, const int32_t *__restrict__ n_child,
-                           const int32_t *__restrict__ child_begin, double theta2, int leaf_first,
-                           const int64_t *__restrict__ child_off,
-                           const uint64_t *__restrict__ emit_off, int2 *__restrict__ next,
-                           uint64_t *__restrict__ p2p_keys, int64_t p2p_base,
-                           uint64_t *__restrict__ m2l_keys, int64_t m2l_base, int kb) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nf) return;
-  const int2 pr = frontier[i];
-  const int a = pr.x, b = pr.y;
-  int n;
-  const int act = classify(a, b, geo, n_child, theta2, leaf_first != 0, &n);
-  const uint64_t key = ((uint64_t)(uint32_t)a << kb) | (uint32_t)b;
-  if (act == kActM2L) {
-    m2l_keys[m2l_base + (int64_t)(emit_off[i] >> 32)] = key;
-  } else if (act == kActP2P) {
-    p2p_keys[p2p_base + (int64_t)(emit_off[i] & 0xffffffffull)] = key;
-  } else {
-    int2 *out = next + child_off[i];
-    if (act == kActSplitBoth) {
-      const int c0 = child_begin[a], nc = n_child[a];
-      for (int x = 0; x < nc; ++x)
-        for (int y = 0; y < nc; ++y) out[x * nc + y] = make_int2(c0 + x, c0 + y);
-    } else if (act == kActSplitA) {
-      const int c0 = child_begin[a];
-      for (int x = 0; x < n; ++x) out[x] = make_int2(c0 + x, b);
+struct ClassifyPair {
+  const int2 *frontier;
+  const double4 *geo;
+  const int32_t *n_child;
+  double theta2;
+  int leaf_first;
+  __device__ PairCount operator()(int64_t i) const {
+    const int2 pr = frontier[i];
+    int n;
+    const int act = classify(pr.x, pr.y, geo, n_child, theta2, leaf_first != 0, &n);
+    return PairCount{n, act == kActM2L ? (1ull << 32) : (act == kActP2P ? 1ull : 0ull), act};
+  }
+};
+
+// Writes the pair's child pairs into the next frontier, or its list entry
+// (key target << kb | source), at the offsets the scan gives it.
+template <typename K>
+struct ExpandPair {
+  const int2 *frontier;
+  const int32_t *n_child, *child_begin;
+  int2 *next;
+  K *p2p_keys, *m2l_keys;
+  int64_t p2p_base, m2l_base;
+  int kb;
+  __device__ void operator()(int64_t i, PairCount off, PairCount v) const {
+    const int2 pr = frontier[i];
+    const int a = pr.x, b = pr.y;
+    const K key = ((K)(uint32_t)a << kb) | (K)(uint32_t)b;
+    if (v.act == kActM2L) {
+      m2l_keys[m2l_base + (int64_t)(off.emit >> 32)] = key;
+    } else if (v.act == kActP2P) {
+      p2p_keys[p2p_base + (int64_t)(off.emit & 0xffffffffull)] = key;
     } else {
-      const int c0 = child_begin[b];
-      for (int y = 0; y < n; ++y) out[y] = make_int2(a, c0 + y);
+      int2 *out = next + off.children;
+      const int n = (int)v.children;
+      if (v.act == kActSplitBoth) {
+        const int c0 = child_begin[a], nc = n_child[a];
+        for (int x = 0; x < nc; ++x)
+          for (int y = 0; y < nc; ++y) out[x * nc + y] = make_int2(c0 + x, c0 + y);
+      } else if (v.act == kActSplitA) {
+        const int c0 = child_begin[a];
+        for (int x = 0; x < n; ++x) out[x] = make_int2(c0 + x, b);
+      } else {
+        const int c0 = child_begin[b];
+        for (int y = 0; y < n; ++y) out[y] = make_int2(a, c0 + y);
+      }
     }
   }
-}
+};
 
 // CSR from sorted keys: row_ptr[r] = first key with target >= r.
-__global__ void csr_rows(int64_t n_rows, const uint64_t *__restrict__ keys, int64_t nnz,
-                         int kb, int64_t *__restrict__ row_ptr) {
+template <typename K>
+__global__ void csr_rows(int64_t n_rows, const K *__restrict__ keys, int64_t nnz, int kb,
+                         int64_t *__restrict__ row_ptr) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r > n_rows) return;
-  const uint64_t want = (uint64_t)r << kb;
+  // (row n_rows may not fit the key type: every key is below it)
+  if (r == n_rows) {
+    row_ptr[r] = nnz;
+    return;
+  }
+  const K want = (K)r << kb;
   int64_t lo = 0, hi = nnz;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
@@ -145,10 +149,11 @@ __global__ void csr_rows(int64_t n_rows, const uint64_t *__restrict__ keys, int6
   row_ptr[r] = lo;
 }
 
-__global__ void csr_cols(int64_t nnz, const uint64_t *__restrict__ keys, int kb,
+template <typename K>
+__global__ void csr_cols(int64_t nnz, const K *__restrict__ keys, int kb,
                          int32_t *__restrict__ col) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nnz) col[i] = (int32_t)(keys[i] & ((1ull << kb) - 1));
+  if (i < nnz) col[i] = (int32_t)(keys[i] & (((K)1 << kb) - 1));
 }
 
 // Growable scratch buffer from the device's stream-ordered memory pool:
@@ -184,12 +189,13 @@ struct Buf {
   }
 };
 
-// Two 64-bit values read back by the host: allocated pinned (once per owner)
-// so that one small device-to-host copy lands directly in them.
+// A few values that kernels write straight into pinned host memory (mapped
+// into the device's address space) and the host reads after a stream
+// synchronisation; allocated once per owner.
 struct Pinned {
   int64_t *p = nullptr;
   hipError_t get() {
-    return p ? hipSuccess : hipHostMalloc((void **)&p, 2 * sizeof(int64_t), hipHostMallocDefault);
+    return p ? hipSuccess : hipHostMalloc((void **)&p, 4 * sizeof(int64_t), hipHostMallocMapped);
   }
   ~Pinned() {
     if (p) (void)hipHostFree(p);
@@ -240,24 +246,23 @@ int keep_pool_memory() {
 
 namespace {
 
-int sort_to_csr(uint64_t *keys, int64_t nnz, int64_t n_rows, int kb, hipStream_t st, Buf &alt,
+template <typename K>
+int sort_to_csr(K *keys, int64_t nnz, int64_t n_rows, int kb, hipStream_t st, Buf &alt,
                 Buf &temp, int64_t *row_ptr_dev, int32_t *col_dev) {
   if (nnz > 0) {
-    TRY(alt.reserve(nnz * sizeof(uint64_t), st, false));
-    hipcub::DoubleBuffer<uint64_t> db(keys, (uint64_t *)alt.p);
-    size_t tb = 0;
-    TRY(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, db, (int)nnz, 0, 2 * kb, st));
-    TRY(temp.reserve(tb, st, false));
-    TRY(hipcub::DeviceRadixSort::SortKeys(temp.p, tb, db, (int)nnz, 0, 2 * kb, st));
-    const uint64_t *sorted = db.Current();
-    csr_rows<<<blocks_for(n_rows + 1, 256), 256, 0, st>>>(n_rows, sorted, nnz, kb, row_ptr_dev);
-    csr_cols<<<blocks_for(nnz, 256), 256, 0, st>>>(nnz, sorted, kb, col_dev);
+    TRY(alt.reserve(nnz * sizeof(K), st, false));
+    TRY(temp.reserve(prims::radix_scratch_bytes(nnz), st, false));
+    bool in_alt = false;
+    TRY(prims::radix_sort<K>(keys, (K *)alt.p, nullptr, nullptr, nnz, 0, 2 * kb, temp.p, st,
+                             &in_alt));
+    const K *sorted = in_alt ? (const K *)alt.p : keys;
+    csr_rows<K><<<blocks_for(n_rows + 1, 256), 256, 0, st>>>(n_rows, sorted, nnz, kb, row_ptr_dev);
+    csr_cols<K><<<blocks_for(nnz, 256), 256, 0, st>>>(nnz, sorted, kb, col_dev);
   } else {
     TRY(hipMemsetAsync(row_ptr_dev, 0, (n_rows + 1) * sizeof(int64_t), st));
   }
   return (int)hipGetLastError();
 }
-
 
 // ---------------------------------------------------------------------------
 // Tree build on the GPU (section 3.3; same rules as tree.cpp, same FP64
@@ -577,11 +582,11 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
   // large pool blocks costs milliseconds); at most kKeepScratchBytes are
   // kept between calls.
   struct Scratch {
-    Buf front[2], counts, emit, coff, eoff, temp, p2p, m2l, alt, tot;
-    Pinned host;  // the level totals, read back once per level
+    Buf front[2], part, temp, p2p, m2l, alt;
+    Pinned host;  // the level totals, written there by the scan
     size_t bytes() const {
-      return front[0].bytes + front[1].bytes + counts.bytes + emit.bytes + coff.bytes +
-             eoff.bytes + temp.bytes + p2p.bytes + m2l.bytes + alt.bytes + tot.bytes;
+      return front[0].bytes + front[1].bytes + part.bytes + temp.bytes + p2p.bytes + m2l.bytes +
+             alt.bytes;
     }
   };
   // (a heap array that is never destroyed: no HIP call at process exit)
@@ -596,82 +601,79 @@ int dual_traverse_gpu(int64_t n_cells, const double *geo, const int32_t *child_b
   }
   if (!sc) sc.reset(new Scratch);
   Buf(&front)[2] = sc->front;
-  Buf &counts = sc->counts, &emit = sc->emit, &coff = sc->coff, &eoff = sc->eoff,
-      &temp = sc->temp, &p2p = sc->p2p, &m2l = sc->m2l, &alt = sc->alt, &tot = sc->tot;
+  Buf &part = sc->part, &temp = sc->temp, &p2p = sc->p2p, &m2l = sc->m2l, &alt = sc->alt;
+  TRY(sc->host.get());
+  // the device's address of the pinned block (the scan's last phase writes there)
+  PairCount *level_total = reinterpret_cast<PairCount *>(sc->host.p);
+  PairCount *level_total_dev = nullptr;
+  TRY(hipHostGetDevicePointer((void **)&level_total_dev, sc->host.p, 0));
   int64_t nf = n_cells > 0 ? 1 : 0, n_p2p = 0, n_m2l = 0;
   TRY(front[0].reserve(sizeof(int2), st, false));
   if (nf) {
     const int2 root = make_int2(0, 0);
     TRY(hipMemcpyAsync(front[0].p, &root, sizeof(int2), hipMemcpyHostToDevice, st));
   }
-  // Counts stay below 2^31 (the sort and the scans take 32-bit sizes);
+  // Counts stay below 2^31 (the sort and the list offsets count in 32 bits);
   // FMM_TRAVERSE_LIMIT lowers the limit so that the failure path can be tested.
   int64_t limit = INT32_MAX;
   if (const char *lim = std::getenv("FMM_TRAVERSE_LIMIT")) {
     const long long v = std::atoll(lim);
     if (v > 0 && v < limit) limit = v;
   }
-  int cur = 0;
-  while (nf > 0) {
-    if (nf > limit) return kTraverseTooLarge;
-    TRY(counts.reserve(nf * sizeof(int64_t), st, false));
-    TRY(emit.reserve(nf * sizeof(uint64_t), st, false));
-    TRY(coff.reserve(nf * sizeof(int64_t), st, false));
-    TRY(eoff.reserve(nf * sizeof(uint64_t), st, false));
-    dtt_count<<<blocks_for(nf, 256), 256, 0, st>>>(nf, (const int2 *)front[cur].p, g, n_child,
-                                                   theta2, leaf_first, (int64_t *)counts.p,
-                                                   (uint64_t *)emit.p);
-    TRY(hipGetLastError());
-    size_t tb1 = 0, tb2 = 0;
-    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb1, (int64_t *)counts.p, (int64_t *)coff.p,
-                                         (int)nf, st));
-    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, (uint64_t *)emit.p, (uint64_t *)eoff.p,
-                                         (int)nf, st));
-    TRY(temp.reserve(tb1 > tb2 ? tb1 : tb2, st, false));
-    TRY(hipcub::DeviceScan::ExclusiveSum(temp.p, tb1, (int64_t *)counts.p, (int64_t *)coff.p,
-                                         (int)nf, st));
-    TRY(hipcub::DeviceScan::ExclusiveSum(temp.p, tb2, (uint64_t *)emit.p, (uint64_t *)eoff.p,
-                                         (int)nf, st));
-    // totals = last offset + last count, both read back in one copy
-    TRY(tot.reserve(2 * sizeof(int64_t), st, false));
-    TRY(sc->host.get());
-    level_totals<<<1, 1, 0, st>>>(nf, (const int64_t *)coff.p, (const int64_t *)counts.p,
-                                  (const uint64_t *)eoff.p, (const uint64_t *)emit.p,
-                                  (int64_t *)tot.p);
-    TRY(hipGetLastError());
-    TRY(hipMemcpyAsync(sc->host.p, tot.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
-    const int64_t n_next = sc->host.p[0];
-    const uint64_t e_tot = (uint64_t)sc->host.p[1];
-    const int64_t add_p2p = (int64_t)(e_tot & 0xffffffffull), add_m2l = (int64_t)(e_tot >> 32);
-    if (n_p2p + add_p2p > limit || n_m2l + add_m2l > limit) return kTraverseTooLarge;
-    TRY(front[1 - cur].reserve((n_next > 0 ? n_next : 1) * sizeof(int2), st, false));
-    TRY(p2p.reserve((n_p2p + add_p2p + 1) * sizeof(uint64_t), st, true));
-    TRY(m2l.reserve((n_m2l + add_m2l + 1) * sizeof(uint64_t), st, true));
-    dtt_expand<<<blocks_for(nf, 256), 256, 0, st>>>(
-        nf, (const int2 *)front[cur].p, g, n_child, child_begin, theta2, leaf_first,
-        (const int64_t *)coff.p, (const uint64_t *)eoff.p, (int2 *)front[1 - cur].p,
-        (uint64_t *)p2p.p, n_p2p, (uint64_t *)m2l.p, n_m2l, kb);
-    TRY(hipGetLastError());
-    n_p2p += add_p2p;
-    n_m2l += add_m2l;
-    nf = n_next;
-    cur = 1 - cur;
-    ++n_levels;
-  }
-  const auto t_front = now();
-  TRY(hipMalloc((void **)&out.p2p_ptr, (n_cells + 1) * sizeof(int64_t)));
-  TRY(hipMalloc((void **)&out.m2l_ptr, (n_cells + 1) * sizeof(int64_t)));
-  TRY(hipMalloc((void **)&out.p2p_col, (n_p2p > 0 ? n_p2p : 1) * sizeof(int32_t)));
-  TRY(hipMalloc((void **)&out.m2l_col, (n_m2l > 0 ? n_m2l : 1) * sizeof(int32_t)));
-  out.p2p_nnz = n_p2p;
-  out.m2l_nnz = n_m2l;
-  if (int rc = sort_to_csr((uint64_t *)p2p.p, n_p2p, n_cells, kb, st, alt, temp, out.p2p_ptr,
-                           out.p2p_col))
-    return rc;
-  if (int rc = sort_to_csr((uint64_t *)m2l.p, n_m2l, n_cells, kb, st, alt, temp, out.m2l_ptr,
-                           out.m2l_col))
-    return rc;
+  auto t_front = now();
+  // The levels and the sort, for 32-bit or 64-bit keys.
+  auto run = [&]<typename K>(K) -> int {
+    int cur = 0;
+    while (nf > 0) {
+      if (nf > limit) return kTraverseTooLarge;
+      // classify and count (scan phases 1 and 2; the level's totals land in
+      // pinned host memory), then one synchronisation to size the outputs
+      const unsigned nb = prims::tiles_for(nf);
+      TRY(part.reserve(nb * sizeof(PairCount), st, false));
+      const ClassifyPair load{(const int2 *)front[cur].p, g, n_child, theta2, leaf_first ? 1 : 0};
+      prims::scan_reduce_kernel<PairCount><<<nb, prims::kThreads, 0, st>>>(nf, load,
+                                                                           (PairCount *)part.p);
+      prims::scan_partials_kernel<PairCount><<<1, prims::kThreads, 0, st>>>(
+          (int64_t)nb, (PairCount *)part.p, level_total_dev);
+      TRY(hipGetLastError());
+      TRY(hipStreamSynchronize(st));
+      const int64_t n_next = level_total->children;
+      const uint64_t e_tot = level_total->emit;
+      const int64_t add_p2p = (int64_t)(e_tot & 0xffffffffull), add_m2l = (int64_t)(e_tot >> 32);
+      if (n_p2p + add_p2p > limit || n_m2l + add_m2l > limit) return kTraverseTooLarge;
+      TRY(front[1 - cur].reserve((n_next > 0 ? n_next : 1) * sizeof(int2), st, false));
+      TRY(p2p.reserve((n_p2p + add_p2p + 1) * sizeof(K), st, true));
+      TRY(m2l.reserve((n_m2l + add_m2l + 1) * sizeof(K), st, true));
+      // phase 3: the offsets place the child pairs and the list entries
+      const ExpandPair<K> store{(const int2 *)front[cur].p, n_child, child_begin,
+                                (int2 *)front[1 - cur].p, (K *)p2p.p, (K *)m2l.p, n_p2p, n_m2l,
+                                kb};
+      prims::scan_apply_kernel<PairCount><<<nb, prims::kThreads, 0, st>>>(
+          nf, load, store, (const PairCount *)part.p, (PairCount *)nullptr);
+      TRY(hipGetLastError());
+      n_p2p += add_p2p;
+      n_m2l += add_m2l;
+      nf = n_next;
+      cur = 1 - cur;
+      ++n_levels;
+    }
+    t_front = now();
+    TRY(hipMalloc((void **)&out.p2p_ptr, (n_cells + 1) * sizeof(int64_t)));
+    TRY(hipMalloc((void **)&out.m2l_ptr, (n_cells + 1) * sizeof(int64_t)));
+    TRY(hipMalloc((void **)&out.p2p_col, (n_p2p > 0 ? n_p2p : 1) * sizeof(int32_t)));
+    TRY(hipMalloc((void **)&out.m2l_col, (n_m2l > 0 ? n_m2l : 1) * sizeof(int32_t)));
+    out.p2p_nnz = n_p2p;
+    out.m2l_nnz = n_m2l;
+    if (int rc = sort_to_csr<K>((K *)p2p.p, n_p2p, n_cells, kb, st, alt, temp, out.p2p_ptr,
+                                out.p2p_col))
+      return rc;
+    if (int rc = sort_to_csr<K>((K *)m2l.p, n_m2l, n_cells, kb, st, alt, temp, out.m2l_ptr,
+                                out.m2l_col))
+      return rc;
+    return 0;
+  };
+  const int rc_run = 2 * kb <= 32 ? run(uint32_t{}) : run(uint64_t{});
+  if (rc_run) return rc_run;
   TRY(hipStreamSynchronize(st));
   const auto t_end = now();
   if (sc->bytes() <= kKeepScratchBytes && dev >= 0 && dev < kMaxDevices) {
@@ -715,11 +717,11 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
   // traversal does; freeing large pool blocks costs milliseconds).
   struct TreeScratch {
     Buf boxes, key, idx, key2, idx2, temp, bb, nbd, lv, par, cb, nc, nch, off, gcnt, goff, gtab,
-        gacc, tot;
-    Pinned host;  // scan totals read back by the host
+        gacc, part;
+    Pinned host;  // scan totals, written there by the scans
     size_t bytes() const {
       const Buf *all[] = {&boxes, &key, &idx, &key2, &idx2, &temp, &bb, &nbd, &lv,
-                          &par, &cb, &nc, &nch, &off, &gcnt, &goff, &gtab, &gacc, &tot};
+                          &par, &cb, &nc, &nch, &off, &gcnt, &goff, &gtab, &gacc, &part};
       size_t s = 0;
       for (const Buf *b : all) s += b->bytes;
       return s;
@@ -735,14 +737,16 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
     if (dev >= 0 && dev < kMaxDevices) sc = std::move(cache[dev]);
   }
   if (!sc) sc.reset(new TreeScratch);
-  // total of an exclusive scan (last offset + last count), one small copy
-  // into pinned memory
-  auto scan_total = [&](const int32_t *offs, const int32_t *cnts, int64_t m, int64_t *res) -> int {
-    TRY(sc->tot.reserve(sizeof(int64_t), st, false));
-    TRY(sc->host.get());
-    scan_total_i32<<<1, 1, 0, st>>>(m, offs, cnts, (int64_t *)sc->tot.p);
-    TRY(hipGetLastError());
-    TRY(hipMemcpyAsync(sc->host.p, sc->tot.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TRY(sc->host.get());
+  int64_t *total_dev = nullptr;  // the device's address of the pinned block
+  TRY(hipHostGetDevicePointer((void **)&total_dev, sc->host.p, 0));
+  // exclusive scan of cnts[0, m) into offs; returns the total to the host
+  // (one synchronisation)
+  auto scan_i32 = [&](const int32_t *cnts, int32_t *offs, int64_t m, int64_t *res) -> int {
+    TRY(sc->part.reserve(prims::scan_scratch_bytes<int64_t>(m), st, false));
+    TRY(prims::exclusive_scan<int64_t>(m, prims::LoadArray<int64_t, int32_t>{cnts},
+                                       prims::StoreArray<int64_t, int32_t>{offs},
+                                       (int64_t *)sc->part.p, total_dev, st));
     TRY(hipStreamSynchronize(st));
     *res = sc->host.p[0];
     return 0;
@@ -800,14 +804,12 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
                                                   2.0 * h, h == 0.0, (uint64_t *)key.p,
                                                   (int32_t *)idx.p);
   TRY(hipGetLastError());
-  hipcub::DoubleBuffer<uint64_t> dk((uint64_t *)key.p, (uint64_t *)key2.p);
-  hipcub::DoubleBuffer<int32_t> dv((int32_t *)idx.p, (int32_t *)idx2.p);
-  size_t tb = 0;
-  TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, dk, dv, (int)n, 0, 63, st));
-  TRY(temp.reserve(tb, st, false));
-  TRY(hipcub::DeviceRadixSort::SortPairs(temp.p, tb, dk, dv, (int)n, 0, 63, st));
-  const uint64_t *skeys = dk.Current();
-  const int32_t *sperm = dv.Current();
+  TRY(temp.reserve(prims::radix_scratch_bytes(n), st, false));
+  bool in_alt = false;
+  TRY(prims::radix_sort<uint64_t>((uint64_t *)key.p, (uint64_t *)key2.p, (int32_t *)idx.p,
+                                  (int32_t *)idx2.p, n, 0, 63, temp.p, st, &in_alt));
+  const uint64_t *skeys = in_alt ? (const uint64_t *)key2.p : (const uint64_t *)key.p;
+  const int32_t *sperm = in_alt ? (const int32_t *)idx2.p : (const int32_t *)idx.p;
   TRY(hipMalloc((void **)&out.perm, n * 4));
   TRY(hipMemcpyAsync(out.perm, sperm, n * 4, hipMemcpyDeviceToDevice, st));
   TRY(hipMalloc((void **)&out.pos, n * 24));
@@ -848,14 +850,8 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
                                                        (const int64_t *)bb.p,
                                                        (const int64_t *)nbd.p, (int32_t *)nch.p);
     TRY(hipGetLastError());
-    size_t tsb = 0;
-    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tsb, (int32_t *)nch.p, (int32_t *)off.p, (int)m,
-                                         st));
-    TRY(temp.reserve(tsb, st, false));
-    TRY(hipcub::DeviceScan::ExclusiveSum(temp.p, tsb, (int32_t *)nch.p, (int32_t *)off.p, (int)m,
-                                         st));
     int64_t added = 0;
-    if (int rc = scan_total((const int32_t *)off.p, (const int32_t *)nch.p, m, &added)) return rc;
+    if (int rc = scan_i32((const int32_t *)nch.p, (int32_t *)off.p, m, &added)) return rc;
     TRY(grow(c1 + added));
     write_children<<<blocks_for(m, 256), 256, 0, st>>>(
         c0, c1, level, skeys, (const int32_t *)nch.p, (const int32_t *)off.p, c1,
@@ -880,15 +876,8 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
     const unsigned gb = blocks_for(ncells, 256);
     geo_chunk_count<<<gb, 256, 0, st>>>(ncells, (const int64_t *)nbd.p, (int32_t *)gcnt.p);
     TRY(hipGetLastError());
-    size_t tsb = 0;
-    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tsb, (int32_t *)gcnt.p, (int32_t *)goff.p,
-                                         (int)ncells, st));
-    TRY(temp.reserve(tsb, st, false));
-    TRY(hipcub::DeviceScan::ExclusiveSum(temp.p, tsb, (int32_t *)gcnt.p, (int32_t *)goff.p,
-                                         (int)ncells, st));
     int64_t nchunks = 0;
-    if (int rc = scan_total((const int32_t *)goff.p, (const int32_t *)gcnt.p, ncells, &nchunks))
-      return rc;
+    if (int rc = scan_i32((const int32_t *)gcnt.p, (int32_t *)goff.p, ncells, &nchunks)) return rc;
     TRY(gtab.reserve(nchunks * 8, st, false));
     geo_chunk_fill<<<gb, 256, 0, st>>>(ncells, (const int32_t *)gcnt.p, (const int32_t *)goff.p,
                                        (uint64_t *)gtab.p, (uint64_t *)gacc.p);
