@@ -600,7 +600,7 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
   // Far field on the caller's stream.
   LAUNCH_TRY(D::p2m(p, fp64, pl.n_leaves, pl.leaf_cell, dt.body_begin, dt.n_body,
                     geo, bodies, mode == D::kDipoles ? vec : nullptr, sc.M, sc.M64, n_top,
-                    stream));
+                    td.n, stream));
   if (int rc = mark(2, s)) return rc;
   for (int lev = max_level - 1; lev >= 0; --lev) {
     const int64_t c0 = td.level_begin[lev], c1 = td.level_begin[lev + 1];

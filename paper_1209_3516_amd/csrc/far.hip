@@ -30,10 +30,15 @@ namespace dev {
 namespace {
 
 // ----------------------------------------------------------------------------
-// P2M: one thread per leaf.  With dipoles (DIP), a body's dipole s adds
-// sum_d s_d (X - x)^(n - e_d) / (n - e_d)! to M_n.
+// P2M: one 64-lane wave per G = 64 / LPL leaves, LPL lanes per leaf (32, or
+// 16 when leaves are small).  Bodies are taken LPL at a time: lane j loads
+// body j (coalesced), forms its term row w_t = q (X - x)^t / t! for every
+// term t (with dipoles s, also sum_d s_d (X - x)^(t - e_d) / (t - e_d)!) and
+// stores the row in LDS; then lane t adds column t over the bodies of the
+// batch, in body order (terms beyond LPL go round again).  The sums need no
+// cross-lane reduction.
 // ----------------------------------------------------------------------------
-template <int P, typename Real, bool DIP>
+template <int P, typename Real, bool DIP, int LPL>
 __global__ __launch_bounds__(64) void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
                            const int32_t *__restrict__ body_begin,
                            const int32_t *__restrict__ n_body, const double4 *__restrict__ geo,
@@ -41,33 +46,66 @@ __global__ __launch_bounds__(64) void p2m_kernel(int64_t n_leaves, const int32_t
                            const typename Vec<Real>::V4 *__restrict__ dip, Real *__restrict__ M,
                            double *__restrict__ M64, int64_t n_top) {
   constexpr int T = nterms(P), S = pad4(T);
-  const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (li >= n_leaves) return;
-  const int c = leaf_cell[li];
+  constexpr int G = 64 / LPL;              // leaves per block
+  constexpr int RS = T + 1;                // LDS row stride (odd: no bank conflicts on reads)
+  constexpr int TPL = (T + LPL - 1) / LPL; // terms per lane
+  __shared__ Real rows[G][LPL * RS];
+  const int grp = threadIdx.x / LPL, j = threadIdx.x % LPL;
+  const int64_t li = G * (int64_t)blockIdx.x + grp;
+  const bool active = li < n_leaves;
+  const int c = active ? leaf_cell[li] : 0;
+  const int b0 = active ? body_begin[c] : 0, nb = active ? n_body[c] : 0;
   const double4 g = geo[c];
-  Real acc[T];
-  static_for<T>([&](auto I) { acc[decltype(I)::value] = Real(0); });
-  const int b0 = body_begin[c], nb = n_body[c];
-  for (int j = 0; j < nb; ++j) {
-    const typename Vec<Real>::V4 b = bodies[b0 + j];
-    Real mono[T];
-    monomials<P, Real>(Real(g.x - (double)b.x), Real(g.y - (double)b.y), Real(g.z - (double)b.z),
-                       mono);
-    static_for<T>([&](auto I) { acc[decltype(I)::value] += b.w * mono[decltype(I)::value]; });
-    if constexpr (DIP) {
-      const typename Vec<Real>::V4 sd = dip[b0 + j];
+  Real *row = rows[grp];
+  Real acc[TPL];
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) acc[k] = Real(0);
+  // every group runs as many batches as the largest leaf of the block needs
+  // (the barrier is block wide)
+  int nbmax = nb;
+#pragma unroll
+  for (int off = LPL; off < 64; off <<= 1) {
+    const int o = __shfl_xor(nbmax, off);
+    nbmax = o > nbmax ? o : nbmax;
+  }
+  for (int j0 = 0; j0 < nbmax; j0 += LPL) {
+    const int nj = min(LPL, nb - j0);
+    if (j < nj) {
+      const typename Vec<Real>::V4 b = bodies[b0 + j0 + j];
+      Real mono[T];
+      monomials<P, Real>(Real(g.x - (double)b.x), Real(g.y - (double)b.y),
+                         Real(g.z - (double)b.z), mono);
+      typename Vec<Real>::V4 sd;
+      if constexpr (DIP) sd = dip[b0 + j0 + j];
       static_for<T>([&](auto I) {
         constexpr int t = decltype(I)::value;
-        if constexpr (kBasis<P>.lo[t][0] >= 0) acc[t] += sd.x * mono[kBasis<P>.lo[t][0]];
-        if constexpr (kBasis<P>.lo[t][1] >= 0) acc[t] += sd.y * mono[kBasis<P>.lo[t][1]];
-        if constexpr (kBasis<P>.lo[t][2] >= 0) acc[t] += sd.z * mono[kBasis<P>.lo[t][2]];
+        Real w = b.w * mono[t];
+        if constexpr (DIP) {
+          if constexpr (kBasis<P>.lo[t][0] >= 0) w += sd.x * mono[kBasis<P>.lo[t][0]];
+          if constexpr (kBasis<P>.lo[t][1] >= 0) w += sd.y * mono[kBasis<P>.lo[t][1]];
+          if constexpr (kBasis<P>.lo[t][2] >= 0) w += sd.z * mono[kBasis<P>.lo[t][2]];
+        }
+        row[j * RS + t] = w;
       });
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      const int t = j + LPL * k;
+      if (t < T)
+        for (int i = 0; i < nj; ++i) acc[k] += row[i * RS + t];
+    }
+    __syncthreads();
   }
-  static_for<T>([&](auto I) { M[(int64_t)c * S + decltype(I)::value] = acc[decltype(I)::value]; });
-  if (c < n_top)
-    static_for<T>(
-        [&](auto I) { M64[(int64_t)c * S + decltype(I)::value] = (double)acc[decltype(I)::value]; });
+  if (!active) return;
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    const int t = j + LPL * k;
+    if (t < T) {
+      M[(int64_t)c * S + t] = acc[k];
+      if (c < n_top) M64[(int64_t)c * S + t] = (double)acc[k];
+    }
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -510,28 +548,32 @@ __global__ __launch_bounds__(256) void l2p_combine_kernel(
 
 int p2m(int p, bool fp64, int64_t n_leaves, const int32_t *leaf_cell, const int32_t *cell_body_begin,
         const int32_t *cell_n_body, const double *geo, const void *bodies, const void *dipoles,
-        void *M, double *M64, int64_t n_top, void *stream) {
+        void *M, double *M64, int64_t n_top, int64_t n_bodies, void *stream) {
   if (n_leaves == 0) return 0;
-  const unsigned nb = blocks_for(n_leaves, 64);
   const double4 *g = (const double4 *)geo;
+  // 16 lanes per leaf when the mean leaf holds at most 16 bodies, else 32
+  const bool small = n_bodies <= 16 * n_leaves;
   return with_p(p, [&](auto PC) {
     constexpr int PP = decltype(PC)::value;
+    auto go = [&](auto LC, auto *b, auto *d, auto *m, int64_t top) {
+      constexpr int LPL = decltype(LC)::value;
+      using R = std::remove_cv_t<std::remove_pointer_t<decltype(m)>>;
+      const unsigned nb = blocks_for(n_leaves, 64 / LPL);
+      if (dipoles)
+        p2m_kernel<PP, R, true, LPL><<<nb, 64, 0, S_(stream)>>>(
+            n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, m, M64, top);
+      else
+        p2m_kernel<PP, R, false, LPL><<<nb, 64, 0, S_(stream)>>>(
+            n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, m, M64, top);
+    };
     if (fp64) {
       const double4 *b = (const double4 *)bodies, *d = (const double4 *)dipoles;
-      if (dipoles)
-        p2m_kernel<PP, double, true><<<nb, 64, 0, S_(stream)>>>(
-            n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, (double *)M, M64, 0);
-      else
-        p2m_kernel<PP, double, false><<<nb, 64, 0, S_(stream)>>>(
-            n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, (double *)M, M64, 0);
+      if (small) go(std::integral_constant<int, 16>{}, b, d, (double *)M, int64_t(0));
+      else go(std::integral_constant<int, 32>{}, b, d, (double *)M, int64_t(0));
     } else {
       const float4 *b = (const float4 *)bodies, *d = (const float4 *)dipoles;
-      if (dipoles)
-        p2m_kernel<PP, float, true><<<nb, 64, 0, S_(stream)>>>(
-            n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, (float *)M, M64, n_top);
-      else
-        p2m_kernel<PP, float, false><<<nb, 64, 0, S_(stream)>>>(
-            n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, (float *)M, M64, n_top);
+      if (small) go(std::integral_constant<int, 16>{}, b, d, (float *)M, n_top);
+      else go(std::integral_constant<int, 32>{}, b, d, (float *)M, n_top);
     }
   });
 }

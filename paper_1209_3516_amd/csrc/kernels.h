@@ -40,9 +40,10 @@ int gather_vectors(bool fp64, int64_t n, const int32_t *perm, const void *v_user
 
 // geo: [n_cells] double4 (centre x, y, z, radius).
 // dipoles: [n] 4-vectors in Morton order, or NULL for charges only.
+// n_bodies: bodies of the tree (the mean leaf size picks the lane layout).
 int p2m(int p, bool fp64, int64_t n_leaves, const int32_t *leaf_cell, const int32_t *cell_body_begin,
         const int32_t *cell_n_body, const double *geo, const void *bodies, const void *dipoles,
-        void *M, double *M64, int64_t n_top, void *stream);
+        void *M, double *M64, int64_t n_top, int64_t n_bodies, void *stream);
 
 // Parents are the cells [c0, c1) of one level; leaves among them are skipped.
 // child_fp64: children's multipoles are read from M64 (else from M).
