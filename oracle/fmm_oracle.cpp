@@ -312,7 +312,27 @@ uint64_t spread_bits(uint64_t v) {
   return out;
 }
 
-void build_tree(const double *xyz, int64_t n, int ncrit, Tree &tr) {
+// Cell geometry.  Default (reading R6): the centre is the middle of the tight
+// bounding box of the cell's bodies.  With `box` (reading R6b, the geometric
+// centre of the cell in the paper's comparison of treecode and FMM, Table 3):
+// the centre of the cell's cube, the cube of side 2h / 2^L of the Morton
+// subdivision of the root cube that holds its key prefix, at
+// (c - h) + (i + 1/2) (2h / 2^L) per axis with i the cell's integer
+// coordinate.  Either way the radius is the largest distance from the
+// centre to a body of the cell.
+double box_centre(double c, double h, int level, uint64_t coord) {
+  const double w = (2.0 * h) / (double)(1ull << level);
+  return (c - h) + ((double)coord + 0.5) * w;
+}
+
+// Integer coordinate along axis d of the level-L cell that holds `key`.
+uint64_t cell_coord(uint64_t key, int level, int d) {
+  uint64_t v = 0;
+  for (int b = 0; b < level; ++b) v |= ((key >> (3 * (20 - level + 1 + b) + d)) & 1ull) << b;
+  return v;
+}
+
+void build_tree(const double *xyz, int64_t n, int ncrit, Tree &tr, bool box = false) {
   tr.n = n;
   tr.ncrit = ncrit;
   tr.cells.clear();
@@ -394,6 +414,9 @@ void build_tree(const double *xyz, int64_t n, int ncrit, Tree &tr) {
       bhi[2] = std::max(bhi[2], tr.zs[j]);
     }
     for (int d = 0; d < 3; ++d) cell.X[d] = 0.5 * (blo[d] + bhi[d]);
+    if (box && h > 0.0)
+      for (int d = 0; d < 3; ++d)
+        cell.X[d] = box_centre(c[d], h, cell.level, cell_coord(tr.keys[b0], cell.level, d));
     double B = 0.0;
     for (int64_t j = b0; j < b0 + cell.n_body; ++j) {
       double dx = tr.xs[j] - cell.X[0], dy = tr.ys[j] - cell.X[1], dz = tr.zs[j] - cell.X[2];
@@ -580,11 +603,12 @@ int oracle_build_hybrid(const double *xyz, int64_t n, int ncrit, double theta, i
   return 0;
 }
 
-// The tree alone; oracle_traverse makes the lists.
-int oracle_build_tree(const double *xyz, int64_t n, int ncrit, oracle_fmm **out) {
+// The tree alone; oracle_traverse makes the lists.  box != 0: cell centres
+// at the centres of the Morton cubes (reading R6b).
+int oracle_build_tree(const double *xyz, int64_t n, int ncrit, int box, oracle_fmm **out) {
   if (n < 0 || ncrit < 1) return -1;
   oracle_fmm *o = new oracle_fmm;
-  build_tree(xyz, n, ncrit, o->tree);
+  build_tree(xyz, n, ncrit, o->tree, box != 0);
   o->lists = Lists();
   o->lists.n_rows = (int64_t)o->tree.cells.size();
   *out = o;

@@ -31,7 +31,7 @@ def _load():
     lib.oracle_build.restype = i32
     lib.oracle_build_hybrid.argtypes = [vp, i64, i32, dbl, i32, i32, ctypes.POINTER(vp)]
     lib.oracle_build_hybrid.restype = i32
-    lib.oracle_build_tree.argtypes = [vp, i64, i32, ctypes.POINTER(vp)]
+    lib.oracle_build_tree.argtypes = [vp, i64, i32, i32, ctypes.POINTER(vp)]
     lib.oracle_build_tree.restype = i32
     lib.oracle_traverse.argtypes = [vp, dbl, i32, i32, vp, i64]
     lib.oracle_traverse.restype = i32
@@ -112,18 +112,22 @@ class OracleFMM:
     m2p_max > 0: the treecode/FMM hybrid lists (accepted pairs whose target is
     a leaf of at most m2p_max bodies go to the M2P list, kind 2)."""
 
-    def __init__(self, xyz, ncrit, theta, leaf_first=False, m2p_max=0, select_leaves=None):
+    def __init__(self, xyz, ncrit, theta, leaf_first=False, m2p_max=0, select_leaves=None,
+                 box_centres=False):
         """select_leaves: None for the whole traversal, or a function of the
         tree (the dict of tree()) returning leaf cells; the lists then hold only
         the rows of those leaves and of their ancestors (the restricted
-        traversal), enough for evaluate_leaves on them."""
+        traversal), enough for evaluate_leaves on them.  box_centres: cell
+        centres at the centres of the Morton cubes instead of the middles of
+        the cells' bounding boxes."""
         lib = _load()
         self.xyz = _f64(xyz, (-1, 3))
         self.n = self.xyz.shape[0]
         h = ctypes.c_void_p()
         self.restricted_to = None
         t0 = time.perf_counter()
-        if lib.oracle_build_tree(_p(self.xyz), self.n, int(ncrit), ctypes.byref(h)) != 0:
+        if lib.oracle_build_tree(_p(self.xyz), self.n, int(ncrit), 1 if box_centres else 0,
+                                 ctypes.byref(h)) != 0:
             raise ValueError("oracle_build_tree failed")
         t1 = time.perf_counter()
         self._h = h
