@@ -63,13 +63,20 @@ enum fmm_traverse_flags {
 };
 
 enum fmm_list_kind { FMM_P2P = 0, FMM_M2L = 1, FMM_M2P = 2 };
+
+/* Flags of fmm_tree_build_ex. */
+enum fmm_tree_flags {
+  FMM_TREE_BOX_CENTRES = 1u /* expansion centres at the centres of the Morton cubes */
+};
 enum { FMM_MAX_M2P = 64 }; /* largest m2p_max of fmm_traverse_hybrid */
 
 enum fmm_eval_flags {
   FMM_EVAL_TIMING = 1, /* record per-phase device times (fmm_last_timings) */
   FMM_EVAL_KEEP_STAGES = 2, /* keep a copy of the locals after M2L (fmm_copy_expansions) */
-  FMM_EVAL_SERIAL = 4 /* run P2P on the caller's stream instead of overlapping it with the
-                         upward pass, M2L and L2L on a second (library-owned) stream */
+  FMM_EVAL_SERIAL = 4, /* run P2P on the caller's stream instead of overlapping it with the
+                          upward pass, M2L and L2L on a second (library-owned) stream */
+  FMM_EVAL_M2L_MFMA = 8 /* M2L batched by translation vector on the matrix cores; needs a
+                           tree built with FMM_TREE_BOX_CENTRES and FMM_MIXED precision */
 };
 
 /* Phases reported by fmm_last_timings, in this order.  Without FMM_EVAL_SERIAL
@@ -140,6 +147,20 @@ typedef struct fmm_lists_stats_t {
  * Host only: no GPU is touched.  *out is owned by the caller until fmm_tree_free.
  */
 int fmm_tree_build(const double *xyz, int64_t n, int ncrit, fmm_tree **out);
+
+/*
+ * fmm_tree_build with options.  flags: 0 (the same tree as fmm_tree_build) or
+ * FMM_TREE_BOX_CENTRES: every cell's expansion centre is the geometric centre
+ * of its cube in the Morton subdivision of the root cube (the geometric
+ * centre of the paper's Table 3), (c_d - h) + (i_d + 1/2) 2h / 2^L for a
+ * level-L cell with integer coordinates i, instead of the middle of its
+ * bodies' bounding box; the radius stays the largest centre-to-body distance.
+ * Translation vectors between such centres are multiples of half a cube
+ * side, so they repeat across the tree (what the MFMA M2L of
+ * FMM_EVAL_M2L_MFMA batches over).  Other arguments and errors as
+ * fmm_tree_build; FMM_EINVAL for unknown flags.  Host only.
+ */
+int fmm_tree_build_ex(const double *xyz, int64_t n, int ncrit, unsigned flags, fmm_tree **out);
 
 /*
  * The same tree built on the GPU (bounding-box reduction, Morton keys with

@@ -16,8 +16,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SOURCES = ["tree.cpp", "traverse.cpp", "plan.cpp", "shard.cpp", "api.cpp"]
-DEVICE_SOURCES = ["p2p.hip", "far.hip", "misc.hip", "tree_gpu.hip", "plan_gpu.hip", "noalloc.hip"]
+HOST_SOURCES = ["tree.cpp", "traverse.cpp", "plan.cpp", "shard.cpp", "m2l_plan.cpp", "api.cpp"]
+DEVICE_SOURCES = ["p2p.hip", "far.hip", "misc.hip", "tree_gpu.hip", "plan_gpu.hip", "noalloc.hip",
+                  "m2l_mfma.hip"]
 # Sources whose FP64 arithmetic must match the host bit for bit (no FMA contraction).
 EXACT_SOURCES = {"tree_gpu.hip"}
 

@@ -95,6 +95,16 @@ struct DevLists {
   void *tmp_phi = nullptr, *tmp_grad = nullptr;
   void *vec4 = nullptr, *tmp_hv = nullptr;  // backward with a gradient upstream
   bool stage_valid = false;
+  // batched M2L of box-centred trees: the plan (built on first use) and the
+  // derivative table of its vectors for order dtab_p
+  bool mfma_ready = false;
+  int32_t *mt_cells = nullptr, *mt_goff = nullptr, *mt_gsrc = nullptr;
+  int64_t *mt_gbeg = nullptr;
+  double *mt_off = nullptr;
+  float *mt_dtab = nullptr;
+  int mt_dtab_p = 0;
+  int64_t mt_n_tiles = 0, mt_n_groups = 0, mt_n_off = 0;
+  std::vector<int64_t> mt_level_tile;
   // near-field stream (forked from / joined into the caller's stream)
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
@@ -116,7 +126,8 @@ struct DevLists {
   void release() {
     release_scratch();
     plan.release();
-    void *ptrs[] = {m2l_ptr, m2l_col, p2p_ptr, p2p_col, m2p_ptr, m2p_col, m2p_rows};
+    void *ptrs[] = {m2l_ptr, m2l_col, p2p_ptr, p2p_col, m2p_ptr, m2p_col, m2p_rows,
+                    mt_cells, mt_goff, mt_gsrc, mt_gbeg, mt_off, mt_dtab};
     for (void *p2 : ptrs)
       if (p2) (void)hipFree(p2);
     if (have_events)
@@ -370,6 +381,52 @@ int ensure_lists_host(fmm_lists *l) {
   return FMM_OK;
 }
 
+// The batched M2L's plan on the device (built on the host on first use from
+// the host copy of the lists) and its derivative table for order p.
+int ensure_m2l_mfma(fmm_tree *t, fmm_lists *l, int p, void *stream) {
+  DevLists &dv = l->dev;
+  if (!t->data.box_centres) {
+    set_error("FMM_EVAL_M2L_MFMA needs a tree built with FMM_TREE_BOX_CENTRES");
+    return FMM_EINVAL;
+  }
+  if (!dv.mfma_ready) {
+    if (int rc = ensure_lists_host(l)) return rc;
+    const auto t0 = std::chrono::steady_clock::now();
+    fmmlib::M2LTilePlan plan;
+    std::string err;
+    if (int rc = fmmlib::build_m2l_tile_plan(t->data, l->data, plan, err)) {
+      set_error(err);
+      return rc;
+    }
+    if (int rc = dev_upload(&dv.mt_cells, plan.tile_cells.data(), plan.tile_cells.size())) return rc;
+    if (int rc = dev_upload(&dv.mt_gbeg, plan.tile_group_begin.data(), plan.tile_group_begin.size()))
+      return rc;
+    if (int rc = dev_upload(&dv.mt_goff, plan.group_offset.data(), plan.group_offset.size()))
+      return rc;
+    if (int rc = dev_upload(&dv.mt_gsrc, plan.group_src.data(), plan.group_src.size())) return rc;
+    if (int rc = dev_upload(&dv.mt_off, plan.offsets.data(), plan.offsets.size())) return rc;
+    dv.mt_n_tiles = plan.n_tiles;
+    dv.mt_n_groups = plan.n_groups;
+    dv.mt_n_off = plan.n_offsets;
+    dv.mt_level_tile = plan.level_tile_begin;
+    dv.mfma_ready = true;
+    if (std::getenv("FMM_LOG"))
+      std::fprintf(stderr, "[fmm] batched M2L plan: %lld tiles, %lld groups, %lld vectors, %.1f ms\n",
+                   (long long)plan.n_tiles, (long long)plan.n_groups, (long long)plan.n_offsets,
+                   ms_since(t0));
+  }
+  if (dv.mt_dtab_p != p) {
+    if (dv.mt_dtab) (void)hipFree(dv.mt_dtab);
+    dv.mt_dtab = nullptr;
+    dv.mt_dtab_p = 0;
+    HIP_TRY(hipMalloc((void **)&dv.mt_dtab,
+                      std::max<int64_t>(1, dv.mt_n_off) * fmmlib::dev::terms(p) * sizeof(float)));
+    HIP_TRY((hipError_t)fmmlib::dev::m2l_offsets(p, dv.mt_n_off, dv.mt_off, dv.mt_dtab, stream));
+    dv.mt_dtab_p = p;
+  }
+  return FMM_OK;
+}
+
 // Leaf index of the tree and first P2P work item of every leaf.
 int ensure_range_tables(fmm_tree *t, fmm_lists *l) {
   if (!t->leaf_ix_valid) {
@@ -461,8 +518,12 @@ int check_opts(const fmm_eval_opts *o) {
     set_error("fp64_top_levels must be -2, -1 or 0..21");
     return FMM_EINVAL;
   }
-  if (o->flags & ~(FMM_EVAL_TIMING | FMM_EVAL_KEEP_STAGES | FMM_EVAL_SERIAL)) {
+  if (o->flags & ~(FMM_EVAL_TIMING | FMM_EVAL_KEEP_STAGES | FMM_EVAL_SERIAL | FMM_EVAL_M2L_MFMA)) {
     set_error("unknown evaluation flags");
+    return FMM_EINVAL;
+  }
+  if ((o->flags & FMM_EVAL_M2L_MFMA) && o->precision != FMM_MIXED) {
+    set_error("FMM_EVAL_M2L_MFMA runs in FP32: it needs FMM_MIXED precision");
     return FMM_EINVAL;
   }
   return FMM_OK;
@@ -626,7 +687,23 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
                           false, stream));
       return FMM_OK;
     };
-    if (!ranged) {
+    const bool mfma = (o->flags & FMM_EVAL_M2L_MFMA) != 0;
+    if (mfma && (ranged || !dv.mfma_ready || dv.mt_dtab_p != p)) {
+      set_error("FMM_EVAL_M2L_MFMA: not for target ranges, and the plan must be on the device");
+      return FMM_EINVAL;
+    }
+    if (mfma) {
+      // FP64-accumulated top levels entry by entry, the rest batched
+      if (n_top > 0) {
+        LAUNCH_TRY(D::m2l(p, fp64, 0, n_top, dv.m2l_ptr, dv.m2l_col, geo, sc.Mr, sc.L, sc.L64,
+                          true, stream));
+      }
+      int lev0 = 0;
+      while (lev0 <= max_level && td.level_begin[lev0] < n_top) ++lev0;
+      LAUNCH_TRY(D::m2l_mfma(p, dv.mt_level_tile[lev0], dv.mt_n_tiles, dv.mt_cells, dv.mt_gbeg,
+                             dv.mt_goff, dv.mt_gsrc, dv.mt_dtab, (const float *)sc.Mr,
+                             (float *)sc.L, stream));
+    } else if (!ranged) {
       if (int rc = m2l_cells(0, td.n_cells())) return rc;
     } else {
       for (int lev = 0; lev <= max_level; ++lev)
@@ -679,6 +756,8 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   if (int rc = ensure_tree_device(t, fp64, stream)) return rc;
   if (int rc = ensure_lists_device(t, l)) return rc;
   if (int rc = ensure_scratch(t, l, o)) return rc;
+  if (o->flags & FMM_EVAL_M2L_MFMA)
+    if (int rc = ensure_m2l_mfma(t, l, o->p, stream)) return rc;
   return enqueue_evaluation(t, l, o, scratch_of(l->dev), false, q, phi, grad, stream, mode,
                             v_user, rb0, rb1);
 }
@@ -745,8 +824,16 @@ int fmm_term_exponents(int p, int32_t *exps) {
 }
 
 int fmm_tree_build(const double *xyz, int64_t n, int ncrit, fmm_tree **out) {
+  return fmm_tree_build_ex(xyz, n, ncrit, 0u, out);
+}
+
+int fmm_tree_build_ex(const double *xyz, int64_t n, int ncrit, unsigned flags, fmm_tree **out) {
   if (!out || n < 0 || ncrit < 1 || (n > 0 && !xyz)) {
     set_error("fmm_tree_build: need out != NULL, n >= 0, ncrit >= 1, xyz != NULL");
+    return FMM_EINVAL;
+  }
+  if (flags & ~(unsigned)FMM_TREE_BOX_CENTRES) {
+    set_error("fmm_tree_build_ex: unknown flags");
     return FMM_EINVAL;
   }
   if (n > (int64_t)INT32_MAX - 1) {
@@ -759,7 +846,9 @@ int fmm_tree_build(const double *xyz, int64_t n, int ncrit, fmm_tree **out) {
   try {
     t = new fmm_tree();
     std::string err;
-    const int rc = fmmlib::build_tree(xyz, n, ncrit, t->data, err);
+    const bool box = (flags & FMM_TREE_BOX_CENTRES) != 0;
+    const int rc = fmmlib::build_tree(xyz, n, ncrit, t->data, err, box);
+    t->data.box_centres = box;
     if (rc != FMM_OK) {
       delete t;
       set_error(err);

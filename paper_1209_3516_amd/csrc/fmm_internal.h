@@ -17,6 +17,7 @@ struct TreeData {
   int64_t n_leaves = 0;
   bool fp32_exact = true;
   bool moved = false;        // positions replaced after the build
+  bool box_centres = false;  // centres of the Morton cubes (built on the host only)
   uint64_t id = 0;           // identifies the tree for lists built from it
   uint64_t pos_version = 0;  // bumped by set_positions
   double root_center[3] = {0, 0, 0};
@@ -90,7 +91,10 @@ void alloc_checkpoint();
 void reset_alloc_checkpoints();
 constexpr int kP2PChunkSources = 8192;
 
-int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string &err);
+// box_centres: cell centres at the centres of the Morton cubes (else the
+// middles of the cells' bounding boxes).
+int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string &err,
+               bool box_centres = false);
 void dual_traverse(const TreeData &t, double theta, bool leaf_first, int m2p_max, ListData &l);
 // p2p_pairs and max_row_sources of finished lists.
 void list_statistics(const TreeData &t, ListData &l);
@@ -101,6 +105,22 @@ int64_t plan_index_limit();
 // Builds the plan of finished lists.  FMM_OK, or FMM_EINVAL with `err` set
 // when its runs, work items or partial slots exceed plan_index_limit().
 int build_p2p_plan(const TreeData &t, const ListData &l, P2PPlan &plan, std::string &err);
+
+// Batched M2L for box-centred trees: tiles of kM2LTile target cells (one
+// level, one octant class), each with groups of entries sharing one
+// (source level, translation vector).  Built on the host from the lists.
+constexpr int kM2LTile = 16;
+struct M2LTilePlan {
+  std::vector<int32_t> tile_cells;        // [n_tiles][kM2LTile], -1 = no cell
+  std::vector<int64_t> level_tile_begin;  // tiles of level L: [b[L], b[L+1])
+  std::vector<int64_t> tile_group_begin;  // [n_tiles + 1]
+  std::vector<int32_t> group_offset;      // [n_groups]: index into offsets
+  std::vector<int32_t> group_src;         // [n_groups][kM2LTile]: source cell or -1
+  std::vector<double> offsets;            // [n_offsets][3]: X_A - X_B
+  int64_t n_tiles = 0, n_groups = 0, n_offsets = 0;
+};
+int build_m2l_tile_plan(const TreeData &t, const ListData &l, M2LTilePlan &plan,
+                        std::string &err);
 
 // fmm_evaluate with every device buffer of the evaluation carved out of a
 // fixed device buffer of scratch_bytes, whose address on the current device

@@ -57,6 +57,17 @@ int m2m(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *child_begin,
 // harmonic).  Cells [0, n_cells).
 int fold_multipoles(int p, bool fp64, int64_t n_cells, const void *M, void *Mr, void *stream);
 
+// Batched M2L of box-centred trees (m2l_mfma.hip).  m2l_offsets: FP32
+// derivative rows dtab[n_off][terms(p)] of the vectors off[n_off][3].
+// m2l_mfma: the tiles [tile0, tile1) of the plan (FP32 multipoles Mr with
+// stride rstride(p), locals L with stride stride(p)); every cell of those
+// tiles gets its M2L locals written.
+int m2l_offsets(int p, int64_t n_off, const double *off, float *dtab, void *stream);
+int m2l_mfma(int p, int64_t tile0, int64_t tile1, const int32_t *tile_cells,
+             const int64_t *tile_group_begin, const int32_t *group_offset,
+             const int32_t *group_src, const float *dtab, const float *Mr, float *L,
+             void *stream);
+
 // Target cells [r0, r1) from the folded multipoles Mr; acc_fp64: the row
 // accumulates in FP64 into L64, else into L (FP32 in mixed mode).
 int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,

@@ -8,8 +8,10 @@
 //  * stable sort by key (ties keep user order);
 //  * a cell at level < 21 with more than ncrit bodies gets one child per
 //    non-empty octant, in octant order; breadth-first numbering;
-//  * expansion centre = middle of the tight bounding box of the cell's bodies,
-//    radius = largest centre-to-body distance (rectangular cells).
+//  * expansion centre = middle of the tight bounding box of the cell's bodies
+//    (rectangular cells), or with box centres the centre of the cell's cube
+//    of the Morton subdivision of the root cube, (c_d - h) + (i_d + 1/2) 2h/2^L;
+//    radius = largest centre-to-body distance.
 // Compiled without FMA contraction so that keys, centres and radii are the
 // same bit for bit as any other code following these rules.
 #include <algorithm>
@@ -62,7 +64,8 @@ void radix_sort_pairs(std::vector<uint64_t> &key, std::vector<int32_t> &idx) {
 
 }  // namespace
 
-int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string &err) {
+int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string &err,
+               bool box_centres) {
   t.n = n;
   t.ncrit = ncrit;
   if (n == 0) {
@@ -212,6 +215,16 @@ int build_tree(const double *xyz, int64_t n, int ncrit, TreeData &t, std::string
   for (int64_t c = 0; c < nc; ++c) {
     double X[3];
     for (int d = 0; d < 3; ++d) X[d] = 0.5 * (blo[3 * c + d] + bhi[3 * c + d]);
+    if (box_centres && t.root_half > 0.0) {
+      const int L = t.level[c];
+      const uint64_t key = t.keys[t.body_begin[c]];
+      const double w = (2.0 * t.root_half) / (double)(1ull << L);
+      for (int d = 0; d < 3; ++d) {
+        uint64_t i = 0;  // the cell's integer coordinate: the top L bits of the body's
+        for (int b = 0; b < L; ++b) i |= ((key >> (3 * (21 - L + b) + d)) & 1ull) << b;
+        X[d] = (t.root_center[d] - t.root_half) + ((double)i + 0.5) * w;
+      }
+    }
     double rmax = 0.0;
     const double *p = &t.pos[3 * t.body_begin[c]];
     for (int64_t j = 0; j < t.n_body[c]; ++j) {

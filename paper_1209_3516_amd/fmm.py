@@ -22,6 +22,8 @@ FMM_MIXED, FMM_FP64 = 0, 1
 FMM_MAC_FIRST, FMM_LEAF_FIRST = 0, 1
 FMM_P2P, FMM_M2L, FMM_M2P = 0, 1, 2
 FMM_EVAL_TIMING, FMM_EVAL_KEEP_STAGES, FMM_EVAL_SERIAL = 1, 2, 4
+FMM_TREE_BOX_CENTRES = 1
+FMM_EVAL_M2L_MFMA = 8
 PHASES = ("gather", "p2p", "p2m", "m2m", "m2l", "l2l", "l2p", "total")
 
 _STATUS = {FMM_EINVAL: "EINVAL", FMM_ENOMEM: "ENOMEM", FMM_EDEVICE: "EDEVICE",
@@ -55,7 +57,7 @@ class _ListStats(ctypes.Structure):
                 ("p2p_max_row_sources", ctypes.c_int64), ("m2p_entries", ctypes.c_int64)]
 
 
-EXPORTS = ("fmm_tree_build", "fmm_tree_set_positions", "fmm_tree_view", "fmm_tree_free",
+EXPORTS = ("fmm_tree_build", "fmm_tree_build_ex", "fmm_tree_set_positions", "fmm_tree_view", "fmm_tree_free",
            "fmm_traverse", "fmm_lists_view", "fmm_lists_stats", "fmm_lists_free",
            "fmm_evaluate", "fmm_evaluate_backward", "fmm_direct", "fmm_last_timings",
            "fmm_last_error", "fmm_num_terms", "fmm_copy_expansions", "fmm_term_exponents",
@@ -80,6 +82,7 @@ def lib():
                               ctypes.c_double)
     sig = {
         "fmm_tree_build": ([vp, i64, i32, ctypes.POINTER(vp)], i32),
+        "fmm_tree_build_ex": ([vp, i64, i32, u32, ctypes.POINTER(vp)], i32),
         "fmm_tree_set_positions": ([vp, vp], i32),
         "fmm_tree_view": ([vp, ctypes.POINTER(_TreeView)], i32),
         "fmm_tree_free": ([vp], None),
@@ -143,14 +146,17 @@ def term_exponents(p):
 
 
 class Tree:
-    """Morton octree with at most ncrit bodies per leaf, built on the host."""
+    """Morton octree with at most ncrit bodies per leaf, built on the host.
+    box_centres=True: expansion centres at the centres of the Morton cubes."""
 
-    def __init__(self, xyz, ncrit):
+    def __init__(self, xyz, ncrit, box_centres=False):
         xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
         self.n = xyz.shape[0]
         self.ncrit = int(ncrit)
         h = ctypes.c_void_p()
-        _check(lib().fmm_tree_build(_np_ptr(xyz), self.n, self.ncrit, ctypes.byref(h)))
+        _check(lib().fmm_tree_build_ex(_np_ptr(xyz), self.n, self.ncrit,
+                                       FMM_TREE_BOX_CENTRES if box_centres else 0,
+                                       ctypes.byref(h)))
         self._h = h
 
     @classmethod
@@ -280,12 +286,14 @@ def _check_tensor(t, n, dtype, name, cols=None):
 
 
 def evaluate(tree, lists, q, p, precision="mixed", grad=True, timing=False, keep_stages=False,
-             fp64_top_levels=-1, out=None, serial=False, body_range=None):
+             fp64_top_levels=-1, out=None, serial=False, body_range=None, m2l_mfma=False):
     """One FMM evaluation.  q: CUDA tensor [n] (float32 for "mixed", float64 for
     "fp64"), user order.  Returns (phi [n], grad [n,3] or None).  serial=True
     keeps the near field on the caller's stream (no overlap with the far field).
     body_range=(b0, b1): only the targets at Morton positions [b0, b1) (leaf
-    boundaries, e.g. from partition()); other output entries are not written."""
+    boundaries, e.g. from partition()); other output entries are not written.
+    m2l_mfma=True: M2L batched by translation vector on the matrix cores
+    (trees built with box_centres=True, mixed precision)."""
     import torch
     dt = _dtype(precision)
     _check_tensor(q, tree.n, dt, "q")
@@ -295,7 +303,7 @@ def evaluate(tree, lists, q, p, precision="mixed", grad=True, timing=False, keep
     else:
         phi, g = out
     flags = ((FMM_EVAL_TIMING if timing else 0) | (FMM_EVAL_KEEP_STAGES if keep_stages else 0)
-             | (FMM_EVAL_SERIAL if serial else 0))
+             | (FMM_EVAL_SERIAL if serial else 0) | (FMM_EVAL_M2L_MFMA if m2l_mfma else 0))
     o = _opts(p, precision, flags, fp64_top_levels)
     if body_range is None:
         _check(lib().fmm_evaluate(tree._h, lists._h, ctypes.byref(o), _t_ptr(q), _t_ptr(phi),

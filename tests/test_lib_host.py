@@ -19,9 +19,9 @@ TREE_KEYS = ("perm", "keys", "level", "parent", "child_begin", "n_child", "body_
              "n_body", "center", "radius")
 
 
-def _compare(x, ncrit, theta, leaf_first=False):
-    o = O.OracleFMM(x, ncrit, theta, leaf_first=leaf_first)
-    t = fmm.Tree(x, ncrit)
+def _compare(x, ncrit, theta, leaf_first=False, box=False):
+    o = O.OracleFMM(x, ncrit, theta, leaf_first=leaf_first, box_centres=box)
+    t = fmm.Tree(x, ncrit, box_centres=box)
     lst = fmm.Lists(t, theta, leaf_first=leaf_first)
     ot, lt = o.tree(), t.view()
     assert lt["n_cells"] == o.num_cells
@@ -48,6 +48,21 @@ def _compare(x, ncrit, theta, leaf_first=False):
 def test_tree_and_lists_match_oracle(dist, n, ncrit, theta, leaf_first):
     x = W.positions(n, dist)
     _compare(x, ncrit, theta, leaf_first)
+
+
+@pytest.mark.parametrize("dist,n,ncrit,theta", [
+    ("uniform", 10_000, 64, 0.4), ("plummer", 8000, 32, 0.35), ("uniform", 3000, 1, 0.5),
+    ("uniform", 1, 4, 0.4), ("uniform", 2, 1, 0.3)])
+@pytest.mark.parametrize("leaf_first", [False, True])
+def test_box_centred_tree_and_lists_match_oracle(dist, n, ncrit, theta, leaf_first):
+    x = W.positions(n, dist)
+    _compare(x, ncrit, theta, leaf_first, box=True)
+
+
+def test_box_centred_lists_match_oracle_at_1e6():
+    c = W.CONFIGS["plummer-1e6-p6"]
+    x = W.positions(c["n"], c["dist"])
+    _compare(x, c["ncrit"], c["theta"], box=True)
 
 
 def test_lists_match_oracle_c1_workload():
