@@ -73,6 +73,12 @@ def parse():
     ap.add_argument("--share-gpus", type=int, default=8,
                     help="also time one GPU's share of the targets when they are split into "
                          "this many Morton ranges (0: skip)")
+    ap.add_argument("--box-centres", action="store_true",
+                    help="cell centres at the centres of the Morton cubes (tree and lists built "
+                         "on the host; the GPU build is not timed)")
+    ap.add_argument("--m2l-mfma", action="store_true",
+                    help="M2L batched by translation vector on the matrix cores (needs "
+                         "--box-centres)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first, as a reference "
                          "for hardware memory-traffic counters")
@@ -114,7 +120,8 @@ def main():
     phi = torch.empty(n, dtype=torch.float32, device=dev)
     grad = torch.empty(n, 3, dtype=torch.float32, device=dev)
     gpu_build = None
-    for _ in range(2):
+    mf = args.m2l_mfma
+    for _ in range(0 if args.box_centres else 2):
         tree = lists = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -127,6 +134,14 @@ def main():
         t3 = time.perf_counter()
         gpu_build = {"tree_ms": 1e3 * (t1 - t0), "lists_and_plan_ms": 1e3 * (t2 - t1),
                      "first_eval_ms": 1e3 * (t3 - t2), "total_ms": 1e3 * (t3 - t0)}
+    if args.box_centres:
+        tree = fmm.Tree(x, ncrit, box_centres=True)
+        lists = fmm.Lists(tree, theta)
+        t0 = time.perf_counter()
+        fmm.evaluate(tree, lists, qt, p, out=(phi, grad), m2l_mfma=mf)
+        torch.cuda.synchronize()
+        gpu_build = {"host_built_box_centres": True,
+                     "first_eval_ms": 1e3 * (time.perf_counter() - t0)}
     print("gpu: %s" % gpu_build, file=sys.stderr, flush=True)
 
     if args.copy_calibration_mib > 0:
@@ -137,7 +152,7 @@ def main():
         del src, dst
 
     for _ in range(args.warmup):
-        fmm.evaluate(tree, lists, qt, p, out=(phi, grad))
+        fmm.evaluate(tree, lists, qt, p, out=(phi, grad), m2l_mfma=mf)
     torch.cuda.synchronize()
 
     # Timed region: K evaluations, each with per-phase HIP events recorded on
@@ -146,7 +161,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        fmm.evaluate(tree, lists, qt, p, timing=True, out=(phi, grad))
+        fmm.evaluate(tree, lists, qt, p, timing=True, out=(phi, grad), m2l_mfma=mf)
         ms = fmm.last_timings(lists)
         for k in fmm.PHASES:
             phase_sum[k] += ms[k]
@@ -164,7 +179,7 @@ def main():
     # range evaluated alone (P2P, M2L, L2L, L2P for its cells; the upward
     # pass in full), device time per range.
     share = None
-    if args.share_gpus > 0:
+    if args.share_gpus > 0 and not mf:
         G = args.share_gpus
         bounds = fmm.partition(tree, lists, G, p=p)
         per = []
@@ -241,7 +256,9 @@ def main():
         "config": {"workload": "laplace3d-%s-N%d-p%d-theta%g-ncrit%d" % (
             cfg["dist"], n, p, theta, ncrit), "n": n, "distribution": cfg["dist"],
             "charges": cfg["charges"], "p": p, "theta": theta, "ncrit": ncrit,
-            "outputs": "potential+gradient", "precision": "fp32 P2P/M2L, Kahan P2P sums"},
+            "outputs": "potential+gradient", "precision": "fp32 P2P/M2L, Kahan P2P sums",
+            "cell_centres": "morton-cube" if args.box_centres else "bounding-box",
+            "m2l": "mfma-batched" if mf else "per-entry"},
         "roofline": {"bound": "alu", "kernel": "p2p", "achieved": achieved,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
