@@ -16,6 +16,7 @@ wrapper, and the FP64 CPU oracle timed on this host (cpu_baseline).
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -169,6 +170,7 @@ def main():
     elapsed = time.perf_counter() - t0
     print("timed %d steps in %.3fs" % (args.steps, elapsed), file=sys.stderr, flush=True)
     phase_ms = {k: v / args.steps for k, v in phase_sum.items()}
+    sclk = gpu_sclk_mhz()  # right after the timed region
     ms_per_step = 1e3 * elapsed / args.steps
     stats = lists.stats()
     pairs = stats["p2p_pairs"]
@@ -268,6 +270,7 @@ def main():
         "p2p_gpairs_per_s": pairs / p2p_s / 1e9,
         "phase_ms": phase_ms,
         "host_s": {"tree_build": t_tree, "traverse": t_trav},
+        "gpu_sclk_mhz_after_timing": sclk,
         "gpu_build": gpu_build,
         "one_gpu_share": share,
         "lists": stats,
@@ -276,6 +279,23 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def gpu_sclk_mhz():
+    """Current shader clock of GPU 0 as rocm-smi reports it (MHz), or None."""
+    import subprocess
+    try:
+        out = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
+                             text=True, timeout=20).stdout
+        d = json.loads(out[out.index("{"):])
+        for card, v in sorted(d.items()):
+            for k, val in v.items():
+                m = re.search(r"(\d+(?:\.\d+)?)\s*mhz", str(val), re.I)
+                if "sclk" in k.lower() and m:
+                    return float(m.group(1))
+    except Exception:
+        return None
+    return None
 
 
 def cpu_model():

@@ -91,6 +91,29 @@ def test_staged_expansions_match_oracle(p):
         assert np.max(np.abs(got - want) / scale) <= 1e-11, key
 
 
+@pytest.mark.parametrize("p", [4, 6, 8])
+def test_staged_expansions_match_oracle_mixed(p):
+    """The FP32 path's multipoles after the upward pass, locals after M2L and
+    after L2L, row by row against the FP64 oracle (relative to each row's
+    largest term): the staged values the mixed-precision kernels produce, not
+    only their effect on the final norms."""
+    x = W.plummer(6000, seed=12)
+    q = W.charges(6000, seed=13)
+    o = O.OracleFMM(x, 16, 0.45)
+    ref = o.evaluate(q, p, staged=True)
+    t, lst, phi, g = gpu_eval(x, q, 16, 0.45, p, "mixed", keep_stages=True)
+    ex_lib = [tuple(r) for r in fmm.term_exponents(p).tolist()]
+    ex_or = [tuple(r) for r in O.term_exponents(p).tolist()]
+    perm = [ex_lib.index(e) for e in ex_or]
+    for kind, key, worst in ((0, "M", 1e-5), (1, "L_m2l", 1e-4), (2, "L", 1e-4)):
+        got = fmm.copy_expansions(lst, kind, p)[:, perm]
+        want = ref[key]
+        scale = np.max(np.abs(want), axis=1) + 1e-300
+        err = np.max(np.abs(got - want), axis=1) / scale
+        assert np.max(err) <= worst, (key, float(np.max(err)))
+        assert np.median(err) <= 3e-6, (key, float(np.median(err)))
+
+
 def test_fp64_top_levels_p8():
     """Mixed mode with the top three levels kept in FP64 (p >= 8)."""
     x = W.uniform_cube(20_000, seed=14)
