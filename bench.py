@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--m2l-mfma", action="store_true",
                     help="M2L batched by translation vector on the matrix cores (needs "
                          "--box-centres)")
+    ap.add_argument("--mutual-p2p", action="store_true",
+                    help="mutual P2P: each unordered pair of P2P leaves evaluated once for both "
+                         "(measured slower than the one-sided kernel at the default workload)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first, as a reference "
                          "for hardware memory-traffic counters")
@@ -122,6 +125,7 @@ def main():
     grad = torch.empty(n, 3, dtype=torch.float32, device=dev)
     gpu_build = None
     mf = args.m2l_mfma
+    mu = args.mutual_p2p
     for _ in range(0 if args.box_centres else 2):
         tree = lists = None
         torch.cuda.synchronize()
@@ -153,7 +157,7 @@ def main():
         del src, dst
 
     for _ in range(args.warmup):
-        fmm.evaluate(tree, lists, qt, p, out=(phi, grad), m2l_mfma=mf)
+        fmm.evaluate(tree, lists, qt, p, out=(phi, grad), m2l_mfma=mf, mutual_p2p=mu)
     torch.cuda.synchronize()
 
     # Timed region: K evaluations, each with per-phase HIP events recorded on
@@ -162,7 +166,8 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        fmm.evaluate(tree, lists, qt, p, timing=True, out=(phi, grad), m2l_mfma=mf)
+        fmm.evaluate(tree, lists, qt, p, timing=True, out=(phi, grad), m2l_mfma=mf,
+                     mutual_p2p=mu)
         ms = fmm.last_timings(lists)
         for k in fmm.PHASES:
             phase_sum[k] += ms[k]
@@ -181,7 +186,7 @@ def main():
     # range evaluated alone (P2P, M2L, L2L, L2P for its cells; the upward
     # pass in full), device time per range.
     share = None
-    if args.share_gpus > 0 and not mf:
+    if args.share_gpus > 0 and not mf and not mu:
         G = args.share_gpus
         bounds = fmm.partition(tree, lists, G, p=p)
         per = []
@@ -260,11 +265,12 @@ def main():
             "charges": cfg["charges"], "p": p, "theta": theta, "ncrit": ncrit,
             "outputs": "potential+gradient", "precision": "fp32 P2P/M2L, Kahan P2P sums",
             "cell_centres": "morton-cube" if args.box_centres else "bounding-box",
-            "m2l": "mfma-batched" if mf else "per-entry"},
-        "roofline": {"bound": "alu", "kernel": "p2p", "achieved": achieved,
-                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "m2l": "mfma-batched" if mf else "per-entry",
+            "p2p": "mutual" if mu else "one-sided"},
+        "roofline": {"bound": "alu", "kernel": "p2p_mutual" if mu else "p2p",
+                     "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic(args.config),
+                     "traffic": None if mu else measured_traffic(args.config),
                      "work": "%d pairs x %d flop" % (pairs, FLOP_PER_PAIR),
                      "p2p_ms": phase_ms["p2p"]},
         "p2p_gpairs_per_s": pairs / p2p_s / 1e9,

@@ -75,8 +75,17 @@ enum fmm_eval_flags {
   FMM_EVAL_KEEP_STAGES = 2, /* keep a copy of the locals after M2L (fmm_copy_expansions) */
   FMM_EVAL_SERIAL = 4, /* run P2P on the caller's stream instead of overlapping it with the
                           upward pass, M2L and L2L on a second (library-owned) stream */
-  FMM_EVAL_M2L_MFMA = 8 /* M2L batched by translation vector on the matrix cores; needs a
+  FMM_EVAL_M2L_MFMA = 8, /* M2L batched by translation vector on the matrix cores; needs a
                            tree built with FMM_TREE_BOX_CENTRES and FMM_MIXED precision */
+  FMM_EVAL_MUTUAL_P2P = 16 /* mutual P2P: each unordered pair of P2P leaves is evaluated
+                              once, for the bodies of both (section 2: the mutual interaction
+                              of falcON that exaFMM inherits).  FMM_MIXED only; every leaf
+                              must hold at most 64 bodies (FMM_EINVAL otherwise, on the
+                              first evaluation, which builds its plan from the host copy of
+                              the lists).  Applies where the sources are charges alone:
+                              fmm_evaluate and the pass of fmm_evaluate_backward without v;
+                              the other passes run one-sided.  Not with
+                              fmm_evaluate_range or fmm_evaluate_noalloc (FMM_EINVAL) */
 };
 
 /* Phases reported by fmm_last_timings, in this order.  Without FMM_EVAL_SERIAL
@@ -246,6 +255,22 @@ int fmm_lists_view(const fmm_lists *l, int kind, const int64_t **row_ptr, const 
                    int64_t *nrows, int64_t *nnz);
 int fmm_lists_stats(const fmm_lists *l, fmm_lists_stats_t *s);
 void fmm_lists_free(fmm_lists *l);
+
+/*
+ * Counts of the work plan FMM_EVAL_MUTUAL_P2P evaluates these lists with
+ * (section 2: falcON's mutual interaction), built on the host and not kept:
+ *   out[0] work items, out[1] runs (one source leaf B > A each),
+ *   out[2] body pairs of the leaf pairs A < B (each evaluated once, for both
+ *          bodies), out[3] ordered body pairs i != j within one leaf
+ *          (evaluated one-sided), out[4] partial-sum slots of the sums the
+ *          bodies of each leaf B receive from its leaves A < B.
+ * For symmetric lists 2 out[2] + out[3] is fmm_lists_stats' p2p_pairs.
+ * out: caller-owned int64[5].  Lists from fmm_traverse_gpu are first copied
+ * to the host (as by fmm_lists_view).  FMM_EINVAL with a message, as the
+ * first evaluation with the flag: leaves of more than 64 bodies, lists that
+ * are not symmetric, counts that need more than 32-bit offsets.
+ */
+int fmm_mutual_plan_stats(const fmm_tree *t, const fmm_lists *l, int64_t *out);
 
 /*
  * Forward evaluation on one GPU: the evaluation phase of the method, i.e. the

@@ -105,6 +105,15 @@ struct DevLists {
   int mt_dtab_p = 0;
   int64_t mt_n_tiles = 0, mt_n_groups = 0, mt_n_off = 0;
   std::vector<int64_t> mt_level_tile;
+  // mutual P2P: its plan (built on first use) and the source-side sums
+  bool mp_ready = false;
+  fmmlib::P2PItem *mp_items = nullptr;
+  int32_t *mp_run_body = nullptr, *mp_run_prefix = nullptr, *mp_run_dst = nullptr;
+  int32_t *mp_leaf_pbase = nullptr, *mp_leaf_nchunk = nullptr, *mp_leaf_mbase = nullptr,
+          *mp_leaf_nlow = nullptr;
+  int64_t mp_n_items = 0, mp_n_partials = 0, mp_n_mslots = 0;
+  void *part_m = nullptr;
+  int64_t part_slots = 0;  // partial-sum slots part_s and part_c hold
   // near-field stream (forked from / joined into the caller's stream)
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
@@ -121,13 +130,17 @@ struct DevLists {
     p = 0;
     prec = -1;
     n_top = -1;
+    part_slots = 0;
     stage_valid = false;
   }
   void release() {
     release_scratch();
     plan.release();
-    void *ptrs[] = {m2l_ptr, m2l_col, p2p_ptr, p2p_col, m2p_ptr, m2p_col, m2p_rows,
-                    mt_cells, mt_goff, mt_gsrc, mt_gbeg, mt_off, mt_dtab};
+    void *ptrs[] = {m2l_ptr,       m2l_col,        p2p_ptr,    p2p_col,    m2p_ptr,
+                    m2p_col,       m2p_rows,       mt_cells,   mt_goff,    mt_gsrc,
+                    mt_gbeg,       mt_off,         mt_dtab,    mp_items,   mp_run_body,
+                    mp_run_prefix, mp_run_dst,     mp_leaf_pbase, mp_leaf_nchunk,
+                    mp_leaf_mbase, mp_leaf_nlow,   part_m};
     for (void *p2 : ptrs)
       if (p2) (void)hipFree(p2);
     if (have_events)
@@ -381,6 +394,45 @@ int ensure_lists_host(fmm_lists *l) {
   return FMM_OK;
 }
 
+// The mutual P2P's plan on the device (built on the host on first use from
+// the host copy of the lists) and its buffer of source-side sums.
+int ensure_mutual(fmm_tree *t, fmm_lists *l) {
+  DevLists &dv = l->dev;
+  if (dv.mp_ready) return FMM_OK;
+  if (int rc = ensure_lists_host(l)) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  fmmlib::P2PMutualPlan plan;
+  std::string err;
+  if (int rc = fmmlib::build_p2p_mutual_plan(t->data, l->data, plan, err)) {
+    set_error(err);
+    return rc;
+  }
+  if (int rc = dev_upload(&dv.mp_items, plan.items.data(), plan.items.size())) return rc;
+  if (int rc = dev_upload(&dv.mp_run_body, plan.run_body.data(), plan.run_body.size())) return rc;
+  if (int rc = dev_upload(&dv.mp_run_prefix, plan.run_prefix.data(), plan.run_prefix.size()))
+    return rc;
+  if (int rc = dev_upload(&dv.mp_run_dst, plan.run_dst.data(), plan.run_dst.size())) return rc;
+  if (int rc = dev_upload(&dv.mp_leaf_pbase, plan.leaf_pbase.data(), plan.leaf_pbase.size()))
+    return rc;
+  if (int rc = dev_upload(&dv.mp_leaf_nchunk, plan.leaf_nchunk.data(), plan.leaf_nchunk.size()))
+    return rc;
+  if (int rc = dev_upload(&dv.mp_leaf_mbase, plan.leaf_mbase.data(), plan.leaf_mbase.size()))
+    return rc;
+  if (int rc = dev_upload(&dv.mp_leaf_nlow, plan.leaf_nlow.data(), plan.leaf_nlow.size()))
+    return rc;
+  HIP_TRY(hipMalloc(&dv.part_m, (size_t)std::max<int64_t>(1, plan.n_mslots) * 16));
+  dv.mp_n_items = (int64_t)plan.items.size();
+  dv.mp_n_partials = plan.n_partials;
+  dv.mp_n_mslots = plan.n_mslots;
+  dv.mp_ready = true;
+  if (std::getenv("FMM_LOG"))
+    std::fprintf(stderr,
+                 "[fmm] mutual P2P plan: %lld items, %lld runs, %lld source slots, %.1f ms\n",
+                 (long long)dv.mp_n_items, (long long)plan.run_body.size(),
+                 (long long)plan.n_mslots, ms_since(t0));
+  return FMM_OK;
+}
+
 // The batched M2L's plan on the device (built on the host on first use from
 // the host copy of the lists) and its derivative table for order p.
 int ensure_m2l_mfma(fmm_tree *t, fmm_lists *l, int p, void *stream) {
@@ -468,7 +520,10 @@ int ensure_scratch(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o) {
   DevLists &dv = l->dev;
   const bool fp64 = o->precision == FMM_FP64;
   const int64_t n_top = top_cells(t->data, o);
-  if (dv.p == o->p && dv.prec == o->precision && dv.n_top == n_top) return FMM_OK;
+  const int64_t slots = std::max<int64_t>(
+      1, std::max<int64_t>(dv.plan.n_partials, dv.mp_ready ? dv.mp_n_partials : 0));
+  if (dv.p == o->p && dv.prec == o->precision && dv.n_top == n_top && dv.part_slots >= slots)
+    return FMM_OK;
   dv.release_scratch();
   const int64_t nc = t->data.n_cells(), n = t->data.n;
   const size_t real = fp64 ? 8 : 4;
@@ -483,9 +538,10 @@ int ensure_scratch(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o) {
     HIP_TRY(hipMalloc((void **)&dv.L64, tc * 8));
     HIP_TRY(hipMalloc((void **)&dv.L64stage, tc * 8));
   }
-  const size_t np = std::max<int64_t>(1, dv.plan.n_partials);
+  const size_t np = (size_t)slots;
   HIP_TRY(hipMalloc(&dv.part_s, np * 4 * real));
   if (!fp64) HIP_TRY(hipMalloc(&dv.part_c, np * 4 * real));
+  dv.part_slots = slots;
   HIP_TRY(hipMalloc(&dv.tmp_phi, std::max<int64_t>(1, n) * real));
   HIP_TRY(hipMalloc(&dv.tmp_grad, std::max<int64_t>(1, n) * 3 * real));
   HIP_TRY(hipMalloc(&dv.vec4, std::max<int64_t>(1, n) * 4 * real));
@@ -518,12 +574,17 @@ int check_opts(const fmm_eval_opts *o) {
     set_error("fp64_top_levels must be -2, -1 or 0..21");
     return FMM_EINVAL;
   }
-  if (o->flags & ~(FMM_EVAL_TIMING | FMM_EVAL_KEEP_STAGES | FMM_EVAL_SERIAL | FMM_EVAL_M2L_MFMA)) {
+  if (o->flags & ~(FMM_EVAL_TIMING | FMM_EVAL_KEEP_STAGES | FMM_EVAL_SERIAL | FMM_EVAL_M2L_MFMA |
+                   FMM_EVAL_MUTUAL_P2P)) {
     set_error("unknown evaluation flags");
     return FMM_EINVAL;
   }
   if ((o->flags & FMM_EVAL_M2L_MFMA) && o->precision != FMM_MIXED) {
     set_error("FMM_EVAL_M2L_MFMA runs in FP32: it needs FMM_MIXED precision");
+    return FMM_EINVAL;
+  }
+  if ((o->flags & FMM_EVAL_MUTUAL_P2P) && o->precision != FMM_MIXED) {
+    set_error("FMM_EVAL_MUTUAL_P2P runs in FP32: it needs FMM_MIXED precision");
     return FMM_EINVAL;
   }
   return FMM_OK;
@@ -624,6 +685,12 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
   // positions (equal positions share a key, hence a leaf), nor in FP32 when
   // every position is FP32-representable; otherwise test every pair.
   const bool mask_all = td.moved || (!fp64 && !td.fp32_exact);
+  // Mutual P2P: evaluations with charges alone over all targets.
+  const bool mutual = (o->flags & FMM_EVAL_MUTUAL_P2P) && mode == D::kCharges && !ranged;
+  if (mutual && (fp64 || fixed_scratch || !dv.mp_ready)) {
+    set_error("internal error: mutual P2P without its plan");
+    return FMM_EINVAL;
+  }
 
   if (int rc = mark(0, s)) return rc;
   LAUNCH_TRY(D::gather_charges(fp64, td.n, dt.perm, q, bodies, stream));
@@ -642,7 +709,11 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
     HIP_TRY(hipStreamWaitEvent(ns, dv.fork, 0));
   }
   if (int rc = mark(8, ns)) return rc;
-  if (!ranged) {
+  if (mutual) {
+    LAUNCH_TRY(D::p2p_mutual(mask_all, dv.mp_n_items, dv.mp_items, dv.mp_run_body,
+                             dv.mp_run_prefix, dv.mp_run_dst, bodies, sc.part_s, sc.part_c,
+                             dv.part_m, ns));
+  } else if (!ranged) {
     LAUNCH_TRY(D::p2p(fp64, mode, mask_all, pl.n_items, pl.items, pl.run_body, pl.run_prefix,
                       bodies, vec, sc.part_s, sc.part_c, ns));
   } else {
@@ -737,10 +808,18 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
   if (int rc = mark(5, s)) return rc;
   if (overlap) HIP_TRY(hipStreamWaitEvent(s, dv.join, 0));
   if (int rc = mark(6, s)) return rc;
-  LAUNCH_TRY(D::l2p_combine(p, fp64, mode, ranged ? rb0 : 0, ranged ? rb1 : td.n, pl.body_leaf, pl.leaf_cell, pl.leaf_pbase,
-                            pl.leaf_nchunk, dt.body_begin, dt.n_body, geo, sc.L, bodies, vec,
-                            sc.part_s, sc.part_c, dv.n_m2p_rows > 0 ? sc.m2p_buf : nullptr,
-                            dt.perm, phi, grad, stream));
+  D::MutualSlots ms;
+  if (mutual) {
+    ms.part_m = dv.part_m;
+    ms.leaf_mbase = dv.mp_leaf_mbase;
+    ms.leaf_nlow = dv.mp_leaf_nlow;
+  }
+  LAUNCH_TRY(D::l2p_combine(p, fp64, mode, ranged ? rb0 : 0, ranged ? rb1 : td.n, pl.body_leaf,
+                            pl.leaf_cell, mutual ? dv.mp_leaf_pbase : pl.leaf_pbase,
+                            mutual ? dv.mp_leaf_nchunk : pl.leaf_nchunk, dt.body_begin, dt.n_body,
+                            geo, sc.L, bodies, vec, sc.part_s, sc.part_c, ms,
+                            dv.n_m2p_rows > 0 ? sc.m2p_buf : nullptr, dt.perm, phi, grad,
+                            stream));
   if (int rc = mark(7, s)) return rc;
   dv.timed_serial = !overlap;
   dv.timing_valid = timing;
@@ -755,6 +834,8 @@ int evaluate_impl(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const void 
   const bool fp64 = o->precision == FMM_FP64;
   if (int rc = ensure_tree_device(t, fp64, stream)) return rc;
   if (int rc = ensure_lists_device(t, l)) return rc;
+  if (o->flags & FMM_EVAL_MUTUAL_P2P)
+    if (int rc = ensure_mutual(t, l)) return rc;
   if (int rc = ensure_scratch(t, l, o)) return rc;
   if (o->flags & FMM_EVAL_M2L_MFMA)
     if (int rc = ensure_m2l_mfma(t, l, o->p, stream)) return rc;
@@ -1192,6 +1273,32 @@ int fmm_lists_stats(const fmm_lists *l, fmm_lists_stats_t *s) {
   return FMM_OK;
 }
 
+int fmm_mutual_plan_stats(const fmm_tree *t, const fmm_lists *l, int64_t *out) {
+  if (int rc = check_pair(t, l)) return rc;
+  if (!out) {
+    set_error("fmm_mutual_plan_stats: out is NULL");
+    return FMM_EINVAL;
+  }
+  try {
+    if (int rc = ensure_lists_host(const_cast<fmm_lists *>(l))) return rc;
+    fmmlib::P2PMutualPlan plan;
+    std::string err;
+    if (int rc = fmmlib::build_p2p_mutual_plan(t->data, l->data, plan, err)) {
+      set_error(err);
+      return rc;
+    }
+    out[0] = (int64_t)plan.items.size();
+    out[1] = (int64_t)plan.run_body.size();
+    out[2] = plan.upper_pairs;
+    out[3] = plan.self_pairs;
+    out[4] = plan.n_mslots;
+  } catch (const std::bad_alloc &) {
+    set_error("fmm_mutual_plan_stats: out of host memory");
+    return FMM_ENOMEM;
+  }
+  return FMM_OK;
+}
+
 void fmm_lists_free(fmm_lists *l) {
   if (!l) return;
   l->dev.release();
@@ -1223,6 +1330,10 @@ int fmm_evaluate_range(const fmm_tree *t, const fmm_lists *l, const fmm_eval_opt
   if (int rc = check_opts(o)) return rc;
   if (!l->data.m2p_col.empty()) {
     set_error("fmm_evaluate_range: hybrid (M2P) lists are not supported");
+    return FMM_EINVAL;
+  }
+  if (o->flags & FMM_EVAL_MUTUAL_P2P) {
+    set_error("fmm_evaluate_range: FMM_EVAL_MUTUAL_P2P evaluates every target");
     return FMM_EINVAL;
   }
   fmm_tree *tt = const_cast<fmm_tree *>(t);

@@ -458,7 +458,7 @@ __global__ __launch_bounds__(256) void l2p_combine_kernel(
     const typename Vec<Real>::V4 *__restrict__ bodies,
     const typename Vec<Real>::V4 *__restrict__ tvec,
     const typename Vec<Real>::V4 *__restrict__ part_s,
-    const typename Vec<Real>::V4 *__restrict__ part_c,
+    const typename Vec<Real>::V4 *__restrict__ part_c, MutualSlots ms,
     const typename Vec<Real>::V4 *__restrict__ m2p_in, const int32_t *__restrict__ perm,
     Real *__restrict__ phi_out, Real *__restrict__ grad_out) {
   using V4 = typename Vec<Real>::V4;
@@ -524,6 +524,24 @@ __global__ __launch_bounds__(256) void l2p_combine_kernel(
     } else {
 #pragma unroll
       for (int k = 0; k < 4; ++k) s4[k] += vs[k];
+    }
+  }
+  if constexpr (KAHAN) {
+    if (ms.part_m) {  // mutual P2P: the sums this body received as a source
+      const float4 *pm = static_cast<const float4 *>(ms.part_m);
+      const int nl = ms.leaf_nlow[a];
+      const int64_t m0 = (int64_t)ms.leaf_mbase[a] + (i - cell_body_begin[c]);
+      for (int j = 0; j < nl; ++j) {
+        const float4 v = pm[m0 + (int64_t)j * nA];
+        const float vs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float y = vs[k] - c4[k];
+          const float t = s4[k] + y;
+          c4[k] = (t - s4[k]) - y;
+          s4[k] = t;
+        }
+      }
     }
   }
   if (m2p_in) {  // hybrid lists: the M2P part of the far field
@@ -692,23 +710,24 @@ void launch_l2p(unsigned nb, hipStream_t st, int64_t i0, int64_t i1, const int32
                 const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
                 const int32_t *cell_body_begin, const int32_t *cell_n_body, const double4 *g,
                 const void *L, const void *bodies, const void *tvec, const void *part_s,
-                const void *part_c, const void *m2p_in, const int32_t *perm, void *phi,
-                void *grad) {
+                const void *part_c, MutualSlots ms, const void *m2p_in, const int32_t *perm,
+                void *phi, void *grad) {
   using V4 = typename Vec<Real>::V4;
   constexpr bool kahan = std::is_same<Real, float>::value;
   l2p_combine_kernel<PP, Real, kahan, HESS><<<nb, 256, 0, st>>>(
       i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk, cell_body_begin, cell_n_body, g,
       (const Real *)L, (const V4 *)bodies, (const V4 *)tvec, (const V4 *)part_s,
-      (const V4 *)part_c, (const V4 *)m2p_in, perm, (Real *)phi, (Real *)grad);
+      (const V4 *)part_c, ms, (const V4 *)m2p_in, perm, (Real *)phi, (Real *)grad);
 }
 
 int l2p_combine(int p, bool fp64, int mode, int64_t i0, int64_t i1, const int32_t *body_leaf,
                 const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
                 const int32_t *cell_body_begin, const int32_t *cell_n_body, const double *geo,
                 const void *L, const void *bodies, const void *tvec, const void *part_s,
-                const void *part_c, const void *m2p_in, const int32_t *perm, void *phi,
-                void *grad, void *stream) {
+                const void *part_c, MutualSlots ms, const void *m2p_in, const int32_t *perm,
+                void *phi, void *grad, void *stream) {
   if (i1 <= i0) return 0;
+  if (fp64 && ms.part_m) return (int)hipErrorInvalidValue;  // mutual sums are FP32
   const unsigned nb = blocks_for(i1 - i0, 256);
   const double4 *g = (const double4 *)geo;
   const hipStream_t st = S_(stream);
@@ -718,19 +737,19 @@ int l2p_combine(int p, bool fp64, int mode, int64_t i0, int64_t i1, const int32_
     if (fp64 && hess)
       launch_l2p<PP, double, true>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                    cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
-                                   nullptr, m2p_in, perm, nullptr, grad);
+                                   nullptr, ms, m2p_in, perm, nullptr, grad);
     else if (fp64)
       launch_l2p<PP, double, false>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                     cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
-                                    nullptr, m2p_in, perm, phi, grad);
+                                    nullptr, ms, m2p_in, perm, phi, grad);
     else if (hess)
       launch_l2p<PP, float, true>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                   cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
-                                  part_c, m2p_in, perm, nullptr, grad);
+                                  part_c, ms, m2p_in, perm, nullptr, grad);
     else
       launch_l2p<PP, float, false>(nb, st, i0, i1, body_leaf, leaf_cell, leaf_pbase, leaf_nchunk,
                                    cell_body_begin, cell_n_body, g, L, bodies, tvec, part_s,
-                                   part_c, m2p_in, perm, phi, grad);
+                                   part_c, ms, m2p_in, perm, phi, grad);
   });
 }
 

@@ -82,6 +82,40 @@ struct P2PPlan {
 // lane holding R targets (R*L >= nt, K*L <= 64).
 void p2p_lane_layout(int nt, int *R, int *L, int *K);
 
+// Work plan of the mutual P2P kernel (charges only): every unordered pair of
+// leaves {A, B} of the symmetric P2P list is evaluated once, in the item of
+// the lower-numbered leaf A, which adds the pair's contributions to both
+// sides (the mutual interaction the paper names among the falcON techniques
+// that exaFMM inherits, section 2).  An item is leaf A (at most 64 bodies)
+// against one chunk of its sources: the self pair (A, A), evaluated one-sided
+// with a zero-distance mask, and the leaves B > A of its row, one run each.
+// Targets of A take the partial-sum slots of the one-sided plan's layout
+// (leaf_pbase + chunk * nA + k).  The sums for the bodies of B go to slots of
+// their own, leaf by leaf: body k of leaf B receives, from the j-th leaf
+// A < B of B's row, slot leaf_mbase[B] + j * nB + k; run_dst of the run of B
+// in A's item is leaf_mbase[B] + j * nB.  Item lane layout tgt_cfg = nt |
+// R << 8 | TL << 16 | K << 24: lane l holds targets l % TL + TL * r (r < R),
+// K = 64 / TL copies of each target.
+struct P2PMutualPlan {
+  std::vector<P2PItem> items;
+  std::vector<int32_t> run_body, run_prefix, run_dst;
+  std::vector<int32_t> leaf_pbase, leaf_nchunk;  // compact leaf numbering (cell order)
+  std::vector<int32_t> leaf_mbase, leaf_nlow;
+  int64_t n_partials = 0;     // target-side slots
+  int64_t n_mslots = 0;       // source-side slots
+  int64_t upper_pairs = 0;  // body pairs of the leaf pairs A < B, each evaluated once
+  int64_t self_pairs = 0;   // ordered body pairs i != j within a leaf
+};
+
+// Mutual lane layout for nt <= 64 targets: TL in {1, 2, 4, 8} target lanes per
+// ring of 16, R = ceil(nt / TL) <= 8 targets per lane.
+void p2p_mutual_layout(int nt, int *R, int *TL);
+
+// FMM_OK, or FMM_EINVAL with `err` set: a leaf of more than 64 bodies, lists
+// that are not symmetric, or counts past plan_index_limit().
+int build_p2p_mutual_plan(const TreeData &t, const ListData &l, P2PMutualPlan &plan,
+                          std::string &err);
+
 constexpr int kP2PMaxRuns = 256;
 
 // Fault injection for failure-handling tests: with FMM_FAULT_INJECT=alloc:K

@@ -34,6 +34,13 @@ int p2p(bool fp64, int mode, bool mask_all, int64_t n_items, const P2PItem *item
         const int32_t *run_body, const int32_t *run_prefix, const void *bodies, const void *vec,
         void *part_s, void *part_c, void *stream);
 
+// Mutual P2P over the items of a P2PMutualPlan (FP32 charges): target sums to
+// (part_s, part_c) at each item's out_off, source sums to part_m at the runs'
+// run_dst.  bodies: [n] float4 (x, y, z, q), Morton order.
+int p2p_mutual(bool mask_all, int64_t n_items, const P2PItem *items, const int32_t *run_body,
+               const int32_t *run_prefix, const int32_t *run_dst, const void *bodies,
+               void *part_s, void *part_c, void *part_m, void *stream);
+
 // out[i] = sign * v[perm[i]] as a 4-vector (w = 0); v is user order [n][3].
 int gather_vectors(bool fp64, int64_t n, const int32_t *perm, const void *v_user, double sign,
                    void *out, void *stream);
@@ -80,6 +87,14 @@ int l2l(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *parent, const d
 
 int copy_top_locals(int p, int64_t n_top, const double *L64, float *L, void *stream);
 
+// Source-side sums of the mutual P2P (FP32 only): body k of compact leaf a
+// adds part_m[leaf_mbase[a] + j * n_body + k], j < leaf_nlow[a] (float4).
+// part_m NULL: none.
+struct MutualSlots {
+  const void *part_m = nullptr;
+  const int32_t *leaf_mbase = nullptr, *leaf_nlow = nullptr;
+};
+
 // kHessVec: tvec holds the per-target vectors (Morton order) and grad receives
 // H v; phi is not written.
 // Bodies [i0, i1) (Morton positions).  m2p_in: [n] (phi, grad) from m2p(),
@@ -88,8 +103,8 @@ int l2p_combine(int p, bool fp64, int mode, int64_t i0, int64_t i1, const int32_
                 const int32_t *leaf_cell, const int32_t *leaf_pbase, const int32_t *leaf_nchunk,
                 const int32_t *cell_body_begin, const int32_t *cell_n_body, const double *geo,
                 const void *L, const void *bodies, const void *tvec, const void *part_s,
-                const void *part_c, const void *m2p_in, const int32_t *perm, void *phi,
-                void *grad, void *stream);
+                const void *part_c, MutualSlots ms, const void *m2p_in, const int32_t *perm,
+                void *phi, void *grad, void *stream);
 
 // M2P for the target leaves rows[0..n_rows) (each at most 64 bodies) over the
 // M2P CSR list: out[b] = (phi, grad) of body b (Morton order) from the

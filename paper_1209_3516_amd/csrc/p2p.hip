@@ -190,6 +190,55 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
   }
 }
 
+// Merge the K streams (lanes s*L + u) into the lanes of stream 0 as a tree:
+// while more than one stream is left, the upper ceil-half folds into the
+// lower part (stream s takes stream s + h), with values moved across lanes by
+// ds_bpermute.  log2(K) steps with every lane busy, no LDS buffer.  Stream 0
+// then writes target u + L r of the item to slot out_off + u + L r.
+template <typename Real, int R, bool KAHAN>
+__device__ __forceinline__ void merge_streams_and_store(Real (&S)[R][4], Real (&C)[R][4], int s,
+                                                        int K, int L, int nt, int32_t out_off,
+                                                        typename Vec<Real>::V4 *__restrict__ out_s,
+                                                        typename Vec<Real>::V4 *__restrict__ out_c) {
+  using V4 = typename Vec<Real>::V4;
+  const int lane = threadIdx.x;
+  int kc = K;
+  while (kc > 1) {
+    const int h = (kc + 1) >> 1;
+    const bool take = s < kc - h;
+    const int from = (lane + h * L) << 2;  // byte address of the partner lane
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        // Sums and compensations are added separately: a stream's value is
+        // S - C, and the log2(K) rounded additions of the tree are the only
+        // ones left uncompensated.
+        const Real vs = lane_shuffle(S[r][c], from);
+        if constexpr (KAHAN) {
+          const Real vc = lane_shuffle(C[r][c], from);
+          if (take) {
+            S[r][c] += vs;
+            C[r][c] += vc;
+          }
+        } else {
+          if (take) S[r][c] += vs;
+        }
+      }
+    kc = h;
+  }
+  if (s == 0 && lane < L) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int t = lane + L * r;
+      if (t < nt) {
+        out_s[out_off + t] = V4{S[r][0], S[r][1], S[r][2], S[r][3]};
+        if constexpr (KAHAN) out_c[out_off + t] = V4{C[r][0], C[r][1], C[r][2], C[r][3]};
+      }
+    }
+  }
+}
+
 template <typename Real, int MODE, int R, bool KAHAN, bool MASK_ALL>
 __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__restrict__ run_body,
                                          const int32_t *__restrict__ run_prefix,
@@ -274,45 +323,7 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
         bodies, vec, src, srcd, s, K, xi, yi, zi, vt, S, C);
   }
 
-  // Merge the K streams (lanes s*L + u) into the lanes of stream 0 as a tree:
-  // while more than one stream is left, the upper ceil-half folds into the
-  // lower part (stream s takes stream s + h), with values moved across lanes
-  // by ds_bpermute.  log2(K) steps with every lane busy, no LDS buffer.
-  int kc = K;
-  while (kc > 1) {
-    const int h = (kc + 1) >> 1;
-    const bool take = s < kc - h;
-    const int from = (lane + h * L) << 2;  // byte address of the partner lane
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        // Sums and compensations are added separately: a stream's value is
-        // S - C, and the log2(K) rounded additions of the tree are the only
-        // ones left uncompensated.
-        const Real vs = lane_shuffle(S[r][c], from);
-        if constexpr (KAHAN) {
-          const Real vc = lane_shuffle(C[r][c], from);
-          if (take) {
-            S[r][c] += vs;
-            C[r][c] += vc;
-          }
-        } else {
-          if (take) S[r][c] += vs;
-        }
-      }
-    kc = h;
-  }
-  if (s == 0 && lane < L) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int t = lane + L * r;
-      if (t < nt) {
-        out_s[it.out_off + t] = V4{S[r][0], S[r][1], S[r][2], S[r][3]};
-        if constexpr (KAHAN) out_c[it.out_off + t] = V4{C[r][0], C[r][1], C[r][2], C[r][3]};
-      }
-    }
-  }
+  merge_streams_and_store<Real, R, KAHAN>(S, C, s, K, L, nt, it.out_off, out_s, out_c);
 }
 
 // vec: per-body dipoles (kDipoles) or per-target vectors (kHessVec), Morton order.
@@ -367,6 +378,245 @@ void launch_p2p(bool mask_all, unsigned G, hipStream_t st, const P2PItem *items,
                                                            (V4 *)part_s, (V4 *)part_c);
 }
 
+// ----------------------------------------------------------------------------
+// Mutual P2P (charges, FP32).  One wave per item of the mutual plan: leaf A's
+// nt <= 64 targets against its self pair (one-sided with the zero-distance
+// mask, as above) and against the bodies of the leaves B > A of its row, each
+// such pair of bodies evaluated once for both of them.
+//
+// The wave is four rows of 16 lanes.  Lane l holds targets l % TL + TL r
+// (r < R), so a row holds 16 / TL copies of each target slot.  Staged sources
+// are taken in rings of 16 (row w takes rings w, w + 4, ...).  At step k < TL
+// lane u of a row evaluates its R targets against ring position (u - k) mod
+// 16: the terms go into the targets' sums and into one sum that belongs to
+// the source and travels with it, one lane up the row after every step (DPP
+// row rotation).  The source at ring position q is at lane q + k at step k,
+// so in TL steps it meets each target slot once; its finished sum (over all
+// of A's targets, plain FP32) is then stored to its slot, and the combine
+// adds it in.  The target sums are merged over rows and copies as in the
+// one-sided kernel.
+// ----------------------------------------------------------------------------
+
+// Value of v in lane (u - 1) mod 16 of the same row of 16 lanes (row_ror:1).
+__device__ __forceinline__ float row_rotate_up(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xf, 0xf, false));
+}
+
+// The terms of one source sj and R targets: the targets' partial sums p gain
+// q_j / r and q_j d / r^3 (d = x_j - x_i); (c0, c1, c2, c3) receive the
+// source's q_i / r and -q_i d / r^3, summed over the R targets.
+template <int R, bool MASK>
+__device__ __forceinline__ void mutual_terms(const float4 &sj, const float (&xi)[R],
+                                             const float (&yi)[R], const float (&zi)[R],
+                                             const float (&qi)[R], float (&p)[R][4], float &c0,
+                                             float &c1, float &c2, float &c3) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float dx = sj.x - xi[r], dy = sj.y - yi[r], dz = sj.z - zi[r];
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    float inv = rsqrt_(r2);
+    if constexpr (MASK) inv = r2 > 0.0f ? inv : 0.0f;
+    const float inv3 = inv * inv * inv;
+    p[r][0] += sj.w * inv;
+    const float tq = sj.w * inv3;
+    p[r][1] += tq * dx;
+    p[r][2] += tq * dy;
+    p[r][3] += tq * dz;
+    const float ts = qi[r] * inv3;
+    if (r == 0) {
+      c0 = qi[r] * inv;
+      c1 = -(ts * dx);
+      c2 = -(ts * dy);
+      c3 = -(ts * dz);
+    } else {
+      c0 += qi[r] * inv;
+      c1 -= ts * dx;
+      c2 -= ts * dy;
+      c3 -= ts * dz;
+    }
+  }
+}
+
+// lookup(c, body, dst): body and source slot of source position c
+// (positions only grow within a lane).
+template <int R, bool MASK, typename LookupFn>
+__device__ __forceinline__ void p2p_mutual_phase(int nsrc, LookupFn lookup,
+                                                 const float4 *__restrict__ bodies,
+                                                 float4 *__restrict__ part_m, float4 *src,
+                                                 int32_t *sdst, int TL, const float (&xi)[R],
+                                                 const float (&yi)[R], const float (&zi)[R],
+                                                 const float (&qi)[R], float (&S)[R][4],
+                                                 float (&C)[R][4]) {
+  const int lane = threadIdx.x;
+  const int u = lane & 15, row = lane >> 4;
+  const float far = Vec<float>::kFar;
+  constexpr int NL = kNB / 64;
+  // A lane meets TL sources per ring, 8 TL per batch: its plain partial is
+  // folded into (S, C) once it covers at least 64.
+  const int kb = TL >= 8 ? 1 : 8 / TL;
+  float p[R][4];
+#pragma unroll
+  for (int r = 0; r < R; ++r) p[r][0] = p[r][1] = p[r][2] = p[r][3] = 0.0f;
+  int batch = 0;
+  for (int off = 0; off < nsrc; off += kNB, ++batch) {
+    const int nb = min(kNB, nsrc - off);
+    // Staging as in p2p_phase (bodies straight into LDS), plus each
+    // position's slot; positions past the batch get far-away zero-charge
+    // bodies and no slot.
+    int bi[NL], di[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int pos = q * 64 + lane;
+      bi[q] = 0;
+      di[q] = -1;
+      if (pos < nb) lookup(off + pos, bi[q], di[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q)
+      __builtin_amdgcn_global_load_lds(static_cast<const void *>(bodies + bi[q]),
+                                       lds_ptr(src + q * 64), 16, 0, 0);
+#pragma unroll
+    for (int q = 0; q < NL; ++q) sdst[q * 64 + lane] = di[q];
+    __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of the loads are done
+    if (nb < kNB) {
+#pragma unroll
+      for (int q = 0; q < NL; ++q)
+        if (q * 64 + lane >= nb) src[q * 64 + lane] = make_float4(far, far, far, 0.0f);
+    }
+    __syncthreads();
+    const int nring = (nb + 15) >> 4;
+    for (int g = row; g < nring; g += 4) {
+      const float4 *ring = src + (g << 4);
+      float a0, a1, a2, a3;
+      mutual_terms<R, MASK>(ring[u], xi, yi, zi, qi, p, a0, a1, a2, a3);
+      for (int k = 1; k < TL; ++k) {
+        float c0, c1, c2, c3;
+        mutual_terms<R, MASK>(ring[(u - k) & 15], xi, yi, zi, qi, p, c0, c1, c2, c3);
+        a0 = row_rotate_up(a0) + c0;
+        a1 = row_rotate_up(a1) + c1;
+        a2 = row_rotate_up(a2) + c2;
+        a3 = row_rotate_up(a3) + c3;
+      }
+      // this lane now holds the sum of ring position u - TL + 1
+      const int d = sdst[(g << 4) + ((u - TL + 1) & 15)];
+      if (d >= 0) part_m[d] = make_float4(a0, a1, a2, a3);
+    }
+    if (batch % kb == kb - 1 || off + kNB >= nsrc) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float y = p[r][c] - C[r][c];
+          const float t = S[r][c] + y;
+          C[r][c] = (t - S[r][c]) - y;
+          S[r][c] = t;
+          p[r][c] = 0.0f;
+        }
+    }
+    __syncthreads();
+  }
+}
+
+template <int R, bool MASK_ALL>
+__device__ __forceinline__ void p2p_mutual_item(
+    const P2PItem &it, const int32_t *__restrict__ run_body,
+    const int32_t *__restrict__ run_prefix, const int32_t *__restrict__ run_dst,
+    const float4 *__restrict__ bodies, float4 *__restrict__ out_s, float4 *__restrict__ out_c,
+    float4 *__restrict__ part_m, float4 *src, int32_t *sdst, int32_t *rb, int32_t *rp,
+    int32_t *rd) {
+  const int lane = threadIdx.x;
+  const int nt = it.tgt_cfg & 0xff;
+  const int TL = (it.tgt_cfg >> 16) & 0xff;
+  const int K = (it.tgt_cfg >> 24) & 0xff;  // 64 / TL copies of each target
+  const int s = lane / TL;
+  const int u = lane - s * TL;
+  float xi[R], yi[R], zi[R], qi[R], vt[R][3];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int t = u + TL * r;
+    vt[r][0] = vt[r][1] = vt[r][2] = 0.0f;
+    if (t < nt) {
+      const float4 b = bodies[it.tgt_begin + t];
+      xi[r] = b.x;
+      yi[r] = b.y;
+      zi[r] = b.z;
+      qi[r] = b.w;
+    } else {
+      xi[r] = yi[r] = zi[r] = -Vec<float>::kFar;
+      qi[r] = 0.0f;
+    }
+  }
+  float S[R][4], C[R][4];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) S[r][c] = C[r][c] = 0.0f;
+
+  if (it.self_n > 0) {
+    // copy s of the targets reads every K-th of A's bodies
+    const int b0 = it.self_begin;
+    p2p_phase<float, kCharges, R, true, true>(
+        it.self_n, [&](int c) { return b0 + c; }, bodies, nullptr, src, nullptr, s, K, xi, yi,
+        zi, vt, S, C);
+  }
+  if (it.n_src > 0) {
+    for (int r = lane; r < it.n_runs; r += 64) {
+      rb[r] = run_body[it.run_begin + r];
+      rp[r] = run_prefix[it.run_begin + r];
+      rd[r] = run_dst[it.run_begin + r];
+    }
+    if (lane < 2) rp[it.n_runs + lane] = it.n_src;
+    __syncthreads();
+    int ri = 0, run_pos = rp[0], next_pos = rp[1];
+    p2p_mutual_phase<R, MASK_ALL>(
+        it.n_src,
+        [&](int c, int &body, int &dst) {
+          while (next_pos <= c) {
+            ++ri;
+            run_pos = next_pos;
+            next_pos = rp[ri + 1];
+          }
+          body = rb[ri] + (c - run_pos);
+          dst = rd[ri] + (c - run_pos);
+        },
+        bodies, part_m, src, sdst, TL, xi, yi, zi, qi, S, C);
+  }
+  merge_streams_and_store<float, R, true>(S, C, s, K, TL, nt, it.out_off, out_s, out_c);
+}
+
+template <bool MASK_ALL>
+__global__ __launch_bounds__(64) void p2p_mutual_kernel(
+    const P2PItem *__restrict__ items, const int32_t *__restrict__ run_body,
+    const int32_t *__restrict__ run_prefix, const int32_t *__restrict__ run_dst,
+    const float4 *__restrict__ bodies, float4 *__restrict__ out_s, float4 *__restrict__ out_c,
+    float4 *__restrict__ part_m) {
+  __shared__ float4 src[kNB + 64];
+  __shared__ int32_t sdst[kNB];
+  __shared__ int32_t rb[kP2PMaxRuns];
+  __shared__ int32_t rp[kP2PMaxRuns + 2];
+  __shared__ int32_t rd[kP2PMaxRuns];
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  const P2PItem it = items[w];
+  switch ((it.tgt_cfg >> 8) & 0xff) {
+#define FMM_P2PM_CASE(RR)                                                                   \
+  case RR:                                                                                  \
+    p2p_mutual_item<RR, MASK_ALL>(it, run_body, run_prefix, run_dst, bodies, out_s, out_c, \
+                                  part_m, src, sdst, rb, rp, rd);                          \
+    break;
+    FMM_P2PM_CASE(1)
+    FMM_P2PM_CASE(2)
+    FMM_P2PM_CASE(3)
+    FMM_P2PM_CASE(4)
+    FMM_P2PM_CASE(5)
+    FMM_P2PM_CASE(6)
+    FMM_P2PM_CASE(7)
+    FMM_P2PM_CASE(8)
+#undef FMM_P2PM_CASE
+    default:
+      break;
+  }
+}
+
 }  // namespace
 
 int p2p(bool fp64, int mode, bool mask_all, int64_t n_items, const P2PItem *items,
@@ -396,6 +646,24 @@ int p2p(bool fp64, int mode, bool mask_all, int64_t n_items, const P2PItem *item
       launch_p2p<float, kHessVec>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
                                   part_s, part_c);
   }
+  return (int)hipGetLastError();
+}
+
+int p2p_mutual(bool mask_all, int64_t n_items, const P2PItem *items, const int32_t *run_body,
+               const int32_t *run_prefix, const int32_t *run_dst, const void *bodies,
+               void *part_s, void *part_c, void *part_m, void *stream) {
+  if (n_items == 0) return 0;
+  const unsigned G = (unsigned)n_items;
+  const hipStream_t st = S_(stream);
+  const float4 *b = (const float4 *)bodies;
+  if (mask_all)
+    p2p_mutual_kernel<true><<<G, 64, 0, st>>>(items, run_body, run_prefix, run_dst, b,
+                                              (float4 *)part_s, (float4 *)part_c,
+                                              (float4 *)part_m);
+  else
+    p2p_mutual_kernel<false><<<G, 64, 0, st>>>(items, run_body, run_prefix, run_dst, b,
+                                               (float4 *)part_s, (float4 *)part_c,
+                                               (float4 *)part_m);
   return (int)hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ FMM_P2P, FMM_M2L, FMM_M2P = 0, 1, 2
 FMM_EVAL_TIMING, FMM_EVAL_KEEP_STAGES, FMM_EVAL_SERIAL = 1, 2, 4
 FMM_TREE_BOX_CENTRES = 1
 FMM_EVAL_M2L_MFMA = 8
+FMM_EVAL_MUTUAL_P2P = 16
 PHASES = ("gather", "p2p", "p2m", "m2m", "m2l", "l2l", "l2p", "total")
 
 _STATUS = {FMM_EINVAL: "EINVAL", FMM_ENOMEM: "ENOMEM", FMM_EDEVICE: "EDEVICE",
@@ -63,7 +64,7 @@ EXPORTS = ("fmm_tree_build", "fmm_tree_build_ex", "fmm_tree_set_positions", "fmm
            "fmm_last_error", "fmm_num_terms", "fmm_copy_expansions", "fmm_term_exponents",
            "fmm_traverse_gpu", "fmm_tree_build_gpu", "fmm_evaluate_range",
            "fmm_partition_targets", "fmm_traverse_hybrid", "fmm_evaluate_noalloc",
-           "fmm_noalloc_scratch_bytes")
+           "fmm_noalloc_scratch_bytes", "fmm_mutual_plan_stats")
 
 _lib = None
 
@@ -93,6 +94,7 @@ def lib():
         "fmm_lists_view": ([vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                             ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
         "fmm_lists_stats": ([vp, ctypes.POINTER(_ListStats)], i32),
+        "fmm_mutual_plan_stats": ([vp, vp, vp], i32),
         "fmm_lists_free": ([vp], None),
         "fmm_evaluate": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp], i32),
         "fmm_evaluate_noalloc": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp], i32),
@@ -268,6 +270,13 @@ class Lists:
         _check(lib().fmm_lists_stats(self._h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in _ListStats._fields_}
 
+    def mutual_plan_stats(self):
+        """Counts of the mutual P2P's work plan (fmm_mutual_plan_stats)."""
+        out = np.zeros(5, dtype=np.int64)
+        _check(lib().fmm_mutual_plan_stats(self.tree._h, self._h, _np_ptr(out)))
+        keys = ("items", "runs", "upper_pairs", "self_pairs", "source_slots")
+        return dict(zip(keys, (int(v) for v in out)))
+
 
 def _opts(p, precision, flags=0, fp64_top_levels=-1):
     prec = {"mixed": FMM_MIXED, "fp64": FMM_FP64}[precision]
@@ -286,14 +295,17 @@ def _check_tensor(t, n, dtype, name, cols=None):
 
 
 def evaluate(tree, lists, q, p, precision="mixed", grad=True, timing=False, keep_stages=False,
-             fp64_top_levels=-1, out=None, serial=False, body_range=None, m2l_mfma=False):
+             fp64_top_levels=-1, out=None, serial=False, body_range=None, m2l_mfma=False,
+             mutual_p2p=False):
     """One FMM evaluation.  q: CUDA tensor [n] (float32 for "mixed", float64 for
     "fp64"), user order.  Returns (phi [n], grad [n,3] or None).  serial=True
     keeps the near field on the caller's stream (no overlap with the far field).
     body_range=(b0, b1): only the targets at Morton positions [b0, b1) (leaf
     boundaries, e.g. from partition()); other output entries are not written.
     m2l_mfma=True: M2L batched by translation vector on the matrix cores
-    (trees built with box_centres=True, mixed precision)."""
+    (trees built with box_centres=True, mixed precision).  mutual_p2p=True:
+    each unordered pair of P2P leaves evaluated once for both (mixed
+    precision, leaves of at most 64 bodies, all targets)."""
     import torch
     dt = _dtype(precision)
     _check_tensor(q, tree.n, dt, "q")
@@ -303,7 +315,8 @@ def evaluate(tree, lists, q, p, precision="mixed", grad=True, timing=False, keep
     else:
         phi, g = out
     flags = ((FMM_EVAL_TIMING if timing else 0) | (FMM_EVAL_KEEP_STAGES if keep_stages else 0)
-             | (FMM_EVAL_SERIAL if serial else 0) | (FMM_EVAL_M2L_MFMA if m2l_mfma else 0))
+             | (FMM_EVAL_SERIAL if serial else 0) | (FMM_EVAL_M2L_MFMA if m2l_mfma else 0)
+             | (FMM_EVAL_MUTUAL_P2P if mutual_p2p else 0))
     o = _opts(p, precision, flags, fp64_top_levels)
     if body_range is None:
         _check(lib().fmm_evaluate(tree._h, lists._h, ctypes.byref(o), _t_ptr(q), _t_ptr(phi),
@@ -355,9 +368,10 @@ def partition(tree, lists, n_parts, weight=None, p=4):
 
 
 def evaluate_backward(tree, lists, q, grad_q, w, p, precision="mixed", need_dq=True,
-                      need_dx=True, fp64_top_levels=-1, v=None):
+                      need_dx=True, fp64_top_levels=-1, v=None, mutual_p2p=False):
     """Backward of L = sum_i w_i phi_i + sum_i v_i . grad_i (v optional):
-    returns (dL/dq [n], dL/dx [n,3])."""
+    returns (dL/dq [n], dL/dx [n,3]).  mutual_p2p=True: the pass with charges
+    alone (v None) uses the mutual P2P."""
     import torch
     dt = _dtype(precision)
     _check_tensor(w, tree.n, dt, "w")
@@ -365,7 +379,7 @@ def evaluate_backward(tree, lists, q, grad_q, w, p, precision="mixed", need_dq=T
         _check_tensor(v, tree.n, dt, "v", 3)
     dq = torch.empty(tree.n, dtype=dt, device=w.device) if need_dq else None
     dx = torch.empty(tree.n, 3, dtype=dt, device=w.device) if need_dx else None
-    o = _opts(p, precision, 0, fp64_top_levels)
+    o = _opts(p, precision, FMM_EVAL_MUTUAL_P2P if mutual_p2p else 0, fp64_top_levels)
     _check(lib().fmm_evaluate_backward(tree._h, lists._h, ctypes.byref(o), _t_ptr(q),
                                        _t_ptr(grad_q), _t_ptr(w), _t_ptr(v), _t_ptr(dq),
                                        _t_ptr(dx), _stream()))
