@@ -109,6 +109,81 @@ __global__ __launch_bounds__(64) void p2m_kernel(int64_t n_leaves, const int32_t
 }
 
 // ----------------------------------------------------------------------------
+// P2M for low orders (at most 20 terms, p <= 4): eight lanes per leaf,
+// thirty-two leaves per 256-thread block, no LDS.  Lane j of a leaf adds the
+// term rows of bodies j, j + 8, j + 16, ... in registers (four bodies' loads
+// in flight at a time), then the eight lane sums are added by an xor-shuffle
+// tree, the same on every lane of the leaf, and lane j stores the terms
+// t = j mod 8.
+// ----------------------------------------------------------------------------
+constexpr int kP2MRegLanes = 8;
+
+template <int P, typename Real, bool DIP>
+__global__ __launch_bounds__(256) void p2m_reg_kernel(
+    int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
+    const int32_t *__restrict__ body_begin, const int32_t *__restrict__ n_body,
+    const double4 *__restrict__ geo, const typename Vec<Real>::V4 *__restrict__ bodies,
+    const typename Vec<Real>::V4 *__restrict__ dip, Real *__restrict__ M,
+    double *__restrict__ M64, int64_t n_top) {
+  using V4 = typename Vec<Real>::V4;
+  constexpr int T = nterms(P), S = pad4(T), LPL = kP2MRegLanes, U = 4;
+  static_assert(T <= 20, "register P2M is for p <= 4");
+  const int j = threadIdx.x % LPL;
+  const int64_t li = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPL;
+  const bool active = li < n_leaves;
+  const int c = active ? leaf_cell[li] : 0;
+  const int b0 = active ? body_begin[c] : 0, nb = active ? n_body[c] : 0;
+  const double4 g = geo[c];
+  Real acc[T];
+  static_for<T>([&](auto I) { acc[decltype(I)::value] = Real(0); });
+  for (int i0 = 0; i0 < nb; i0 += U * LPL) {
+    V4 bv[U], dv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + j + LPL * u;
+      if (i < nb) {
+        bv[u] = bodies[b0 + i];
+        if constexpr (DIP) dv[u] = dip[b0 + i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + j + LPL * u < nb) {
+        const V4 b = bv[u];
+        Real mono[T];
+        monomials<P, Real>(Real(g.x - (double)b.x), Real(g.y - (double)b.y),
+                           Real(g.z - (double)b.z), mono);
+        static_for<T>([&](auto I) {
+          constexpr int t = decltype(I)::value;
+          Real w = b.w * mono[t];
+          if constexpr (DIP) {
+            if constexpr (kBasis<P>.lo[t][0] >= 0) w += dv[u].x * mono[kBasis<P>.lo[t][0]];
+            if constexpr (kBasis<P>.lo[t][1] >= 0) w += dv[u].y * mono[kBasis<P>.lo[t][1]];
+            if constexpr (kBasis<P>.lo[t][2] >= 0) w += dv[u].z * mono[kBasis<P>.lo[t][2]];
+          }
+          acc[t] += w;
+        });
+      }
+    }
+  }
+  // a + b on one lane, b + a on its partner: every lane ends with the same sums
+#pragma unroll
+  for (int off = LPL / 2; off >= 1; off >>= 1)
+    static_for<T>([&](auto I) {
+      constexpr int t = decltype(I)::value;
+      acc[t] += __shfl_xor(acc[t], off);
+    });
+  if (!active) return;
+  static_for<T>([&](auto I) {
+    constexpr int t = decltype(I)::value;
+    if (t % LPL == j) {
+      M[(int64_t)c * S + t] = acc[t];
+      if (c < n_top) M64[(int64_t)c * S + t] = (double)acc[t];
+    }
+  });
+}
+
+// ----------------------------------------------------------------------------
 // M2M: one thread per parent cell of one level; the parent gathers from its
 // contiguous children (no atomics).
 // ----------------------------------------------------------------------------
@@ -573,6 +648,23 @@ int p2m(int p, bool fp64, int64_t n_leaves, const int32_t *leaf_cell, const int3
   const bool small = n_bodies <= 16 * n_leaves;
   return with_p(p, [&](auto PC) {
     constexpr int PP = decltype(PC)::value;
+    if constexpr (nterms(PP) <= 20) {
+      const unsigned nbk = blocks_for(n_leaves, 256 / kP2MRegLanes);
+      auto reg = [&](auto *b, auto *d, auto *m, int64_t top) {
+        using R = std::remove_cv_t<std::remove_pointer_t<decltype(m)>>;
+        if (dipoles)
+          p2m_reg_kernel<PP, R, true><<<nbk, 256, 0, S_(stream)>>>(
+              n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, m, M64, top);
+        else
+          p2m_reg_kernel<PP, R, false><<<nbk, 256, 0, S_(stream)>>>(
+              n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, m, M64, top);
+      };
+      if (fp64)
+        reg((const double4 *)bodies, (const double4 *)dipoles, (double *)M, int64_t(0));
+      else
+        reg((const float4 *)bodies, (const float4 *)dipoles, (float *)M, n_top);
+      return;
+    }
     auto go = [&](auto LC, auto *b, auto *d, auto *m, int64_t top) {
       constexpr int LPL = decltype(LC)::value;
       using R = std::remove_cv_t<std::remove_pointer_t<decltype(m)>>;
