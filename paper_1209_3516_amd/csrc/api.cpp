@@ -133,14 +133,25 @@ struct DevLists {
     part_slots = 0;
     stage_valid = false;
   }
+  // the mutual P2P's plan and source-side sums
+  void release_mutual() {
+    void *ptrs[] = {mp_items,      mp_run_body,    mp_run_prefix, mp_run_dst, mp_leaf_pbase,
+                    mp_leaf_nchunk, mp_leaf_mbase, mp_leaf_nlow,  part_m};
+    for (void *p2 : ptrs)
+      if (p2) (void)hipFree(p2);
+    mp_items = nullptr;
+    mp_run_body = mp_run_prefix = mp_run_dst = nullptr;
+    mp_leaf_pbase = mp_leaf_nchunk = mp_leaf_mbase = mp_leaf_nlow = nullptr;
+    part_m = nullptr;
+    mp_n_items = mp_n_partials = mp_n_mslots = 0;
+    mp_ready = false;
+  }
   void release() {
     release_scratch();
+    release_mutual();
     plan.release();
-    void *ptrs[] = {m2l_ptr,       m2l_col,        p2p_ptr,    p2p_col,    m2p_ptr,
-                    m2p_col,       m2p_rows,       mt_cells,   mt_goff,    mt_gsrc,
-                    mt_gbeg,       mt_off,         mt_dtab,    mp_items,   mp_run_body,
-                    mp_run_prefix, mp_run_dst,     mp_leaf_pbase, mp_leaf_nchunk,
-                    mp_leaf_mbase, mp_leaf_nlow,   part_m};
+    void *ptrs[] = {m2l_ptr, m2l_col, p2p_ptr, p2p_col, m2p_ptr, m2p_col, m2p_rows,
+                    mt_cells, mt_goff, mt_gsrc, mt_gbeg, mt_off, mt_dtab};
     for (void *p2 : ptrs)
       if (p2) (void)hipFree(p2);
     if (have_events)
@@ -407,20 +418,24 @@ int ensure_mutual(fmm_tree *t, fmm_lists *l) {
     set_error(err);
     return rc;
   }
-  if (int rc = dev_upload(&dv.mp_items, plan.items.data(), plan.items.size())) return rc;
-  if (int rc = dev_upload(&dv.mp_run_body, plan.run_body.data(), plan.run_body.size())) return rc;
-  if (int rc = dev_upload(&dv.mp_run_prefix, plan.run_prefix.data(), plan.run_prefix.size()))
+  // on a failure nothing is kept, so a later call starts afresh
+  int rc = dev_upload(&dv.mp_items, plan.items.data(), plan.items.size());
+  if (!rc) rc = dev_upload(&dv.mp_run_body, plan.run_body.data(), plan.run_body.size());
+  if (!rc) rc = dev_upload(&dv.mp_run_prefix, plan.run_prefix.data(), plan.run_prefix.size());
+  if (!rc) rc = dev_upload(&dv.mp_run_dst, plan.run_dst.data(), plan.run_dst.size());
+  if (!rc) rc = dev_upload(&dv.mp_leaf_pbase, plan.leaf_pbase.data(), plan.leaf_pbase.size());
+  if (!rc) rc = dev_upload(&dv.mp_leaf_nchunk, plan.leaf_nchunk.data(), plan.leaf_nchunk.size());
+  if (!rc) rc = dev_upload(&dv.mp_leaf_mbase, plan.leaf_mbase.data(), plan.leaf_mbase.size());
+  if (!rc) rc = dev_upload(&dv.mp_leaf_nlow, plan.leaf_nlow.data(), plan.leaf_nlow.size());
+  if (!rc) {
+    const hipError_t e =
+        hipMalloc(&dv.part_m, (size_t)std::max<int64_t>(1, plan.n_mslots) * 16);
+    if (e != hipSuccess) rc = hip_fail(e, "hipMalloc");
+  }
+  if (rc) {
+    dv.release_mutual();
     return rc;
-  if (int rc = dev_upload(&dv.mp_run_dst, plan.run_dst.data(), plan.run_dst.size())) return rc;
-  if (int rc = dev_upload(&dv.mp_leaf_pbase, plan.leaf_pbase.data(), plan.leaf_pbase.size()))
-    return rc;
-  if (int rc = dev_upload(&dv.mp_leaf_nchunk, plan.leaf_nchunk.data(), plan.leaf_nchunk.size()))
-    return rc;
-  if (int rc = dev_upload(&dv.mp_leaf_mbase, plan.leaf_mbase.data(), plan.leaf_mbase.size()))
-    return rc;
-  if (int rc = dev_upload(&dv.mp_leaf_nlow, plan.leaf_nlow.data(), plan.leaf_nlow.size()))
-    return rc;
-  HIP_TRY(hipMalloc(&dv.part_m, (size_t)std::max<int64_t>(1, plan.n_mslots) * 16));
+  }
   dv.mp_n_items = (int64_t)plan.items.size();
   dv.mp_n_partials = plan.n_partials;
   dv.mp_n_mslots = plan.n_mslots;
@@ -450,13 +465,21 @@ int ensure_m2l_mfma(fmm_tree *t, fmm_lists *l, int p, void *stream) {
       set_error(err);
       return rc;
     }
-    if (int rc = dev_upload(&dv.mt_cells, plan.tile_cells.data(), plan.tile_cells.size())) return rc;
-    if (int rc = dev_upload(&dv.mt_gbeg, plan.tile_group_begin.data(), plan.tile_group_begin.size()))
+    // on a failure nothing is kept, so a later call starts afresh
+    int rc = dev_upload(&dv.mt_cells, plan.tile_cells.data(), plan.tile_cells.size());
+    if (!rc) rc = dev_upload(&dv.mt_gbeg, plan.tile_group_begin.data(), plan.tile_group_begin.size());
+    if (!rc) rc = dev_upload(&dv.mt_goff, plan.group_offset.data(), plan.group_offset.size());
+    if (!rc) rc = dev_upload(&dv.mt_gsrc, plan.group_src.data(), plan.group_src.size());
+    if (!rc) rc = dev_upload(&dv.mt_off, plan.offsets.data(), plan.offsets.size());
+    if (rc) {
+      void *ps[] = {dv.mt_cells, dv.mt_gbeg, dv.mt_goff, dv.mt_gsrc, dv.mt_off};
+      for (void *q : ps)
+        if (q) (void)hipFree(q);
+      dv.mt_cells = dv.mt_goff = dv.mt_gsrc = nullptr;
+      dv.mt_gbeg = nullptr;
+      dv.mt_off = nullptr;
       return rc;
-    if (int rc = dev_upload(&dv.mt_goff, plan.group_offset.data(), plan.group_offset.size()))
-      return rc;
-    if (int rc = dev_upload(&dv.mt_gsrc, plan.group_src.data(), plan.group_src.size())) return rc;
-    if (int rc = dev_upload(&dv.mt_off, plan.offsets.data(), plan.offsets.size())) return rc;
+    }
     dv.mt_n_tiles = plan.n_tiles;
     dv.mt_n_groups = plan.n_groups;
     dv.mt_n_off = plan.n_offsets;
