@@ -288,19 +288,25 @@ def main():
 
 
 def gpu_sclk_mhz():
-    """Current shader clock of GPU 0 as rocm-smi reports it (MHz), or None."""
-    import subprocess
-    try:
-        out = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
-                             text=True, timeout=20).stdout
-        d = json.loads(out[out.index("{"):])
-        for card, v in sorted(d.items()):
-            for k, val in v.items():
-                m = re.search(r"(\d+(?:\.\d+)?)\s*mhz", str(val), re.I)
-                if "sclk" in k.lower() and m:
-                    return float(m.group(1))
-    except Exception:
-        return None
+    """Current shader clock of the GPU (MHz) from the amdgpu driver's sysfs
+    files (the hwmon sclk input, else the level marked current in
+    pp_dpm_sclk), or None.  Read directly: no helper program is started from
+    this process once it has used the GPU."""
+    import glob
+    for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+        try:
+            for lab in sorted(glob.glob(dev + "/hwmon/hwmon*/freq*_label")):
+                with open(lab) as f:
+                    if f.read().strip().lower() == "sclk":
+                        with open(lab.replace("_label", "_input")) as g:
+                            return int(g.read().strip()) / 1e6
+            with open(dev + "/pp_dpm_sclk") as f:
+                for line in f:
+                    m = re.search(r"(\d+(?:\.\d+)?)\s*mhz\s*\*", line, re.I)
+                    if m:
+                        return float(m.group(1))
+        except (OSError, ValueError):
+            continue
     return None
 
 

@@ -109,8 +109,9 @@ __global__ __launch_bounds__(64) void p2m_kernel(int64_t n_leaves, const int32_t
 }
 
 // ----------------------------------------------------------------------------
-// P2M for low orders (at most 20 terms, p <= 4): eight lanes per leaf,
-// thirty-two leaves per 256-thread block, no LDS.  Lane j of a leaf adds the
+// P2M for low orders (at most 20 terms, p <= 4): eight lanes per leaf, eight
+// leaves per one-wave block (one-wave blocks find room beside the P2P
+// kernel's waves when the two streams overlap), no LDS.  Lane j of a leaf adds the
 // term rows of bodies j, j + 8, j + 16, ... in registers (four bodies' loads
 // in flight at a time), then the eight lane sums are added by an xor-shuffle
 // tree, the same on every lane of the leaf, and lane j stores the terms
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(64) void p2m_kernel(int64_t n_leaves, const int32_t
 constexpr int kP2MRegLanes = 8;
 
 template <int P, typename Real, bool DIP>
-__global__ __launch_bounds__(256) void p2m_reg_kernel(
+__global__ __launch_bounds__(64) void p2m_reg_kernel(
     int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
     const int32_t *__restrict__ body_begin, const int32_t *__restrict__ n_body,
     const double4 *__restrict__ geo, const typename Vec<Real>::V4 *__restrict__ bodies,
@@ -649,14 +650,14 @@ int p2m(int p, bool fp64, int64_t n_leaves, const int32_t *leaf_cell, const int3
   return with_p(p, [&](auto PC) {
     constexpr int PP = decltype(PC)::value;
     if constexpr (nterms(PP) <= 20) {
-      const unsigned nbk = blocks_for(n_leaves, 256 / kP2MRegLanes);
+      const unsigned nbk = blocks_for(n_leaves, 64 / kP2MRegLanes);
       auto reg = [&](auto *b, auto *d, auto *m, int64_t top) {
         using R = std::remove_cv_t<std::remove_pointer_t<decltype(m)>>;
         if (dipoles)
-          p2m_reg_kernel<PP, R, true><<<nbk, 256, 0, S_(stream)>>>(
+          p2m_reg_kernel<PP, R, true><<<nbk, 64, 0, S_(stream)>>>(
               n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, m, M64, top);
         else
-          p2m_reg_kernel<PP, R, false><<<nbk, 256, 0, S_(stream)>>>(
+          p2m_reg_kernel<PP, R, false><<<nbk, 64, 0, S_(stream)>>>(
               n_leaves, leaf_cell, cell_body_begin, cell_n_body, g, b, d, m, M64, top);
       };
       if (fp64)
