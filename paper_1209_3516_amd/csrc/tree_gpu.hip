@@ -202,6 +202,26 @@ struct Pinned {
   }
 };
 
+// A growable pinned host block that device-to-host copies land in
+// asynchronously (a copy to pageable memory is staged and waited for one at
+// a time); kept with the build's scratch, so later builds reuse it.
+struct PinnedStage {
+  void *p = nullptr;
+  size_t bytes = 0;
+  hipError_t reserve(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    const hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e == hipSuccess) bytes = want;
+    return e;
+  }
+  ~PinnedStage() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
 #define TRY(x)                             \
   do {                                     \
     hipError_t e_ = (x);                   \
@@ -719,6 +739,7 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
     Buf boxes, key, idx, key2, idx2, temp, bb, nbd, lv, par, cb, nc, nch, off, gcnt, goff, gtab,
         gacc, part;
     Pinned host;  // scan totals, written there by the scans
+    PinnedStage stage;  // the host copy of the cell arrays passes through here
     size_t bytes() const {
       const Buf *all[] = {&boxes, &key, &idx, &key2, &idx2, &temp, &bb, &nbd, &lv,
                           &par, &cb, &nc, &nch, &off, &gcnt, &goff, &gtab, &gacc, &part};
@@ -910,7 +931,8 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
   TRY(hipMemcpyAsync(out.parent, par.p, ncells * 4, hipMemcpyDeviceToDevice, st));
   TRY(hipMalloc((void **)&out.keys, n * 8));
   TRY(hipMemcpyAsync(out.keys, skeys, n * 8, hipMemcpyDeviceToDevice, st));
-  // host copy of the cell arrays (the per-body arrays stay on the device)
+  // host copy of the cell arrays (the per-body arrays stay on the device):
+  // seven asynchronous copies into the pinned block, one wait
   t.level.resize(ncells);
   t.parent.resize(ncells);
   t.child_begin.resize(ncells);
@@ -919,19 +941,31 @@ int build_tree_gpu(const double *xyz, int64_t n, int ncrit, void *stream, Device
   t.n_body.resize(ncells);
   t.center.resize(3 * ncells);
   t.radius.resize(ncells);
-  std::vector<double> geo(4 * ncells);
-  TRY(hipMemcpyAsync(t.level.data(), lv.p, ncells * 4, hipMemcpyDeviceToHost, st));
-  TRY(hipMemcpyAsync(t.parent.data(), par.p, ncells * 4, hipMemcpyDeviceToHost, st));
-  TRY(hipMemcpyAsync(t.child_begin.data(), cb.p, ncells * 4, hipMemcpyDeviceToHost, st));
-  TRY(hipMemcpyAsync(t.n_child.data(), nc.p, ncells * 4, hipMemcpyDeviceToHost, st));
-  TRY(hipMemcpyAsync(t.body_begin.data(), bb.p, ncells * 8, hipMemcpyDeviceToHost, st));
-  TRY(hipMemcpyAsync(t.n_body.data(), nbd.p, ncells * 8, hipMemcpyDeviceToHost, st));
-  TRY(hipMemcpyAsync(geo.data(), out.geo, ncells * 32, hipMemcpyDeviceToHost, st));
+  const size_t nc_ = (size_t)ncells;
+  TRY(sc->stage.reserve(nc_ * (4 * 4 + 2 * 8 + 32)));
+  char *hs = static_cast<char *>(sc->stage.p);
+  int32_t *h_lv = reinterpret_cast<int32_t *>(hs), *h_par = h_lv + nc_, *h_cb = h_par + nc_,
+          *h_nc = h_cb + nc_;
+  int64_t *h_bb = reinterpret_cast<int64_t *>(hs + 16 * nc_), *h_nbd = h_bb + nc_;
+  double *h_geo = reinterpret_cast<double *>(hs + 32 * nc_);
+  TRY(hipMemcpyAsync(h_lv, lv.p, nc_ * 4, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(h_par, par.p, nc_ * 4, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(h_cb, cb.p, nc_ * 4, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(h_nc, nc.p, nc_ * 4, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(h_bb, bb.p, nc_ * 8, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(h_nbd, nbd.p, nc_ * 8, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(h_geo, out.geo, nc_ * 32, hipMemcpyDeviceToHost, st));
   TRY(hipStreamSynchronize(st));
+  std::copy(h_lv, h_lv + nc_, t.level.begin());
+  std::copy(h_par, h_par + nc_, t.parent.begin());
+  std::copy(h_cb, h_cb + nc_, t.child_begin.begin());
+  std::copy(h_nc, h_nc + nc_, t.n_child.begin());
+  std::copy(h_bb, h_bb + nc_, t.body_begin.begin());
+  std::copy(h_nbd, h_nbd + nc_, t.n_body.begin());
   t.n_leaves = 0;
   for (int64_t c = 0; c < ncells; ++c) {
-    for (int d = 0; d < 3; ++d) t.center[3 * c + d] = geo[4 * c + d];
-    t.radius[c] = geo[4 * c + 3];
+    for (int d = 0; d < 3; ++d) t.center[3 * c + d] = h_geo[4 * c + d];
+    t.radius[c] = h_geo[4 * c + 3];
     t.n_leaves += t.n_child[c] == 0;
   }
   out.n = n;
