@@ -708,6 +708,11 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
   // positions (equal positions share a key, hence a leaf), nor in FP32 when
   // every position is FP32-representable; otherwise test every pair.
   const bool mask_all = td.moved || (!fp64 && !td.fp32_exact);
+  // The FP32 P2P kernel at four waves per SIMD, except for p = 5 and 6: their
+  // M2L waves (about 148 registers) start beside P2P only where a finished
+  // P2P wave of the three-wave kernel (168) makes room; at p <= 4 M2L is
+  // small enough either way, and at p >= 7 it never fits beside P2P.
+  const bool p2p_four_waves = o->p <= 4 || o->p >= 7;
   // Mutual P2P: evaluations with charges alone over all targets.
   const bool mutual = (o->flags & FMM_EVAL_MUTUAL_P2P) && mode == D::kCharges && !ranged;
   if (mutual && (fp64 || fixed_scratch || !dv.mp_ready)) {
@@ -737,16 +742,16 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
                              dv.mp_run_prefix, dv.mp_run_dst, bodies, sc.part_s, sc.part_c,
                              dv.part_m, ns));
   } else if (!ranged) {
-    LAUNCH_TRY(D::p2p(fp64, mode, mask_all, pl.n_items, pl.items, pl.run_body, pl.run_prefix,
-                      bodies, vec, sc.part_s, sc.part_c, ns));
+    LAUNCH_TRY(D::p2p(fp64, mode, mask_all, p2p_four_waves, pl.n_items, pl.items, pl.run_body,
+                      pl.run_prefix, bodies, vec, sc.part_s, sc.part_c, ns));
   } else {
     // the items of the range's leaves: one contiguous run per level
     for (int lev = 0; lev <= max_level; ++lev) {
       const int64_t i0 = dv.leaf_item_host[rcells.leaf_lo[lev]];
       const int64_t i1 = dv.leaf_item_host[rcells.leaf_hi[lev]];
       if (i1 > i0)
-        LAUNCH_TRY(D::p2p(fp64, mode, mask_all, i1 - i0, pl.items + i0, pl.run_body,
-                          pl.run_prefix, bodies, vec, sc.part_s, sc.part_c, ns));
+        LAUNCH_TRY(D::p2p(fp64, mode, mask_all, p2p_four_waves, i1 - i0, pl.items + i0,
+                          pl.run_body, pl.run_prefix, bodies, vec, sc.part_s, sc.part_c, ns));
     }
   }
   if (int rc = mark(9, ns)) return rc;

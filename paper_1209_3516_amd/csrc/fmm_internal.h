@@ -79,7 +79,10 @@ struct P2PPlan {
 };
 
 // Lane layout of a P2P work item with nt targets: K streams of L lanes, each
-// lane holding R targets (R*L >= nt, K*L <= 64).
+// lane holding R <= kP2PMaxTargetsPerLane targets (R*L >= nt, K*L <= 64).
+// At most six targets per lane keep the FP32 kernel within 128 registers,
+// i.e. four waves per SIMD.
+constexpr int kP2PMaxTargetsPerLane = 6;
 void p2p_lane_layout(int nt, int *R, int *L, int *K);
 
 // Work plan of the mutual P2P kernel (charges only): every unordered pair of

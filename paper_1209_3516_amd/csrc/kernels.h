@@ -30,9 +30,12 @@ enum EvalMode { kCharges = 0, kDipoles = 1, kHessVec = 2 };
 
 // vec: [n] float4/double4 per-body dipoles (kDipoles) or per-target vectors
 // (kHessVec), Morton order; unused for kCharges.
-int p2p(bool fp64, int mode, bool mask_all, int64_t n_items, const P2PItem *items,
-        const int32_t *run_body, const int32_t *run_prefix, const void *bodies, const void *vec,
-        void *part_s, void *part_c, void *stream);
+// four_waves: in FP32 charges mode, the kernel held to four waves per SIMD
+// (else the general one, three waves); the caller picks it by whether the
+// far field's M2L waves, running beside P2P, fit in what its waves leave.
+int p2p(bool fp64, int mode, bool mask_all, bool four_waves, int64_t n_items,
+        const P2PItem *items, const int32_t *run_body, const int32_t *run_prefix,
+        const void *bodies, const void *vec, void *part_s, void *part_c, void *stream);
 
 // Mutual P2P over the items of a P2PMutualPlan (FP32 charges): target sums to
 // (part_s, part_c) at each item's out_off, source sums to part_m at the runs'

@@ -26,7 +26,10 @@ namespace {
 // The per-target result is always a 4-vector, so the partial-sum layout and
 // the merge are shared.
 // ----------------------------------------------------------------------------
-constexpr int kNB = 512;
+// Sources staged per batch.  With 384 the LDS of one wave (staged sources
+// and run table, about 9 KB) lets a CU hold the sixteen waves (four per
+// SIMD) that the FP32 charges kernel's registers allow.
+constexpr int kNB = 384;
 
 // An LDS pointer in the LDS address space, as global_load_lds takes it.
 template <typename T>
@@ -59,9 +62,9 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
   const int lane = threadIdx.x;
   const Real far = Vec<Real>::kFar;
   // The plain partial of a stream is added into (S, C) every `kb` batches, so
-  // that it covers at least 64 sources when a stream's share of one batch is
-  // smaller (kb = ceil(K / 8)).
-  const int kb = (K + 7) >> 3;
+  // that it covers at least 64 sources when a stream's share of one batch
+  // (kNB / K) is smaller: kb = ceil(64 K / kNB).
+  const int kb = (64 * K + kNB - 1) / kNB;
   Real p[R][4];
 #pragma unroll
   for (int r = 0; r < R; ++r) p[r][0] = p[r][1] = p[r][2] = p[r][3] = Real(0);
@@ -326,15 +329,16 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
   merge_streams_and_store<Real, R, KAHAN>(S, C, s, K, L, nt, it.out_off, out_s, out_c);
 }
 
+// One work item per wave, dispatched on its lane layout's R.
 // vec: per-body dipoles (kDipoles) or per-target vectors (kHessVec), Morton order.
-template <typename Real, int MODE, bool KAHAN, bool MASK_ALL>
-__global__ __launch_bounds__(64) void p2p_kernel(const P2PItem *__restrict__ items,
-                                                 const int32_t *__restrict__ run_body,
-                                                 const int32_t *__restrict__ run_prefix,
-                                                 const typename Vec<Real>::V4 *__restrict__ bodies,
-                                                 const typename Vec<Real>::V4 *__restrict__ vec,
-                                                 typename Vec<Real>::V4 *__restrict__ out_s,
-                                                 typename Vec<Real>::V4 *__restrict__ out_c) {
+template <typename Real, int MODE, bool KAHAN, bool MASK_ALL, int MAXR>
+__device__ __forceinline__ void p2p_wave(const P2PItem *__restrict__ items,
+                                         const int32_t *__restrict__ run_body,
+                                         const int32_t *__restrict__ run_prefix,
+                                         const typename Vec<Real>::V4 *__restrict__ bodies,
+                                         const typename Vec<Real>::V4 *__restrict__ vec,
+                                         typename Vec<Real>::V4 *__restrict__ out_s,
+                                         typename Vec<Real>::V4 *__restrict__ out_c) {
   using V4 = typename Vec<Real>::V4;
   __shared__ V4 src[kNB + 64];
   __shared__ V4 srcd[MODE == kDipoles ? kNB + 64 : 1];
@@ -342,11 +346,13 @@ __global__ __launch_bounds__(64) void p2p_kernel(const P2PItem *__restrict__ ite
   __shared__ int32_t rp[kP2PMaxRuns + 2];
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
   const P2PItem it = items[w];
+  static_assert(kP2PMaxTargetsPerLane <= MAXR && MAXR <= 8, "a case for every R of the plan");
   switch ((it.tgt_cfg >> 8) & 0xff) {
-#define FMM_P2P_CASE(RR)                                                                  \
-  case RR:                                                                                \
-    p2p_item<Real, MODE, RR, KAHAN, MASK_ALL>(it, run_body, run_prefix, bodies, vec, out_s, \
-                                              out_c, src, srcd, rb, rp);                   \
+#define FMM_P2P_CASE(RR)                                                                    \
+  case RR:                                                                                  \
+    if constexpr (RR <= MAXR)                                                               \
+      p2p_item<Real, MODE, RR, KAHAN, MASK_ALL>(it, run_body, run_prefix, bodies, vec, out_s, \
+                                                out_c, src, srcd, rb, rp);                   \
     break;
     FMM_P2P_CASE(1)
     FMM_P2P_CASE(2)
@@ -362,14 +368,56 @@ __global__ __launch_bounds__(64) void p2p_kernel(const P2PItem *__restrict__ ite
   }
 }
 
+// The general kernel: every mode and precision.  Its code has a case for R
+// up to 8 (the plan uses at most kP2PMaxTargetsPerLane), which in FP32
+// charges mode gives about 168 registers, i.e. three waves per SIMD.
+template <typename Real, int MODE, bool KAHAN, bool MASK_ALL>
+__global__ __launch_bounds__(64) void p2p_kernel(const P2PItem *__restrict__ items,
+                                                 const int32_t *__restrict__ run_body,
+                                                 const int32_t *__restrict__ run_prefix,
+                                                 const typename Vec<Real>::V4 *__restrict__ bodies,
+                                                 const typename Vec<Real>::V4 *__restrict__ vec,
+                                                 typename Vec<Real>::V4 *__restrict__ out_s,
+                                                 typename Vec<Real>::V4 *__restrict__ out_c) {
+  p2p_wave<Real, MODE, KAHAN, MASK_ALL, 8>(items, run_body, run_prefix, bodies, vec, out_s,
+                                           out_c);
+}
+
+// The FP32 charges kernel held to four waves per SIMD (at most 128
+// registers per lane, cases R <= kP2PMaxTargetsPerLane only): with more
+// waves in flight each batch's staging latency is better hidden (leaves of
+// about ten bodies, whose sources are staged most often per pair, gain
+// most).  Its waves leave too few registers for a far-field M2L wave of
+// p = 5 or 6 (about 148) to start beside them, so for those orders the
+// evaluation takes the general kernel, whose finished waves make room.
+template <bool MASK_ALL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void p2p_kernel_w4(
+    const P2PItem *__restrict__ items, const int32_t *__restrict__ run_body,
+    const int32_t *__restrict__ run_prefix, const float4 *__restrict__ bodies,
+    float4 *__restrict__ out_s, float4 *__restrict__ out_c) {
+  p2p_wave<float, kCharges, true, MASK_ALL, kP2PMaxTargetsPerLane>(
+      items, run_body, run_prefix, bodies, nullptr, out_s, out_c);
+}
+
 template <typename Real, int MODE>
-void launch_p2p(bool mask_all, unsigned G, hipStream_t st, const P2PItem *items,
+void launch_p2p(bool mask_all, bool four_waves, unsigned G, hipStream_t st, const P2PItem *items,
                 const int32_t *run_body, const int32_t *run_prefix, const void *bodies,
                 const void *vec, void *part_s, void *part_c) {
   using V4 = typename Vec<Real>::V4;
   constexpr bool kahan = std::is_same<Real, float>::value;
   const V4 *b = (const V4 *)bodies;
   const V4 *v = (const V4 *)vec;
+  if constexpr (std::is_same<Real, float>::value && MODE == kCharges) {
+    if (four_waves) {
+      if (mask_all)
+        p2p_kernel_w4<true><<<G, 64, 0, st>>>(items, run_body, run_prefix, b, (V4 *)part_s,
+                                              (V4 *)part_c);
+      else
+        p2p_kernel_w4<false><<<G, 64, 0, st>>>(items, run_body, run_prefix, b, (V4 *)part_s,
+                                               (V4 *)part_c);
+      return;
+    }
+  }
   if (mask_all)
     p2p_kernel<Real, MODE, kahan, true><<<G, 64, 0, st>>>(items, run_body, run_prefix, b, v,
                                                           (V4 *)part_s, (V4 *)part_c);
@@ -451,9 +499,9 @@ __device__ __forceinline__ void p2p_mutual_phase(int nsrc, LookupFn lookup,
   const int u = lane & 15, row = lane >> 4;
   const float far = Vec<float>::kFar;
   constexpr int NL = kNB / 64;
-  // A lane meets TL sources per ring, 8 TL per batch: its plain partial is
+  // A lane meets TL sources per ring, NL TL per batch: its plain partial is
   // folded into (S, C) once it covers at least 64.
-  const int kb = TL >= 8 ? 1 : 8 / TL;
+  const int kb = (64 + NL * TL - 1) / (NL * TL);
   float p[R][4];
 #pragma unroll
   for (int r = 0; r < R; ++r) p[r][0] = p[r][1] = p[r][2] = p[r][3] = 0.0f;
@@ -619,32 +667,29 @@ __global__ __launch_bounds__(64) void p2p_mutual_kernel(
 
 }  // namespace
 
-int p2p(bool fp64, int mode, bool mask_all, int64_t n_items, const P2PItem *items,
-        const int32_t *run_body, const int32_t *run_prefix, const void *bodies, const void *vec,
-        void *part_s, void *part_c, void *stream) {
+int p2p(bool fp64, int mode, bool mask_all, bool four_waves, int64_t n_items,
+        const P2PItem *items, const int32_t *run_body, const int32_t *run_prefix,
+        const void *bodies, const void *vec, void *part_s, void *part_c, void *stream) {
   if (n_items == 0) return 0;
   const unsigned G = (unsigned)n_items;
   const hipStream_t st = S_(stream);
+  auto go = [&](auto real, auto mode_c) {
+    using R = decltype(real);
+    constexpr int M = decltype(mode_c)::value;
+    launch_p2p<R, M>(mask_all, four_waves, G, st, items, run_body, run_prefix, bodies, vec,
+                     part_s, std::is_same<R, float>::value ? part_c : nullptr);
+  };
+  using IC = std::integral_constant<int, kCharges>;
+  using ID = std::integral_constant<int, kDipoles>;
+  using IH = std::integral_constant<int, kHessVec>;
   if (fp64) {
-    if (mode == kCharges)
-      launch_p2p<double, kCharges>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
-                                   part_s, nullptr);
-    else if (mode == kDipoles)
-      launch_p2p<double, kDipoles>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
-                                   part_s, nullptr);
-    else
-      launch_p2p<double, kHessVec>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
-                                   part_s, nullptr);
+    if (mode == kCharges) go(0.0, IC{});
+    else if (mode == kDipoles) go(0.0, ID{});
+    else go(0.0, IH{});
   } else {
-    if (mode == kCharges)
-      launch_p2p<float, kCharges>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
-                                  part_s, part_c);
-    else if (mode == kDipoles)
-      launch_p2p<float, kDipoles>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
-                                  part_s, part_c);
-    else
-      launch_p2p<float, kHessVec>(mask_all, G, st, items, run_body, run_prefix, bodies, vec,
-                                  part_s, part_c);
+    if (mode == kCharges) go(0.0f, IC{});
+    else if (mode == kDipoles) go(0.0f, ID{});
+    else go(0.0f, IH{});
   }
   return (int)hipGetLastError();
 }

@@ -25,7 +25,7 @@ int64_t plan_index_limit() {
 void p2p_lane_layout(int nt, int *R, int *L, int *K) {
   double best = -1.0;
   int bR = 1, bL = nt, bK = 1;
-  for (int r = 1; r <= 8; ++r) {
+  for (int r = 1; r <= kP2PMaxTargetsPerLane; ++r) {
     const int l = (nt + r - 1) / r;
     if (l > 64) continue;
     const int k = 64 / l;
