@@ -160,21 +160,19 @@ def main():
         fmm.evaluate(tree, lists, qt, p, out=(phi, grad), m2l_mfma=mf, mutual_p2p=mu)
     torch.cuda.synchronize()
 
-    # Timed region: K evaluations, each with per-phase HIP events recorded on
-    # the stream the kernels run on.
-    phase_sum = dict.fromkeys(fmm.PHASES, 0.0)
+    # Timed region: K evaluations back to back, each recording per-phase HIP
+    # events on the streams its kernels run on; the events are read after the
+    # region (the mean over the last min(K, TIMING_HISTORY) evaluations), so
+    # that no step waits for the previous one.
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         fmm.evaluate(tree, lists, qt, p, timing=True, out=(phi, grad), m2l_mfma=mf,
                      mutual_p2p=mu)
-        ms = fmm.last_timings(lists)
-        for k in fmm.PHASES:
-            phase_sum[k] += ms[k]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     print("timed %d steps in %.3fs" % (args.steps, elapsed), file=sys.stderr, flush=True)
-    phase_ms = {k: v / args.steps for k, v in phase_sum.items()}
+    phase_ms = fmm.mean_timings(lists, min(args.steps, fmm.TIMING_HISTORY))
     sclk = gpu_sclk_mhz()  # right after the timed region
     ms_per_step = 1e3 * elapsed / args.steps
     stats = lists.stats()

@@ -401,10 +401,25 @@ int fmm_direct(const void *xyz_dev, const void *q_dev, int64_t n, const int64_t 
 
 /*
  * Per-phase device times (milliseconds, enum fmm_phase order) of the last
- * fmm_evaluate on these lists that was called with FMM_EVAL_TIMING.  Waits for
- * that evaluation to finish.  ms must hold FMM_NUM_PHASES doubles.
+ * evaluation on these lists (fmm_evaluate, fmm_evaluate_range or
+ * fmm_evaluate_backward's passes), which must have been called with
+ * FMM_EVAL_TIMING (FMM_ESTATE otherwise).  Waits for that evaluation to
+ * finish.  ms must hold FMM_NUM_PHASES doubles.
  */
 int fmm_last_timings(const fmm_lists *l, double *ms);
+
+/*
+ * Mean per-phase device times (milliseconds, enum fmm_phase order) over the
+ * last n evaluations on these lists, all called with FMM_EVAL_TIMING one
+ * after another (an evaluation without the flag starts the count again);
+ * the events of the last FMM_TIMING_HISTORY timed evaluations are held, so a
+ * run of evaluations can be timed without waiting between them and read
+ * afterwards.  Waits for the newest to finish.  ms must hold FMM_NUM_PHASES
+ * doubles.  FMM_EINVAL unless 1 <= n <= FMM_TIMING_HISTORY; FMM_ESTATE if
+ * fewer than n such evaluations are held.
+ */
+#define FMM_TIMING_HISTORY 64
+int fmm_mean_timings(const fmm_lists *l, int n, double *ms);
 
 /* Message for the last failure on the calling thread ("" if none). */
 const char *fmm_last_error(void);

@@ -117,9 +117,15 @@ struct DevLists {
   // near-field stream (forked from / joined into the caller's stream)
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
-  // timing: 8 marks on the caller's stream, 2 around P2P
-  hipEvent_t ev[FMM_NUM_PHASES + 2] = {};
-  bool have_events = false, timing_valid = false, timed_serial = false;
+  // timing: each timed evaluation records 8 marks on the caller's stream and
+  // 2 around P2P into the next of FMM_TIMING_HISTORY sets, so that a run of
+  // evaluations can be timed and read afterwards without waiting between
+  // them.  ring_count: consecutive timed evaluations held, the last one
+  // newest (an evaluation without timing sets it to 0).
+  hipEvent_t ev[FMM_TIMING_HISTORY][FMM_NUM_PHASES + 2] = {};
+  bool ev_made[FMM_TIMING_HISTORY] = {};
+  bool ring_serial[FMM_TIMING_HISTORY] = {};
+  int ring_next = 0, ring_count = 0;
   void release_scratch() {
     void *ptrs[] = {M, Mr, L, Lstage, M64, L64, L64stage, part_s, part_c, tmp_phi, tmp_grad,
                     vec4, tmp_hv, m2p_buf};
@@ -154,8 +160,9 @@ struct DevLists {
                     mt_cells, mt_goff, mt_gsrc, mt_gbeg, mt_off, mt_dtab};
     for (void *p2 : ptrs)
       if (p2) (void)hipFree(p2);
-    if (have_events)
-      for (auto &e : ev) (void)hipEventDestroy(e);
+    for (int k = 0; k < FMM_TIMING_HISTORY; ++k)
+      if (ev_made[k])
+        for (auto &e : ev[k]) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
     if (side) (void)hipStreamDestroy(side);
@@ -680,9 +687,10 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
     set_error("internal error: timing or kept stages with a fixed scratch buffer");
     return FMM_EINVAL;
   }
-  if (timing && !dv.have_events) {
-    for (auto &e : dv.ev) HIP_TRY(hipEventCreate(&e));
-    dv.have_events = true;
+  const int set = dv.ring_next;  // the event set of a timed evaluation
+  if (timing && !dv.ev_made[set]) {
+    for (auto &e : dv.ev[set]) HIP_TRY(hipEventCreate(&e));
+    dv.ev_made[set] = true;
   }
   if (overlap && !dv.side) {
     // default priority, non-blocking with respect to the null stream
@@ -690,10 +698,14 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
     HIP_TRY(hipEventCreateWithFlags(&dv.fork, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&dv.join, hipEventDisableTiming));
   }
-  dv.timing_valid = false;
+  // An evaluation that fails part way leaves no timed evaluations held.  The
+  // allocation-free path leaves the timings (and kept stages) of the last
+  // allocating evaluation as they are.
+  const int prev_count = dv.ring_count;
+  if (!fixed_scratch) dv.ring_count = 0;
   g_launch_counter = 0;
   auto mark = [&](int k, hipStream_t st) -> int {
-    if (timing) HIP_TRY(hipEventRecord(dv.ev[k], st));
+    if (timing) HIP_TRY(hipEventRecord(dv.ev[set][k], st));
     return FMM_OK;
   };
   const int p = o->p;
@@ -819,7 +831,7 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
       HIP_TRY(hipMemcpyAsync(dv.L64stage, sc.L64, (size_t)n_top * S * 8, hipMemcpyDeviceToDevice,
                              s));
     dv.stage_valid = true;
-  } else {
+  } else if (!fixed_scratch) {
     dv.stage_valid = false;
   }
   if (int rc = mark(4, s)) return rc;
@@ -849,8 +861,13 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
                             dv.n_m2p_rows > 0 ? sc.m2p_buf : nullptr, dt.perm, phi, grad,
                             stream));
   if (int rc = mark(7, s)) return rc;
-  dv.timed_serial = !overlap;
-  dv.timing_valid = timing;
+  if (timing) {
+    dv.ring_serial[set] = !overlap;
+    dv.ring_next = (set + 1) % FMM_TIMING_HISTORY;
+    dv.ring_count = std::min(prev_count + 1, FMM_TIMING_HISTORY);
+  } else if (fixed_scratch) {
+    dv.ring_count = prev_count;
+  }
   return FMM_OK;
 }
 
@@ -1487,31 +1504,59 @@ int fmm_direct(const void *xyz_dev, const void *q_dev, int64_t n, const int64_t 
   return FMM_OK;
 }
 
+namespace {
+
+// Per-phase times (ms) of the timed evaluation whose events are set k.
+int set_timings(const DevLists &dv, int k, double *ms) {
+  HIP_TRY(hipEventSynchronize(dv.ev[k][7]));
+  HIP_TRY(hipEventSynchronize(dv.ev[k][9]));
+  // marks: 0 start, 1 after gather, 8/9 around P2P, 2 after P2M, 3 after M2M,
+  // 4 after M2L, 5 after L2L, 6 after the join, 7 end.
+  const int p2m_from = dv.ring_serial[k] ? 9 : 1;
+  const int pairs[FMM_NUM_PHASES][2] = {{0, 1}, {8, 9}, {p2m_from, 2}, {2, 3},
+                                        {3, 4}, {4, 5}, {6, 7}, {0, 7}};
+  for (int i = 0; i < FMM_NUM_PHASES; ++i) {
+    float f = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&f, dv.ev[k][pairs[i][0]], dv.ev[k][pairs[i][1]]));
+    ms[i] = f;
+  }
+  return FMM_OK;
+}
+
+}  // namespace
+
 int fmm_last_timings(const fmm_lists *l, double *ms) {
   if (!l || !ms) {
     set_error("fmm_last_timings: NULL argument");
     return FMM_EINVAL;
   }
   const DevLists &dv = l->dev;
-  if (!dv.timing_valid) {
+  if (dv.ring_count < 1) {
     set_error("fmm_last_timings: last evaluation was not timed");
     return FMM_ESTATE;
   }
-  HIP_TRY(hipEventSynchronize(dv.ev[7]));
-  HIP_TRY(hipEventSynchronize(dv.ev[9]));
-  auto span = [&](int a, int b, double *out) -> int {
-    float f = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&f, dv.ev[a], dv.ev[b]));
-    *out = f;
-    return FMM_OK;
-  };
-  // marks: 0 start, 1 after gather, 8/9 around P2P, 2 after P2M, 3 after M2M,
-  // 4 after M2L, 5 after L2L, 6 after the join, 7 end.
-  const int p2m_from = dv.timed_serial ? 9 : 1;
-  const int pairs[FMM_NUM_PHASES][2] = {{0, 1}, {8, 9}, {p2m_from, 2}, {2, 3},
-                                        {3, 4}, {4, 5}, {6, 7}, {0, 7}};
-  for (int k = 0; k < FMM_NUM_PHASES; ++k)
-    if (int rc = span(pairs[k][0], pairs[k][1], &ms[k])) return rc;
+  return set_timings(dv, (dv.ring_next + FMM_TIMING_HISTORY - 1) % FMM_TIMING_HISTORY, ms);
+}
+
+int fmm_mean_timings(const fmm_lists *l, int n, double *ms) {
+  if (!l || !ms || n < 1 || n > FMM_TIMING_HISTORY) {
+    set_error("fmm_mean_timings: need l, ms != NULL and 1 <= n <= FMM_TIMING_HISTORY");
+    return FMM_EINVAL;
+  }
+  const DevLists &dv = l->dev;
+  if (dv.ring_count < n) {
+    set_error("fmm_mean_timings: fewer than n timed evaluations in a row are held");
+    return FMM_ESTATE;
+  }
+  for (int i = 0; i < FMM_NUM_PHASES; ++i) ms[i] = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double one[FMM_NUM_PHASES];
+    if (int rc = set_timings(dv, (dv.ring_next + FMM_TIMING_HISTORY - 1 - j) % FMM_TIMING_HISTORY,
+                             one))
+      return rc;
+    for (int i = 0; i < FMM_NUM_PHASES; ++i) ms[i] += one[i];
+  }
+  for (int i = 0; i < FMM_NUM_PHASES; ++i) ms[i] /= n;
   return FMM_OK;
 }
 

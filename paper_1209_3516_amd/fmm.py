@@ -60,7 +60,7 @@ class _ListStats(ctypes.Structure):
 
 EXPORTS = ("fmm_tree_build", "fmm_tree_build_ex", "fmm_tree_set_positions", "fmm_tree_view", "fmm_tree_free",
            "fmm_traverse", "fmm_lists_view", "fmm_lists_stats", "fmm_lists_free",
-           "fmm_evaluate", "fmm_evaluate_backward", "fmm_direct", "fmm_last_timings",
+           "fmm_evaluate", "fmm_evaluate_backward", "fmm_direct", "fmm_last_timings", "fmm_mean_timings",
            "fmm_last_error", "fmm_num_terms", "fmm_copy_expansions", "fmm_term_exponents",
            "fmm_traverse_gpu", "fmm_tree_build_gpu", "fmm_evaluate_range",
            "fmm_partition_targets", "fmm_traverse_hybrid", "fmm_evaluate_noalloc",
@@ -106,6 +106,7 @@ def lib():
                                    vp], i32),
         "fmm_direct": ([vp, vp, i64, vp, i64, vp, vp, vp], i32),
         "fmm_last_timings": ([vp, ctypes.POINTER(dbl)], i32),
+        "fmm_mean_timings": ([vp, i32, ctypes.POINTER(dbl)], i32),
         "fmm_last_error": ([], ctypes.c_char_p),
         "fmm_num_terms": ([i32], i32),
         "fmm_copy_expansions": ([vp, i32, vp], i32),
@@ -404,6 +405,18 @@ def last_timings(lists):
     """Per-phase device times (ms) of the last evaluation run with timing=True."""
     ms = (ctypes.c_double * len(PHASES))()
     _check(lib().fmm_last_timings(lists._h, ms))
+    return dict(zip(PHASES, list(ms)))
+
+
+TIMING_HISTORY = 64
+
+
+def mean_timings(lists, n):
+    """Mean per-phase device times (ms) of the last n evaluations, all run with
+    timing=True one after another (n <= TIMING_HISTORY); read after the run,
+    so that the run itself has no waits between evaluations."""
+    ms = (ctypes.c_double * len(PHASES))()
+    _check(lib().fmm_mean_timings(lists._h, int(n), ms))
     return dict(zip(PHASES, list(ms)))
 
 

@@ -240,6 +240,44 @@ def test_timings_are_reported():
     assert 0 < ms["p2p"] <= ms["total"] and ms["m2l"] > 0
 
 
+def test_mean_timings_over_a_run_without_waits():
+    """fmm_mean_timings: the mean of the per-evaluation times of the last n
+    timed evaluations (the same events fmm_last_timings reads one by one); an
+    untimed evaluation starts the count again; the allocation-free entry
+    point leaves the timings of the last timed fmm_evaluate as they are."""
+    x = W.uniform_cube(20_000, seed=29)
+    t = fmm.Tree(x, 64)
+    lst = fmm.Lists(t, 0.4)
+    qt = torch.tensor(W.charges(20_000), dtype=torch.float32, device=DEV)
+    one = []
+    for _ in range(3):
+        fmm.evaluate(t, lst, qt, 4, timing=True)
+        one.append(fmm.last_timings(lst))
+    mean = fmm.mean_timings(lst, 3)
+    for k in fmm.PHASES:
+        assert abs(mean[k] - sum(o[k] for o in one) / 3) <= 1e-9 * max(1.0, abs(mean[k]))
+    assert fmm.mean_timings(lst, 1)["total"] == one[-1]["total"]
+    with pytest.raises(fmm.FMMError) as e:
+        fmm.mean_timings(lst, 4)
+    assert e.value.code == fmm.FMM_ESTATE
+    with pytest.raises(fmm.FMMError) as e:
+        fmm.mean_timings(lst, fmm.TIMING_HISTORY + 1)
+    assert e.value.code == fmm.FMM_EINVAL
+    # a run longer than the history: the newest TIMING_HISTORY are held
+    for _ in range(fmm.TIMING_HISTORY + 2):
+        fmm.evaluate(t, lst, qt, 4, timing=True)
+    assert fmm.mean_timings(lst, fmm.TIMING_HISTORY)["p2p"] > 0
+    phi = torch.empty(20_000, dtype=torch.float32, device=DEV)
+    g = torch.empty(20_000, 3, dtype=torch.float32, device=DEV)
+    fmm.evaluate_noalloc(t, lst, qt, phi, g, 4)
+    torch.cuda.synchronize()
+    assert fmm.mean_timings(lst, 2)["total"] > 0
+    fmm.evaluate(t, lst, qt, 4)  # untimed: nothing timed is held any more
+    with pytest.raises(fmm.FMMError) as e:
+        fmm.mean_timings(lst, 1)
+    assert e.value.code == fmm.FMM_ESTATE
+
+
 def test_serial_and_overlapped_agree_bitwise():
     x = W.uniform_cube(50_000, seed=31)
     t = fmm.Tree(x, 64)

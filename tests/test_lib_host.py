@@ -164,6 +164,9 @@ def test_invalid_arguments_are_rejected_without_gpu():
     assert L.fmm_evaluate_backward(t._h, lst._h, ctypes.byref(o), dummy, dummy, None, dummy,
                                    dummy, dummy, None) == fmm.FMM_EINVAL
     assert L.fmm_last_timings(lst._h, (ctypes.c_double * 8)()) == fmm.FMM_ESTATE
+    assert L.fmm_mean_timings(lst._h, 1, (ctypes.c_double * 8)()) == fmm.FMM_ESTATE
+    assert L.fmm_mean_timings(lst._h, 0, (ctypes.c_double * 8)()) == fmm.FMM_EINVAL
+    assert L.fmm_mean_timings(lst._h, 65, (ctypes.c_double * 8)()) == fmm.FMM_EINVAL
     assert L.fmm_copy_expansions(lst._h, 0, dummy) == fmm.FMM_ESTATE
     assert L.fmm_num_terms(0) == -1 and L.fmm_num_terms(4) == 20 and L.fmm_num_terms(8) == 120
 
