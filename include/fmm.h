@@ -273,6 +273,27 @@ void fmm_lists_free(fmm_lists *l);
 int fmm_mutual_plan_stats(const fmm_tree *t, const fmm_lists *l, int64_t *out);
 
 /*
+ * The order in which an evaluation over all targets dispatches its P2P and
+ * M2L work on the GPU (scheduling only: it changes no result, and the
+ * method does not define it), copied to the host.  Work-groups go to the
+ * GPU's eight XCDs in turn.
+ *   kind FMM_P2P: the P2P work items (one per group of at most 64 targets of
+ *     a leaf and chunk of its sources) by decreasing estimated cost, ties in
+ *     plan order; *len = the number of work items, and out holds a
+ *     permutation of 0 .. *len - 1 (work-group w takes item out[w]).
+ *   kind FMM_M2L: the cells in eight contiguous ranges of about equal M2L
+ *     work (a row costs one pass per 64 entries, plus one), range x for XCD
+ *     x, each range's rows by decreasing length (ties in cell order);
+ *     *len = 8 m, m the cells of the largest range, and out[8 j + x] is the
+ *     j-th cell of range x or -1 past its end (work-group w takes cell
+ *     out[w]; every cell occurs once).
+ * The lists must be on the device (after fmm_traverse_gpu or a first
+ * evaluation; FMM_ESTATE otherwise).  out: caller-owned int32[cap], or NULL
+ * to get *len only; FMM_EINVAL for another kind, a NULL len, or cap < *len.
+ */
+int fmm_dispatch_order(const fmm_lists *l, int kind, int32_t *out, int64_t cap, int64_t *len);
+
+/*
  * Forward evaluation on one GPU: the evaluation phase of the method, i.e. the
  * kernels the paper names (section 3.3 and the list of kernels timed with
  * Table 4): P2M on every leaf and M2M up the tree (upward pass), M2L over the

@@ -75,6 +75,9 @@ struct DevLists {
   bool host_valid = true;  // ListData holds the CSR lists (else only the device does)
   int64_t *m2l_ptr = nullptr, *p2p_ptr = nullptr;
   int32_t *m2l_col = nullptr, *p2p_col = nullptr;
+  // M2L dispatch order for a launch over all cells (m2l_order_len entries)
+  int32_t *m2l_order = nullptr;
+  int64_t m2l_order_len = 0;
   int64_t p2p_nnz = 0, m2l_nnz = 0;
   // hybrid lists: M2P CSR and the target leaves that have M2P entries
   int64_t *m2p_ptr = nullptr;
@@ -156,7 +159,7 @@ struct DevLists {
     release_scratch();
     release_mutual();
     plan.release();
-    void *ptrs[] = {m2l_ptr, m2l_col, p2p_ptr, p2p_col, m2p_ptr, m2p_col, m2p_rows,
+    void *ptrs[] = {m2l_ptr, m2l_col, m2l_order, p2p_ptr, p2p_col, m2p_ptr, m2p_col, m2p_rows,
                     mt_cells, mt_goff, mt_gsrc, mt_gbeg, mt_off, mt_dtab};
     for (void *p2 : ptrs)
       if (p2) (void)hipFree(p2);
@@ -351,6 +354,10 @@ int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
   dp.release();
   if (int rc = dev_upload(&dv.m2l_ptr, ld.m2l_ptr.data(), ld.m2l_ptr.size())) return rc;
   if (int rc = dev_upload(&dv.m2l_col, ld.m2l_col.data(), ld.m2l_col.size())) return rc;
+  if (dv.m2l_order) (void)hipFree(dv.m2l_order);
+  if (int rc = fmmlib::dev::order_m2l_rows(dv.m2l_ptr, ld.n_rows, &dv.m2l_order,
+                                           &dv.m2l_order_len, nullptr))
+    return hip_fail((hipError_t)rc, "order_m2l_rows");
   if (!ld.m2p_col.empty()) {
     std::vector<int32_t> rows;
     for (int64_t c = 0; c < ld.n_rows; ++c)
@@ -374,6 +381,8 @@ int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
   dp.n_partials = pl.n_partials;
   dp.max_row_sources = pl.max_row_sources;
   dp.p2p_pairs = ld.p2p_pairs;
+  if (int rc = fmmlib::dev::order_p2p_items(dp, nullptr))
+    return hip_fail((hipError_t)rc, "order_p2p_items");
   dv.leaf_nchunk_host = pl.leaf_nchunk;
   dv.device = t->dev.device;
   dv.uploaded = true;
@@ -754,8 +763,8 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
                              dv.mp_run_prefix, dv.mp_run_dst, bodies, sc.part_s, sc.part_c,
                              dv.part_m, ns));
   } else if (!ranged) {
-    LAUNCH_TRY(D::p2p(fp64, mode, mask_all, p2p_four_waves, pl.n_items, pl.items, pl.run_body,
-                      pl.run_prefix, bodies, vec, sc.part_s, sc.part_c, ns));
+    LAUNCH_TRY(D::p2p(fp64, mode, mask_all, p2p_four_waves, pl.n_items, pl.items, pl.order,
+                      pl.run_body, pl.run_prefix, bodies, vec, sc.part_s, sc.part_c, ns));
   } else {
     // the items of the range's leaves: one contiguous run per level
     for (int lev = 0; lev <= max_level; ++lev) {
@@ -763,7 +772,8 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
       const int64_t i1 = dv.leaf_item_host[rcells.leaf_hi[lev]];
       if (i1 > i0)
         LAUNCH_TRY(D::p2p(fp64, mode, mask_all, p2p_four_waves, i1 - i0, pl.items + i0,
-                          pl.run_body, pl.run_prefix, bodies, vec, sc.part_s, sc.part_c, ns));
+                          nullptr, pl.run_body, pl.run_prefix, bodies, vec, sc.part_s, sc.part_c,
+                          ns));
     }
   }
   if (int rc = mark(9, ns)) return rc;
@@ -788,14 +798,18 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
     // every cell is an M2L row (one without entries writes zeros); the top
     // n_top cells accumulate in FP64.  A target range takes, level by level,
     // the cells holding its bodies.
+    // a launch over all cells takes the cells in the lists' dispatch order
+    auto order_for = [&](int64_t a, int64_t b) -> const int32_t * {
+      return a == 0 && b == td.n_cells() ? dv.m2l_order : nullptr;
+    };
     auto m2l_cells = [&](int64_t c0, int64_t c1) -> int {
       const int64_t split = std::max(c0, std::min(n_top, c1));
       if (split > c0)
         LAUNCH_TRY(D::m2l(p, fp64, c0, split, dv.m2l_ptr, dv.m2l_col, geo, sc.Mr, sc.L, sc.L64,
-                          true, stream));
+                          true, order_for(c0, split), dv.m2l_order_len, stream));
       if (c1 > split)
         LAUNCH_TRY(D::m2l(p, fp64, split, c1, dv.m2l_ptr, dv.m2l_col, geo, sc.Mr, sc.L, sc.L64,
-                          false, stream));
+                          false, order_for(split, c1), dv.m2l_order_len, stream));
       return FMM_OK;
     };
     const bool mfma = (o->flags & FMM_EVAL_M2L_MFMA) != 0;
@@ -807,7 +821,7 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
       // FP64-accumulated top levels entry by entry, the rest batched
       if (n_top > 0) {
         LAUNCH_TRY(D::m2l(p, fp64, 0, n_top, dv.m2l_ptr, dv.m2l_col, geo, sc.Mr, sc.L, sc.L64,
-                          true, stream));
+                          true, order_for(0, n_top), dv.m2l_order_len, stream));
       }
       int lev0 = 0;
       while (lev0 <= max_level && td.level_begin[lev0] < n_top) ++lev0;
@@ -1256,6 +1270,15 @@ int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists 
         fmm_lists_free(l);
         return hip_fail((hipError_t)rc, "build_p2p_plan_gpu");
       }
+      if (const int rc2 = fmmlib::dev::order_p2p_items(dv.plan, stream)) {
+        fmm_lists_free(l);
+        return hip_fail((hipError_t)rc2, "order_p2p_items");
+      }
+      if (const int rc2 = fmmlib::dev::order_m2l_rows(dv.m2l_ptr, td.n_cells(), &dv.m2l_order,
+                                                      &dv.m2l_order_len, stream)) {
+        fmm_lists_free(l);
+        return hip_fail((hipError_t)rc2, "order_m2l_rows");
+      }
       if (std::getenv("FMM_LOG"))
         std::fprintf(stderr, "[fmm] device work plan: %.2f ms (%lld items, %lld runs)\n",
                      ms_since(t_plan), (long long)dv.plan.n_items, (long long)dv.plan.n_runs);
@@ -1341,6 +1364,28 @@ int fmm_mutual_plan_stats(const fmm_tree *t, const fmm_lists *l, int64_t *out) {
     set_error("fmm_mutual_plan_stats: out of host memory");
     return FMM_ENOMEM;
   }
+  return FMM_OK;
+}
+
+int fmm_dispatch_order(const fmm_lists *l, int kind, int32_t *out, int64_t cap, int64_t *len) {
+  if (!l || !len || (kind != FMM_P2P && kind != FMM_M2L)) {
+    set_error("fmm_dispatch_order: NULL lists or len, or kind is not FMM_P2P or FMM_M2L");
+    return FMM_EINVAL;
+  }
+  const DevLists &dv = l->dev;
+  if (!dv.uploaded) {
+    set_error("fmm_dispatch_order: the lists are not on a device yet");
+    return FMM_ESTATE;
+  }
+  const int32_t *src = kind == FMM_P2P ? dv.plan.order : dv.m2l_order;
+  const int64_t n = !src ? 0 : kind == FMM_P2P ? dv.plan.n_items : dv.m2l_order_len;
+  *len = n;
+  if (!out) return FMM_OK;
+  if (cap < n) {
+    set_error("fmm_dispatch_order: cap is smaller than the order's length");
+    return FMM_EINVAL;
+  }
+  if (n > 0) HIP_TRY(hipMemcpy(out, src, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost));
   return FMM_OK;
 }
 

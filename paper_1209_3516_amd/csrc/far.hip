@@ -261,10 +261,12 @@ __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ 
                                         const int32_t *__restrict__ col,
                                         const double4 *__restrict__ geo,
                                         const Real *__restrict__ Mr, Acc *__restrict__ Lout,
-                                        Acc *__restrict__ red) {
+                                        Acc *__restrict__ red,
+                                        const int32_t *__restrict__ order) {
   constexpr int T = nterms(P), S = pad4(T), TR = rterms(P), SR = pad4(TR);
   const int lane = threadIdx.x;
-  const int A = (int)(r0 + xcd_remap(blockIdx.x, gridDim.x));
+  const int A = order ? order[blockIdx.x] : (int)(r0 + xcd_remap(blockIdx.x, gridDim.x));
+  if (A < 0) return;  // padding of an ordered launch
   const double4 ga = geo[A];
   Acc acc[TR];
   static_for<TR>([&](auto I) { acc[decltype(I)::value] = Acc(0); });
@@ -386,9 +388,10 @@ template <int P, typename Real, typename Acc>
 __global__ __launch_bounds__(64) void m2l_kernel(int64_t r0, const int64_t *__restrict__ ptr,
                                                  const int32_t *__restrict__ col,
                                                  const double4 *__restrict__ geo,
-                                                 const Real *__restrict__ Mr, Acc *__restrict__ Lout) {
+                                                 const Real *__restrict__ Mr, Acc *__restrict__ Lout,
+                                                 const int32_t *__restrict__ order) {
   __shared__ Acc red[64 * (m2l_red_terms(nterms(P)) + 1)];
-  m2l_row<P, Real, Acc>(r0, ptr, col, geo, Mr, Lout, red);
+  m2l_row<P, Real, Acc>(r0, ptr, col, geo, Mr, Lout, red, order);
 }
 
 // The same for high orders in FP32, held to two waves per SIMD (at most 256
@@ -397,9 +400,10 @@ __global__ __launch_bounds__(64) void m2l_kernel(int64_t r0, const int64_t *__re
 template <int P, typename Real, typename Acc>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_kernel_w2(
     int64_t r0, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-    const double4 *__restrict__ geo, const Real *__restrict__ Mr, Acc *__restrict__ Lout) {
+    const double4 *__restrict__ geo, const Real *__restrict__ Mr, Acc *__restrict__ Lout,
+    const int32_t *__restrict__ order) {
   __shared__ Acc red[64 * (m2l_red_terms(nterms(P)) + 1)];
-  m2l_row<P, Real, Acc>(r0, ptr, col, geo, Mr, Lout, red);
+  m2l_row<P, Real, Acc>(r0, ptr, col, geo, Mr, Lout, red, order);
 }
 
 // Middle orders in FP32 at three waves per SIMD (at most 168 registers per
@@ -407,9 +411,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 template <int P, typename Real, typename Acc>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void m2l_kernel_w3(
     int64_t r0, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-    const double4 *__restrict__ geo, const Real *__restrict__ Mr, Acc *__restrict__ Lout) {
+    const double4 *__restrict__ geo, const Real *__restrict__ Mr, Acc *__restrict__ Lout,
+    const int32_t *__restrict__ order) {
   __shared__ Acc red[64 * (32 + 1)];
-  m2l_row<P, Real, Acc, 32, true>(r0, ptr, col, geo, Mr, Lout, red);
+  m2l_row<P, Real, Acc, 32, true>(r0, ptr, col, geo, Mr, Lout, red, order);
 }
 
 // ----------------------------------------------------------------------------
@@ -726,27 +731,28 @@ int fold_multipoles(int p, bool fp64, int64_t n_cells, const void *M, void *Mr, 
 
 int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
         const int32_t *col, const double *geo, const void *Mr, void *L, double *L64,
-        bool acc_fp64, void *stream) {
+        bool acc_fp64, const int32_t *order, int64_t n_order, void *stream) {
   if (r1 <= r0) return 0;
-  const unsigned G = (unsigned)(r1 - r0);
+  const unsigned G = (unsigned)(order ? n_order : r1 - r0);
   const double4 *g = (const double4 *)geo;
+  const int32_t *o = order;
   return with_p(p, [&](auto PC) {
     constexpr int PP = decltype(PC)::value;
     if (fp64)
-      m2l_kernel<PP, double, double><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
-                                                               (const double *)Mr, (double *)L);
+      m2l_kernel<PP, double, double><<<G, 64, 0, S_(stream)>>>(
+          r0, ptr, col, g, (const double *)Mr, (double *)L, o);
     else if (acc_fp64)
       m2l_kernel<PP, float, double><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
-                                                              (const float *)Mr, L64);
+                                                              (const float *)Mr, L64, o);
     else if constexpr (rterms(PP) > 36)
       m2l_kernel_w2<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
-                                                                (const float *)Mr, (float *)L);
+                                                                (const float *)Mr, (float *)L, o);
     else if constexpr (PP >= 5)
       m2l_kernel_w3<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
-                                                                (const float *)Mr, (float *)L);
+                                                                (const float *)Mr, (float *)L, o);
     else
       m2l_kernel<PP, float, float><<<G, 64, 0, S_(stream)>>>(r0, ptr, col, g,
-                                                             (const float *)Mr, (float *)L);
+                                                             (const float *)Mr, (float *)L, o);
   });
 }
 

@@ -33,9 +33,17 @@ enum EvalMode { kCharges = 0, kDipoles = 1, kHessVec = 2 };
 // four_waves: in FP32 charges mode, the kernel held to four waves per SIMD
 // (else the general one, three waves); the caller picks it by whether the
 // far field's M2L waves, running beside P2P, fit in what its waves leave.
+// order: NULL (work-group w of the launch takes item xcd_remap(w), so that
+// each XCD works on a contiguous range of the Morton-ordered items), or a
+// permutation of the n_items items (work-group w takes item order[w]), such
+// as DevicePlan::order for a launch over all items of a plan.
 int p2p(bool fp64, int mode, bool mask_all, bool four_waves, int64_t n_items,
-        const P2PItem *items, const int32_t *run_body, const int32_t *run_prefix,
-        const void *bodies, const void *vec, void *part_s, void *part_c, void *stream);
+        const P2PItem *items, const int32_t *order, const int32_t *run_body,
+        const int32_t *run_prefix, const void *bodies, const void *vec, void *part_s,
+        void *part_c, void *stream);
+
+// Sources the P2P kernels stage through LDS per batch.
+constexpr int kP2PStageBatch = 384;
 
 // Mutual P2P over the items of a P2PMutualPlan (FP32 charges): target sums to
 // (part_s, part_c) at each item's out_off, source sums to part_m at the runs'
@@ -80,9 +88,29 @@ int m2l_mfma(int p, int64_t tile0, int64_t tile1, const int32_t *tile_cells,
 
 // Target cells [r0, r1) from the folded multipoles Mr; acc_fp64: the row
 // accumulates in FP64 into L64, else into L (FP32 in mixed mode).
+// order: NULL (r1 - r0 work-groups; work-group w takes cell r0 + xcd_remap(w)),
+// or the n_order entries of an order_m2l_rows order of the cells [r0, r1)
+// (n_order work-groups; work-group w takes cell order[w], none if it is -1).
 int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
         const int32_t *col, const double *geo, const void *Mr, void *L, double *L64,
-        bool acc_fp64, void *stream);
+        bool acc_fp64, const int32_t *order, int64_t n_order, void *stream);
+
+// Dispatch order of the M2L rows of n_cells cells (CSR row pointers ptr) for
+// a launch over all of them.  Work-groups go to the eight XCDs in turn
+// (work-group w to XCD w mod 8), and contiguous ranges of cells differ
+// widely in work (cells are numbered breadth first, and the upper levels'
+// rows are the longest), so the cells are cut into eight contiguous ranges
+// of about equal work (a row costs one pass of its wave per 64 entries,
+// plus one), range x going to XCD x: its rows keep their neighbourhood, and
+// with it the reuse of source multipoles in that XCD's L2.  Within a range
+// the rows go by decreasing length (ties in cell order), so that the long
+// rows start first.  *order (allocated here, freed by the caller with
+// hipFree) receives *n_order = 8 * (cells of the largest range) entries:
+// entry 8 j + x is the j-th cell of range x, or -1 past its end.
+// Synchronises the library's build stream (waiting for `stream` first).
+// Returns 0 or a hipError_t.
+int order_m2l_rows(const int64_t *ptr, int64_t n_cells, int32_t **order, int64_t *n_order,
+                   void *stream);
 
 // Children are the cells [c0, c1) of one level.
 int l2l(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *parent, const double *geo,
@@ -178,6 +206,9 @@ struct PlanLayouts {
 };
 struct DevicePlan {
   P2PItem *items = nullptr;
+  // Dispatch order of the items for a P2P launch over all of them (see
+  // order_p2p_items), or NULL.
+  int32_t *order = nullptr;
   int32_t *run_body = nullptr, *run_prefix = nullptr;
   int32_t *leaf_cell = nullptr, *leaf_pbase = nullptr, *leaf_nchunk = nullptr,
           *body_leaf = nullptr;
@@ -193,6 +224,19 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
                        const int32_t *body_begin, const int32_t *n_body, const int64_t *p2p_ptr,
                        const int32_t *p2p_col, const PlanLayouts &layouts, void *stream,
                        DevicePlan &out);
+
+// The dispatch order of plan.items for a P2P launch over all n_items of them
+// (replacing plan.order): the items by decreasing estimated cost (the wave's
+// VALU work: its staged batches, the steps over its lanes' targets, the
+// stream merge), ties in plan order.  The long items start first and the
+// short ones fill the end of the launch; and since work-groups go to the
+// eight XCDs in turn, every XCD gets an even share of the work (by this
+// estimate, the eight contiguous Morton ranges of items that xcd_remap gives
+// the XCDs differ in cost by up to 2.7x on a Plummer sphere of 10^6
+// bodies).  The items themselves, their partial-sum slots and every
+// result are unchanged.  Synchronises the library's build stream (waiting
+// for `stream` first).  Returns 0 or a hipError_t.
+int order_p2p_items(DevicePlan &plan, void *stream);
 
 // pos: device [n][3] FP64 (Morton order) -> out: device [n] double4 (fp64)
 // or float4 (rounded to nearest), (x, y, z, 0).

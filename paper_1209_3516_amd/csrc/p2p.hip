@@ -29,7 +29,8 @@ namespace {
 // Sources staged per batch.  With 384 the LDS of one wave (staged sources
 // and run table, about 9 KB) lets a CU hold the sixteen waves (four per
 // SIMD) that the FP32 charges kernel's registers allow.
-constexpr int kNB = 384;
+constexpr int kNB = kP2PStageBatch;
+static_assert(kNB % 64 == 0, "whole rows of 64 staged positions");
 
 // An LDS pointer in the LDS address space, as global_load_lds takes it.
 template <typename T>
@@ -333,6 +334,7 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
 // vec: per-body dipoles (kDipoles) or per-target vectors (kHessVec), Morton order.
 template <typename Real, int MODE, bool KAHAN, bool MASK_ALL, int MAXR>
 __device__ __forceinline__ void p2p_wave(const P2PItem *__restrict__ items,
+                                         const int32_t *__restrict__ order,
                                          const int32_t *__restrict__ run_body,
                                          const int32_t *__restrict__ run_prefix,
                                          const typename Vec<Real>::V4 *__restrict__ bodies,
@@ -344,8 +346,7 @@ __device__ __forceinline__ void p2p_wave(const P2PItem *__restrict__ items,
   __shared__ V4 srcd[MODE == kDipoles ? kNB + 64 : 1];
   __shared__ int32_t rb[kP2PMaxRuns];
   __shared__ int32_t rp[kP2PMaxRuns + 2];
-  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
-  const P2PItem it = items[w];
+  const P2PItem it = items[order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x)];
   static_assert(kP2PMaxTargetsPerLane <= MAXR && MAXR <= 8, "a case for every R of the plan");
   switch ((it.tgt_cfg >> 8) & 0xff) {
 #define FMM_P2P_CASE(RR)                                                                    \
@@ -373,14 +374,15 @@ __device__ __forceinline__ void p2p_wave(const P2PItem *__restrict__ items,
 // charges mode gives about 168 registers, i.e. three waves per SIMD.
 template <typename Real, int MODE, bool KAHAN, bool MASK_ALL>
 __global__ __launch_bounds__(64) void p2p_kernel(const P2PItem *__restrict__ items,
+                                                 const int32_t *__restrict__ order,
                                                  const int32_t *__restrict__ run_body,
                                                  const int32_t *__restrict__ run_prefix,
                                                  const typename Vec<Real>::V4 *__restrict__ bodies,
                                                  const typename Vec<Real>::V4 *__restrict__ vec,
                                                  typename Vec<Real>::V4 *__restrict__ out_s,
                                                  typename Vec<Real>::V4 *__restrict__ out_c) {
-  p2p_wave<Real, MODE, KAHAN, MASK_ALL, 8>(items, run_body, run_prefix, bodies, vec, out_s,
-                                           out_c);
+  p2p_wave<Real, MODE, KAHAN, MASK_ALL, 8>(items, order, run_body, run_prefix, bodies, vec,
+                                           out_s, out_c);
 }
 
 // The FP32 charges kernel held to four waves per SIMD (at most 128
@@ -392,16 +394,16 @@ __global__ __launch_bounds__(64) void p2p_kernel(const P2PItem *__restrict__ ite
 // evaluation takes the general kernel, whose finished waves make room.
 template <bool MASK_ALL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void p2p_kernel_w4(
-    const P2PItem *__restrict__ items, const int32_t *__restrict__ run_body,
-    const int32_t *__restrict__ run_prefix, const float4 *__restrict__ bodies,
-    float4 *__restrict__ out_s, float4 *__restrict__ out_c) {
+    const P2PItem *__restrict__ items, const int32_t *__restrict__ order,
+    const int32_t *__restrict__ run_body, const int32_t *__restrict__ run_prefix,
+    const float4 *__restrict__ bodies, float4 *__restrict__ out_s, float4 *__restrict__ out_c) {
   p2p_wave<float, kCharges, true, MASK_ALL, kP2PMaxTargetsPerLane>(
-      items, run_body, run_prefix, bodies, nullptr, out_s, out_c);
+      items, order, run_body, run_prefix, bodies, nullptr, out_s, out_c);
 }
 
 template <typename Real, int MODE>
 void launch_p2p(bool mask_all, bool four_waves, unsigned G, hipStream_t st, const P2PItem *items,
-                const int32_t *run_body, const int32_t *run_prefix, const void *bodies,
+                const int32_t *order, const int32_t *run_body, const int32_t *run_prefix, const void *bodies,
                 const void *vec, void *part_s, void *part_c) {
   using V4 = typename Vec<Real>::V4;
   constexpr bool kahan = std::is_same<Real, float>::value;
@@ -410,20 +412,20 @@ void launch_p2p(bool mask_all, bool four_waves, unsigned G, hipStream_t st, cons
   if constexpr (std::is_same<Real, float>::value && MODE == kCharges) {
     if (four_waves) {
       if (mask_all)
-        p2p_kernel_w4<true><<<G, 64, 0, st>>>(items, run_body, run_prefix, b, (V4 *)part_s,
-                                              (V4 *)part_c);
+        p2p_kernel_w4<true><<<G, 64, 0, st>>>(items, order, run_body, run_prefix, b,
+                                              (V4 *)part_s, (V4 *)part_c);
       else
-        p2p_kernel_w4<false><<<G, 64, 0, st>>>(items, run_body, run_prefix, b, (V4 *)part_s,
-                                               (V4 *)part_c);
+        p2p_kernel_w4<false><<<G, 64, 0, st>>>(items, order, run_body, run_prefix, b,
+                                               (V4 *)part_s, (V4 *)part_c);
       return;
     }
   }
   if (mask_all)
-    p2p_kernel<Real, MODE, kahan, true><<<G, 64, 0, st>>>(items, run_body, run_prefix, b, v,
-                                                          (V4 *)part_s, (V4 *)part_c);
+    p2p_kernel<Real, MODE, kahan, true><<<G, 64, 0, st>>>(items, order, run_body, run_prefix,
+                                                          b, v, (V4 *)part_s, (V4 *)part_c);
   else
-    p2p_kernel<Real, MODE, kahan, false><<<G, 64, 0, st>>>(items, run_body, run_prefix, b, v,
-                                                           (V4 *)part_s, (V4 *)part_c);
+    p2p_kernel<Real, MODE, kahan, false><<<G, 64, 0, st>>>(items, order, run_body, run_prefix,
+                                                           b, v, (V4 *)part_s, (V4 *)part_c);
 }
 
 // ----------------------------------------------------------------------------
@@ -668,16 +670,17 @@ __global__ __launch_bounds__(64) void p2p_mutual_kernel(
 }  // namespace
 
 int p2p(bool fp64, int mode, bool mask_all, bool four_waves, int64_t n_items,
-        const P2PItem *items, const int32_t *run_body, const int32_t *run_prefix,
-        const void *bodies, const void *vec, void *part_s, void *part_c, void *stream) {
+        const P2PItem *items, const int32_t *order, const int32_t *run_body,
+        const int32_t *run_prefix, const void *bodies, const void *vec, void *part_s,
+        void *part_c, void *stream) {
   if (n_items == 0) return 0;
   const unsigned G = (unsigned)n_items;
   const hipStream_t st = S_(stream);
   auto go = [&](auto real, auto mode_c) {
     using R = decltype(real);
     constexpr int M = decltype(mode_c)::value;
-    launch_p2p<R, M>(mask_all, four_waves, G, st, items, run_body, run_prefix, bodies, vec,
-                     part_s, std::is_same<R, float>::value ? part_c : nullptr);
+    launch_p2p<R, M>(mask_all, four_waves, G, st, items, order, run_body, run_prefix, bodies,
+                     vec, part_s, std::is_same<R, float>::value ? part_c : nullptr);
   };
   using IC = std::integral_constant<int, kCharges>;
   using ID = std::integral_constant<int, kDipoles>;

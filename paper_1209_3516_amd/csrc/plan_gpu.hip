@@ -7,6 +7,7 @@
 // leaf its offsets, a writing pass.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -350,8 +351,222 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
   return 0;
 }
 
+namespace {
+
+// Estimated VALU work of an item's wave, in units of 16 instructions (at
+// most 0xffff): each staged batch of nb sources takes ceil(nb / K) steps
+// over the R targets of a lane (about 14 instructions per target, 3 per
+// step) and about 90 for staging and the run lookup; the item adds the
+// log2(K) levels of its stream merge (16 R each) and about 200 for set-up
+// and stores.
+__device__ __forceinline__ uint32_t p2p_item_cost(const P2PItem &it) {
+  const int64_t R = (it.tgt_cfg >> 8) & 0xff, K = (it.tgt_cfg >> 24) & 0xff;
+  const int64_t nb = kP2PStageBatch;
+  auto phase = [&](int64_t n) -> int64_t {
+    if (n <= 0 || K <= 0) return 0;
+    const int64_t full = n / nb, part = n - full * nb;
+    const int64_t steps = full * ((nb + K - 1) / K) + (part + K - 1) / K;
+    return steps * (14 * R + 3) + 90 * (full + (part > 0 ? 1 : 0));
+  };
+  int64_t levels = 0;
+  for (int64_t k = 1; k < K; k <<= 1) ++levels;
+  const int64_t u = (phase(it.n_src) + phase(it.self_n) + 16 * R * levels + 200) >> 4;
+  return (uint32_t)(u < 0xffff ? u : 0xffff);
+}
+
+// Sort key of an item: its inverted cost, so that an ascending (stable) sort
+// puts the costly items first and keeps plan order among equal costs.
+__global__ __launch_bounds__(256) void p2p_order_keys(int64_t n, const P2PItem *__restrict__ items,
+                                                      uint32_t *__restrict__ keys,
+                                                      int32_t *__restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = 0xffffu - p2p_item_cost(items[i]);
+  vals[i] = (int32_t)i;
+}
+
+// Work of M2L row i in passes of its wave over 64 entries, plus one for the
+// row's set-up and its final sum over the lanes.
+struct M2LRowCost {
+  const int64_t *ptr;
+  __device__ int64_t operator()(int64_t i) const { return (ptr[i + 1] - ptr[i] + 63) / 64 + 1; }
+};
+
+// Keys of the balanced M2L order: the XCD range of row i (the eighth of the
+// total work that holds the middle of the row's work, from the exclusive
+// prefix sums of the work) above its inverted length; counts[x] = rows of
+// range x.
+__global__ __launch_bounds__(256) void m2l_order_keys(int64_t n, const int64_t *__restrict__ ptr,
+                                                      const int64_t *__restrict__ prefix,
+                                                      const int64_t *__restrict__ total,
+                                                      uint32_t *__restrict__ keys,
+                                                      int32_t *__restrict__ vals,
+                                                      int32_t *__restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t t = *total, c = M2LRowCost{ptr}(i);
+  int64_t x = t > 0 ? (8 * (2 * prefix[i] + c)) / (2 * t) : 0;
+  if (x > 7) x = 7;
+  const int64_t len = ptr[i + 1] - ptr[i];
+  keys[i] = ((uint32_t)x << 16) | (0xffffu - (uint32_t)(len < 0xffff ? len : 0xffff));
+  vals[i] = (int32_t)i;
+  atomicAdd(&counts[x], 1);
+}
+
+struct RangeStarts {
+  int32_t first[8];
+};
+
+// order[8 j + x] = the j-th row of range x (the rows sorted by key).
+__global__ __launch_bounds__(256) void m2l_order_scatter(int64_t n,
+                                                         const uint32_t *__restrict__ keys,
+                                                         const int32_t *__restrict__ vals,
+                                                         RangeStarts rs,
+                                                         int32_t *__restrict__ order) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int x = (int)(keys[k] >> 16);
+  order[8 * (k - rs.first[x]) + x] = vals[k];
+}
+
+__global__ __launch_bounds__(256) void fill_i32(int64_t n, int32_t v, int32_t *__restrict__ p) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+// *out (a new device array of n entries) = 0 .. n-1 stably sorted by the
+// 16-bit keys that make_keys(keys, vals, stream) writes beside them.
+template <class MakeKeys>
+int sorted_indices(int64_t n, MakeKeys make_keys, int32_t **out, void *stream) {
+  *out = nullptr;
+  if (n <= 0) return 0;
+  hipStream_t st;
+  if (int rc = build_stream(stream, reinterpret_cast<void **>(&st))) return rc;
+  uint32_t *keys = nullptr, *keys_alt = nullptr;
+  int32_t *vals = nullptr, *vals_alt = nullptr;
+  void *scratch = nullptr;
+  hipError_t e = hipSuccess;
+  auto ok = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+    return e == hipSuccess;
+  };
+  const size_t bytes = (size_t)n * 4;
+  bool in_alt = false;
+  if (ok(hipMallocAsync((void **)&keys, bytes, st)) &&
+      ok(hipMallocAsync((void **)&keys_alt, bytes, st)) &&
+      ok(hipMallocAsync((void **)&vals, bytes, st)) &&
+      ok(hipMallocAsync((void **)&vals_alt, bytes, st)) &&
+      ok(hipMallocAsync(&scratch, prims::radix_scratch_bytes(n), st))) {
+    make_keys(keys, vals, st);
+    if (ok(hipGetLastError()) &&
+        ok(prims::radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, n, 0, 16, scratch, st,
+                                       &in_alt)) &&
+        ok(hipMalloc((void **)out, bytes)))
+      ok(hipMemcpyAsync(*out, in_alt ? vals_alt : vals, bytes, hipMemcpyDeviceToDevice, st));
+  }
+  void *ps[] = {keys, keys_alt, vals, vals_alt, scratch};
+  for (void *q : ps)
+    if (q) (void)hipFreeAsync(q, st);
+  ok(hipStreamSynchronize(st));
+  if (e != hipSuccess && *out) {
+    (void)hipFree(*out);
+    *out = nullptr;
+  }
+  return (int)e;
+}
+
+}  // namespace
+
+int order_p2p_items(DevicePlan &plan, void *stream) {
+  if (plan.order) {
+    (void)hipFree(plan.order);
+    plan.order = nullptr;
+  }
+  const int64_t n = plan.n_items;
+  const P2PItem *items = plan.items;
+  return sorted_indices(
+      n,
+      [&](uint32_t *keys, int32_t *vals, hipStream_t st) {
+        p2p_order_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, items, keys, vals);
+      },
+      &plan.order, stream);
+}
+
+int order_m2l_rows(const int64_t *ptr, int64_t n_cells, int32_t **order, int64_t *n_order,
+                   void *stream) {
+  *order = nullptr;
+  *n_order = 0;
+  if (n_cells <= 0) return 0;
+  hipStream_t st;
+  if (int rc = build_stream(stream, reinterpret_cast<void **>(&st))) return rc;
+  const int64_t n = n_cells;
+  int64_t *prefix = nullptr, *total = nullptr;
+  uint32_t *keys = nullptr, *keys_alt = nullptr;
+  int32_t *vals = nullptr, *vals_alt = nullptr, *counts = nullptr;
+  void *scratch = nullptr;
+  hipError_t e = hipSuccess;
+  auto ok = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+    return e == hipSuccess;
+  };
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  const size_t sbytes = std::max(prims::radix_scratch_bytes(n), prims::scan_scratch_bytes<int64_t>(n));
+  int32_t host_counts[8] = {};
+  bool in_alt = false;
+  if (ok(hipMallocAsync((void **)&prefix, (size_t)n * 8, st)) &&
+      ok(hipMallocAsync((void **)&total, 8, st)) &&
+      ok(hipMallocAsync((void **)&keys, (size_t)n * 4, st)) &&
+      ok(hipMallocAsync((void **)&keys_alt, (size_t)n * 4, st)) &&
+      ok(hipMallocAsync((void **)&vals, (size_t)n * 4, st)) &&
+      ok(hipMallocAsync((void **)&vals_alt, (size_t)n * 4, st)) &&
+      ok(hipMallocAsync((void **)&counts, 8 * 4, st)) &&
+      ok(hipMallocAsync(&scratch, sbytes, st))) {
+    fill_i32<<<1, 256, 0, st>>>(8, 0, counts);
+    if (ok(hipGetLastError()) &&
+        ok(prims::exclusive_scan<int64_t>(n, M2LRowCost{ptr},
+                                          prims::StoreArray<int64_t, int64_t>{prefix},
+                                          (int64_t *)scratch, total, st))) {
+      m2l_order_keys<<<nb, 256, 0, st>>>(n, ptr, prefix, total, keys, vals, counts);
+      if (ok(hipGetLastError()) &&
+          ok(prims::radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, n, 0, 19, scratch, st,
+                                         &in_alt)) &&
+          ok(hipMemcpyAsync(host_counts, counts, sizeof(host_counts), hipMemcpyDeviceToHost,
+                            st)) &&
+          ok(hipStreamSynchronize(st))) {
+        RangeStarts rs;
+        int64_t first = 0, widest = 0;
+        for (int x = 0; x < 8; ++x) {
+          rs.first[x] = (int32_t)first;
+          first += host_counts[x];
+          widest = std::max<int64_t>(widest, host_counts[x]);
+        }
+        const int64_t m = 8 * widest;
+        if (ok(hipMalloc((void **)order, (size_t)m * 4))) {
+          fill_i32<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(m, -1, *order);
+          if (ok(hipGetLastError())) {
+            m2l_order_scatter<<<nb, 256, 0, st>>>(n, in_alt ? keys_alt : keys,
+                                                   in_alt ? vals_alt : vals, rs, *order);
+            if (ok(hipGetLastError())) *n_order = m;
+          }
+        }
+      }
+    }
+  }
+  void *ps[] = {prefix, total, keys, keys_alt, vals, vals_alt, counts, scratch};
+  for (void *q : ps)
+    if (q) (void)hipFreeAsync(q, st);
+  ok(hipStreamSynchronize(st));
+  if (e != hipSuccess) {
+    if (*order) (void)hipFree(*order);
+    *order = nullptr;
+    *n_order = 0;
+  }
+  return (int)e;
+}
+
 void DevicePlan::release() {
-  void *ps[] = {items, run_body, run_prefix, leaf_cell, leaf_pbase, leaf_nchunk, body_leaf};
+  void *ps[] = {items, order, run_body, run_prefix, leaf_cell, leaf_pbase, leaf_nchunk,
+                body_leaf};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   *this = DevicePlan();

@@ -64,7 +64,7 @@ EXPORTS = ("fmm_tree_build", "fmm_tree_build_ex", "fmm_tree_set_positions", "fmm
            "fmm_last_error", "fmm_num_terms", "fmm_copy_expansions", "fmm_term_exponents",
            "fmm_traverse_gpu", "fmm_tree_build_gpu", "fmm_evaluate_range",
            "fmm_partition_targets", "fmm_traverse_hybrid", "fmm_evaluate_noalloc",
-           "fmm_noalloc_scratch_bytes", "fmm_mutual_plan_stats")
+           "fmm_noalloc_scratch_bytes", "fmm_mutual_plan_stats", "fmm_dispatch_order")
 
 _lib = None
 
@@ -95,6 +95,7 @@ def lib():
                             ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
         "fmm_lists_stats": ([vp, ctypes.POINTER(_ListStats)], i32),
         "fmm_mutual_plan_stats": ([vp, vp, vp], i32),
+        "fmm_dispatch_order": ([vp, i32, vp, i64, ctypes.POINTER(i64)], i32),
         "fmm_lists_free": ([vp], None),
         "fmm_evaluate": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp], i32),
         "fmm_evaluate_noalloc": ([vp, vp, ctypes.POINTER(_EvalOpts), vp, vp, vp, vp], i32),
@@ -277,6 +278,17 @@ class Lists:
         _check(lib().fmm_mutual_plan_stats(self.tree._h, self._h, _np_ptr(out)))
         keys = ("items", "runs", "upper_pairs", "self_pairs", "source_slots")
         return dict(zip(keys, (int(v) for v in out)))
+
+    def dispatch_order(self, kind):
+        """The GPU dispatch order of a full evaluation's P2P work items
+        (kind FMM_P2P) or M2L cells (FMM_M2L, with -1 padding), as int32
+        (fmm_dispatch_order)."""
+        n = ctypes.c_int64()
+        _check(lib().fmm_dispatch_order(self._h, int(kind), None, 0, ctypes.byref(n)))
+        out = np.zeros(max(n.value, 1), dtype=np.int32)
+        _check(lib().fmm_dispatch_order(self._h, int(kind), _np_ptr(out), int(out.size),
+                                        ctypes.byref(n)))
+        return out[:n.value]
 
 
 def _opts(p, precision, flags=0, fp64_top_levels=-1):

@@ -197,7 +197,9 @@ def test_end_to_end_on_gpu_full_size():
 def test_target_ranges_reassemble_the_full_evaluation(kind, n, ncrit, theta, p, precision, G,
                                                       device):
     """Evaluating the G ranges of a partition, each writing only its targets,
-    gives the full evaluation bit for bit."""
+    gives the full evaluation bit for bit.  (The full evaluation dispatches
+    its P2P items and M2L rows in the lists' cost orders, a range in Morton
+    order: so the orders change no result either.)"""
     x = {"uniform": lambda: W.uniform_cube(n, seed=120), "plummer": lambda: W.plummer(n, seed=120),
          "dup": lambda: _points("dup")}[kind]()
     m = x.shape[0]

@@ -168,6 +168,11 @@ def test_invalid_arguments_are_rejected_without_gpu():
     assert L.fmm_mean_timings(lst._h, 0, (ctypes.c_double * 8)()) == fmm.FMM_EINVAL
     assert L.fmm_mean_timings(lst._h, 65, (ctypes.c_double * 8)()) == fmm.FMM_EINVAL
     assert L.fmm_copy_expansions(lst._h, 0, dummy) == fmm.FMM_ESTATE
+    # dispatch orders: host lists are not on a device yet; bad kind or len
+    n = ctypes.c_int64()
+    assert L.fmm_dispatch_order(lst._h, fmm.FMM_P2P, None, 0, ctypes.byref(n)) == fmm.FMM_ESTATE
+    assert L.fmm_dispatch_order(lst._h, 7, None, 0, ctypes.byref(n)) == fmm.FMM_EINVAL
+    assert L.fmm_dispatch_order(lst._h, fmm.FMM_M2L, None, 0, None) == fmm.FMM_EINVAL
     assert L.fmm_num_terms(0) == -1 and L.fmm_num_terms(4) == 20 and L.fmm_num_terms(8) == 120
 
 
