@@ -276,17 +276,19 @@ int fmm_mutual_plan_stats(const fmm_tree *t, const fmm_lists *l, int64_t *out);
  * The order in which an evaluation over all targets dispatches its P2P and
  * M2L work on the GPU (scheduling only: it changes no result, and the
  * method does not define it), copied to the host.  Work-groups go to the
- * GPU's eight XCDs in turn.
- *   kind FMM_P2P: the P2P work items (one per group of at most 64 targets of
- *     a leaf and chunk of its sources) by decreasing estimated cost, ties in
- *     plan order; *len = the number of work items, and out holds a
- *     permutation of 0 .. *len - 1 (work-group w takes item out[w]).
- *   kind FMM_M2L: the cells in eight contiguous ranges of about equal M2L
- *     work (a row costs one pass per 64 entries, plus one), range x for XCD
- *     x, each range's rows by decreasing length (ties in cell order);
- *     *len = 8 m, m the cells of the largest range, and out[8 j + x] is the
- *     j-th cell of range x or -1 past its end (work-group w takes cell
- *     out[w]; every cell occurs once).
+ * GPU's eight XCDs in turn (work-group w to XCD w mod 8).  Both orders cut
+ * their units, in plan order, into eight contiguous ranges of about equal
+ * work (range x: the units whose work midpoints fall in the x-th eighth of
+ * the total), range x for XCD x, and take each range by decreasing rank,
+ * ties in plan order; *len = 8 m, m the units of the largest range, and
+ * out[8 j + x] is the j-th unit of range x, or -1 past its end (work-group w
+ * takes unit out[w]; every unit occurs once).
+ *   kind FMM_P2P: the units are the P2P work items (one per group of at
+ *     most 64 targets of a leaf and chunk of its sources); work and rank
+ *     are both the item's estimated cost (its staged source batches, the
+ *     steps over each lane's targets, the merge of its source streams).
+ *   kind FMM_M2L: the units are the cells; a row's work is one pass per 64
+ *     entries, plus one, and its rank is its length.
  * The lists must be on the device (after fmm_traverse_gpu or a first
  * evaluation; FMM_ESTATE otherwise).  out: caller-owned int32[cap], or NULL
  * to get *len only; FMM_EINVAL for another kind, a NULL len, or cap < *len.

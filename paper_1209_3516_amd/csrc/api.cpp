@@ -764,7 +764,8 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
                              dv.part_m, ns));
   } else if (!ranged) {
     LAUNCH_TRY(D::p2p(fp64, mode, mask_all, p2p_four_waves, pl.n_items, pl.items, pl.order,
-                      pl.run_body, pl.run_prefix, bodies, vec, sc.part_s, sc.part_c, ns));
+                      pl.order_len, pl.run_body, pl.run_prefix, bodies, vec, sc.part_s,
+                      sc.part_c, ns));
   } else {
     // the items of the range's leaves: one contiguous run per level
     for (int lev = 0; lev <= max_level; ++lev) {
@@ -772,8 +773,8 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
       const int64_t i1 = dv.leaf_item_host[rcells.leaf_hi[lev]];
       if (i1 > i0)
         LAUNCH_TRY(D::p2p(fp64, mode, mask_all, p2p_four_waves, i1 - i0, pl.items + i0,
-                          nullptr, pl.run_body, pl.run_prefix, bodies, vec, sc.part_s, sc.part_c,
-                          ns));
+                          nullptr, 0, pl.run_body, pl.run_prefix, bodies, vec, sc.part_s,
+                          sc.part_c, ns));
     }
   }
   if (int rc = mark(9, ns)) return rc;
@@ -1378,7 +1379,7 @@ int fmm_dispatch_order(const fmm_lists *l, int kind, int32_t *out, int64_t cap, 
     return FMM_ESTATE;
   }
   const int32_t *src = kind == FMM_P2P ? dv.plan.order : dv.m2l_order;
-  const int64_t n = !src ? 0 : kind == FMM_P2P ? dv.plan.n_items : dv.m2l_order_len;
+  const int64_t n = !src ? 0 : kind == FMM_P2P ? dv.plan.order_len : dv.m2l_order_len;
   *len = n;
   if (!out) return FMM_OK;
   if (cap < n) {

@@ -33,12 +33,13 @@ enum EvalMode { kCharges = 0, kDipoles = 1, kHessVec = 2 };
 // four_waves: in FP32 charges mode, the kernel held to four waves per SIMD
 // (else the general one, three waves); the caller picks it by whether the
 // far field's M2L waves, running beside P2P, fit in what its waves leave.
-// order: NULL (work-group w of the launch takes item xcd_remap(w), so that
-// each XCD works on a contiguous range of the Morton-ordered items), or a
-// permutation of the n_items items (work-group w takes item order[w]), such
-// as DevicePlan::order for a launch over all items of a plan.
+// order: NULL (n_items work-groups; work-group w takes item xcd_remap(w), so
+// that each XCD works on an equal-count contiguous range of the
+// Morton-ordered items), or the n_order entries of an order_p2p_items order
+// of the n_items items (n_order work-groups; work-group w takes item
+// order[w], none if it is -1).
 int p2p(bool fp64, int mode, bool mask_all, bool four_waves, int64_t n_items,
-        const P2PItem *items, const int32_t *order, const int32_t *run_body,
+        const P2PItem *items, const int32_t *order, int64_t n_order, const int32_t *run_body,
         const int32_t *run_prefix, const void *bodies, const void *vec, void *part_s,
         void *part_c, void *stream);
 
@@ -207,8 +208,9 @@ struct PlanLayouts {
 struct DevicePlan {
   P2PItem *items = nullptr;
   // Dispatch order of the items for a P2P launch over all of them (see
-  // order_p2p_items), or NULL.
+  // order_p2p_items; order_len entries), or NULL.
   int32_t *order = nullptr;
+  int64_t order_len = 0;
   int32_t *run_body = nullptr, *run_prefix = nullptr;
   int32_t *leaf_cell = nullptr, *leaf_pbase = nullptr, *leaf_nchunk = nullptr,
           *body_leaf = nullptr;
@@ -226,16 +228,18 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
                        DevicePlan &out);
 
 // The dispatch order of plan.items for a P2P launch over all n_items of them
-// (replacing plan.order): the items by decreasing estimated cost (the wave's
-// VALU work: its staged batches, the steps over its lanes' targets, the
-// stream merge), ties in plan order.  The long items start first and the
-// short ones fill the end of the launch; and since work-groups go to the
-// eight XCDs in turn, every XCD gets an even share of the work (by this
-// estimate, the eight contiguous Morton ranges of items that xcd_remap gives
-// the XCDs differ in cost by up to 2.7x on a Plummer sphere of 10^6
-// bodies).  The items themselves, their partial-sum slots and every
-// result are unchanged.  Synchronises the library's build stream (waiting
-// for `stream` first).  Returns 0 or a hipError_t.
+// (replacing plan.order and plan.order_len), built as order_m2l_rows builds
+// the M2L order, with an item's estimated cost (the wave's VALU work: its
+// staged batches, the steps over its lanes' targets, the stream merge) as
+// both its work and its rank: eight contiguous (Morton) ranges of items of
+// about equal cost, one per XCD, so that each XCD's L2 keeps serving the
+// neighbouring sources its items share, each range's items by decreasing
+// cost, so that the long ones start first and the short ones fill the end
+// of the launch.  (By this estimate the equal-count ranges that xcd_remap
+// gives the XCDs differ in cost by up to 2.7x on a Plummer sphere of 10^6
+// bodies.)  The items themselves, their partial-sum slots and every result
+// are unchanged.  Synchronises the library's build stream (waiting for
+// `stream` first).  Returns 0 or a hipError_t.
 int order_p2p_items(DevicePlan &plan, void *stream);
 
 // pos: device [n][3] FP64 (Morton order) -> out: device [n] double4 (fp64)

@@ -346,7 +346,9 @@ __device__ __forceinline__ void p2p_wave(const P2PItem *__restrict__ items,
   __shared__ V4 srcd[MODE == kDipoles ? kNB + 64 : 1];
   __shared__ int32_t rb[kP2PMaxRuns];
   __shared__ int32_t rp[kP2PMaxRuns + 2];
-  const P2PItem it = items[order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x)];
+  const int64_t w = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
+  if (w < 0) return;  // padding of an ordered launch
+  const P2PItem it = items[w];
   static_assert(kP2PMaxTargetsPerLane <= MAXR && MAXR <= 8, "a case for every R of the plan");
   switch ((it.tgt_cfg >> 8) & 0xff) {
 #define FMM_P2P_CASE(RR)                                                                    \
@@ -670,11 +672,11 @@ __global__ __launch_bounds__(64) void p2p_mutual_kernel(
 }  // namespace
 
 int p2p(bool fp64, int mode, bool mask_all, bool four_waves, int64_t n_items,
-        const P2PItem *items, const int32_t *order, const int32_t *run_body,
+        const P2PItem *items, const int32_t *order, int64_t n_order, const int32_t *run_body,
         const int32_t *run_prefix, const void *bodies, const void *vec, void *part_s,
         void *part_c, void *stream) {
   if (n_items == 0) return 0;
-  const unsigned G = (unsigned)n_items;
+  const unsigned G = (unsigned)(order ? n_order : n_items);
   const hipStream_t st = S_(stream);
   auto go = [&](auto real, auto mode_c) {
     using R = decltype(real);

@@ -353,12 +353,16 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
 
 namespace {
 
-// Estimated VALU work of an item's wave, in units of 16 instructions (at
+// Estimated work of an item's wave, in units of 16 VALU instructions (at
 // most 0xffff): each staged batch of nb sources takes ceil(nb / K) steps
 // over the R targets of a lane (about 14 instructions per target, 3 per
 // step) and about 90 for staging and the run lookup; the item adds the
-// log2(K) levels of its stream merge (16 R each) and about 200 for set-up
-// and stores.
+// log2(K) levels of its stream merge (16 R each) and a fixed 2500 for its
+// set-up, the latency of its first loads and its stores.  The fixed part is
+// measured, not counted: with 200 the XCD ranges full of small items (the
+// outskirts of a Plummer sphere) ran well past their estimate, and P2P on
+// a Plummer sphere of 10^6 bodies took 1.74 ms against 1.56, 1.49 and
+// 1.45 ms with 800, 1500 and 2500 (the uniform cube: 1.76-1.77 ms for all).
 __device__ __forceinline__ uint32_t p2p_item_cost(const P2PItem &it) {
   const int64_t R = (it.tgt_cfg >> 8) & 0xff, K = (it.tgt_cfg >> 24) & 0xff;
   const int64_t nb = kP2PStageBatch;
@@ -370,45 +374,46 @@ __device__ __forceinline__ uint32_t p2p_item_cost(const P2PItem &it) {
   };
   int64_t levels = 0;
   for (int64_t k = 1; k < K; k <<= 1) ++levels;
-  const int64_t u = (phase(it.n_src) + phase(it.self_n) + 16 * R * levels + 200) >> 4;
+  const int64_t u = (phase(it.n_src) + phase(it.self_n) + 16 * R * levels + 2500) >> 4;
   return (uint32_t)(u < 0xffff ? u : 0xffff);
 }
 
-// Sort key of an item: its inverted cost, so that an ascending (stable) sort
-// puts the costly items first and keeps plan order among equal costs.
-__global__ __launch_bounds__(256) void p2p_order_keys(int64_t n, const P2PItem *__restrict__ items,
-                                                      uint32_t *__restrict__ keys,
-                                                      int32_t *__restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  keys[i] = 0xffffu - p2p_item_cost(items[i]);
-  vals[i] = (int32_t)i;
-}
-
-// Work of M2L row i in passes of its wave over 64 entries, plus one for the
-// row's set-up and its final sum over the lanes.
-struct M2LRowCost {
-  const int64_t *ptr;
-  __device__ int64_t operator()(int64_t i) const { return (ptr[i + 1] - ptr[i] + 63) / 64 + 1; }
+// The work of unit i, which balances the XCD ranges, and its rank within a
+// range (at most 0xffff; higher ranks start first).  A P2P item: its
+// estimated cost, both.
+struct P2PItemWork {
+  const P2PItem *items;
+  __device__ int64_t operator()(int64_t i) const { return p2p_item_cost(items[i]); }
+  __device__ uint32_t rank(int64_t i) const { return p2p_item_cost(items[i]); }
 };
 
-// Keys of the balanced M2L order: the XCD range of row i (the eighth of the
-// total work that holds the middle of the row's work, from the exclusive
-// prefix sums of the work) above its inverted length; counts[x] = rows of
-// range x.
-__global__ __launch_bounds__(256) void m2l_order_keys(int64_t n, const int64_t *__restrict__ ptr,
-                                                      const int64_t *__restrict__ prefix,
-                                                      const int64_t *__restrict__ total,
-                                                      uint32_t *__restrict__ keys,
-                                                      int32_t *__restrict__ vals,
-                                                      int32_t *__restrict__ counts) {
+// An M2L row: one pass of its wave per 64 entries plus one for the row's
+// set-up and final sum over the lanes; ranked by its length.
+struct M2LRowWork {
+  const int64_t *ptr;
+  __device__ int64_t operator()(int64_t i) const { return (ptr[i + 1] - ptr[i] + 63) / 64 + 1; }
+  __device__ uint32_t rank(int64_t i) const {
+    const int64_t len = ptr[i + 1] - ptr[i];
+    return (uint32_t)(len < 0xffff ? len : 0xffff);
+  }
+};
+
+// Keys of a balanced order: the XCD range of unit i (the eighth of the total
+// work that holds the middle of the unit's work, from the exclusive prefix
+// sums of the work) above its inverted rank; counts[x] = units of range x.
+template <class Work>
+__global__ __launch_bounds__(256) void balanced_order_keys(int64_t n, Work w,
+                                                           const int64_t *__restrict__ prefix,
+                                                           const int64_t *__restrict__ total,
+                                                           uint32_t *__restrict__ keys,
+                                                           int32_t *__restrict__ vals,
+                                                           int32_t *__restrict__ counts) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t t = *total, c = M2LRowCost{ptr}(i);
+  const int64_t t = *total, c = w(i);
   int64_t x = t > 0 ? (8 * (2 * prefix[i] + c)) / (2 * t) : 0;
   if (x > 7) x = 7;
-  const int64_t len = ptr[i + 1] - ptr[i];
-  keys[i] = ((uint32_t)x << 16) | (0xffffu - (uint32_t)(len < 0xffff ? len : 0xffff));
+  keys[i] = ((uint32_t)x << 16) | (0xffffu - w.rank(i));
   vals[i] = (int32_t)i;
   atomicAdd(&counts[x], 1);
 }
@@ -417,12 +422,12 @@ struct RangeStarts {
   int32_t first[8];
 };
 
-// order[8 j + x] = the j-th row of range x (the rows sorted by key).
-__global__ __launch_bounds__(256) void m2l_order_scatter(int64_t n,
-                                                         const uint32_t *__restrict__ keys,
-                                                         const int32_t *__restrict__ vals,
-                                                         RangeStarts rs,
-                                                         int32_t *__restrict__ order) {
+// order[8 j + x] = the j-th unit of range x (the units sorted by key).
+__global__ __launch_bounds__(256) void balanced_order_scatter(int64_t n,
+                                                              const uint32_t *__restrict__ keys,
+                                                              const int32_t *__restrict__ vals,
+                                                              RangeStarts rs,
+                                                              int32_t *__restrict__ order) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int x = (int)(keys[k] >> 16);
@@ -434,72 +439,17 @@ __global__ __launch_bounds__(256) void fill_i32(int64_t n, int32_t v, int32_t *_
   if (k < n) p[k] = v;
 }
 
-// *out (a new device array of n entries) = 0 .. n-1 stably sorted by the
-// 16-bit keys that make_keys(keys, vals, stream) writes beside them.
-template <class MakeKeys>
-int sorted_indices(int64_t n, MakeKeys make_keys, int32_t **out, void *stream) {
-  *out = nullptr;
+// The XCD-balanced dispatch order of n units (see order_m2l_rows in
+// kernels.h): eight contiguous ranges of about equal work, range x for XCD
+// x, each by decreasing rank (ties in unit order), interleaved as
+// order[8 j + x] with -1 past a range's end.
+template <class Work>
+int xcd_balanced_order(int64_t n, Work w, int32_t **order, int64_t *n_order, void *stream) {
+  *order = nullptr;
+  *n_order = 0;
   if (n <= 0) return 0;
   hipStream_t st;
   if (int rc = build_stream(stream, reinterpret_cast<void **>(&st))) return rc;
-  uint32_t *keys = nullptr, *keys_alt = nullptr;
-  int32_t *vals = nullptr, *vals_alt = nullptr;
-  void *scratch = nullptr;
-  hipError_t e = hipSuccess;
-  auto ok = [&](hipError_t r) {
-    if (e == hipSuccess) e = r;
-    return e == hipSuccess;
-  };
-  const size_t bytes = (size_t)n * 4;
-  bool in_alt = false;
-  if (ok(hipMallocAsync((void **)&keys, bytes, st)) &&
-      ok(hipMallocAsync((void **)&keys_alt, bytes, st)) &&
-      ok(hipMallocAsync((void **)&vals, bytes, st)) &&
-      ok(hipMallocAsync((void **)&vals_alt, bytes, st)) &&
-      ok(hipMallocAsync(&scratch, prims::radix_scratch_bytes(n), st))) {
-    make_keys(keys, vals, st);
-    if (ok(hipGetLastError()) &&
-        ok(prims::radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, n, 0, 16, scratch, st,
-                                       &in_alt)) &&
-        ok(hipMalloc((void **)out, bytes)))
-      ok(hipMemcpyAsync(*out, in_alt ? vals_alt : vals, bytes, hipMemcpyDeviceToDevice, st));
-  }
-  void *ps[] = {keys, keys_alt, vals, vals_alt, scratch};
-  for (void *q : ps)
-    if (q) (void)hipFreeAsync(q, st);
-  ok(hipStreamSynchronize(st));
-  if (e != hipSuccess && *out) {
-    (void)hipFree(*out);
-    *out = nullptr;
-  }
-  return (int)e;
-}
-
-}  // namespace
-
-int order_p2p_items(DevicePlan &plan, void *stream) {
-  if (plan.order) {
-    (void)hipFree(plan.order);
-    plan.order = nullptr;
-  }
-  const int64_t n = plan.n_items;
-  const P2PItem *items = plan.items;
-  return sorted_indices(
-      n,
-      [&](uint32_t *keys, int32_t *vals, hipStream_t st) {
-        p2p_order_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, items, keys, vals);
-      },
-      &plan.order, stream);
-}
-
-int order_m2l_rows(const int64_t *ptr, int64_t n_cells, int32_t **order, int64_t *n_order,
-                   void *stream) {
-  *order = nullptr;
-  *n_order = 0;
-  if (n_cells <= 0) return 0;
-  hipStream_t st;
-  if (int rc = build_stream(stream, reinterpret_cast<void **>(&st))) return rc;
-  const int64_t n = n_cells;
   int64_t *prefix = nullptr, *total = nullptr;
   uint32_t *keys = nullptr, *keys_alt = nullptr;
   int32_t *vals = nullptr, *vals_alt = nullptr, *counts = nullptr;
@@ -510,7 +460,8 @@ int order_m2l_rows(const int64_t *ptr, int64_t n_cells, int32_t **order, int64_t
     return e == hipSuccess;
   };
   const unsigned nb = (unsigned)((n + 255) / 256);
-  const size_t sbytes = std::max(prims::radix_scratch_bytes(n), prims::scan_scratch_bytes<int64_t>(n));
+  const size_t sbytes =
+      std::max(prims::radix_scratch_bytes(n), prims::scan_scratch_bytes<int64_t>(n));
   int32_t host_counts[8] = {};
   bool in_alt = false;
   if (ok(hipMallocAsync((void **)&prefix, (size_t)n * 8, st)) &&
@@ -523,10 +474,9 @@ int order_m2l_rows(const int64_t *ptr, int64_t n_cells, int32_t **order, int64_t
       ok(hipMallocAsync(&scratch, sbytes, st))) {
     fill_i32<<<1, 256, 0, st>>>(8, 0, counts);
     if (ok(hipGetLastError()) &&
-        ok(prims::exclusive_scan<int64_t>(n, M2LRowCost{ptr},
-                                          prims::StoreArray<int64_t, int64_t>{prefix},
+        ok(prims::exclusive_scan<int64_t>(n, w, prims::StoreArray<int64_t, int64_t>{prefix},
                                           (int64_t *)scratch, total, st))) {
-      m2l_order_keys<<<nb, 256, 0, st>>>(n, ptr, prefix, total, keys, vals, counts);
+      balanced_order_keys<<<nb, 256, 0, st>>>(n, w, prefix, total, keys, vals, counts);
       if (ok(hipGetLastError()) &&
           ok(prims::radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, n, 0, 19, scratch, st,
                                          &in_alt)) &&
@@ -544,8 +494,8 @@ int order_m2l_rows(const int64_t *ptr, int64_t n_cells, int32_t **order, int64_t
         if (ok(hipMalloc((void **)order, (size_t)m * 4))) {
           fill_i32<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(m, -1, *order);
           if (ok(hipGetLastError())) {
-            m2l_order_scatter<<<nb, 256, 0, st>>>(n, in_alt ? keys_alt : keys,
-                                                   in_alt ? vals_alt : vals, rs, *order);
+            balanced_order_scatter<<<nb, 256, 0, st>>>(n, in_alt ? keys_alt : keys,
+                                                        in_alt ? vals_alt : vals, rs, *order);
             if (ok(hipGetLastError())) *n_order = m;
           }
         }
@@ -562,6 +512,21 @@ int order_m2l_rows(const int64_t *ptr, int64_t n_cells, int32_t **order, int64_t
     *n_order = 0;
   }
   return (int)e;
+}
+
+}  // namespace
+
+int order_p2p_items(DevicePlan &plan, void *stream) {
+  if (plan.order) (void)hipFree(plan.order);
+  plan.order = nullptr;
+  plan.order_len = 0;
+  return xcd_balanced_order(plan.n_items, P2PItemWork{plan.items}, &plan.order, &plan.order_len,
+                            stream);
+}
+
+int order_m2l_rows(const int64_t *ptr, int64_t n_cells, int32_t **order, int64_t *n_order,
+                   void *stream) {
+  return xcd_balanced_order(n_cells, M2LRowWork{ptr}, order, n_order, stream);
 }
 
 void DevicePlan::release() {

@@ -1,12 +1,13 @@
 """GPU dispatch orders of a full evaluation (fmm_dispatch_order), read back
-from the device and checked against their definitions, recomputed here from
-the lists:
+from the device and checked against their definitions:
 
-* P2P: a permutation of the work items;
-* M2L: entry 8 j + x is the j-th cell of XCD range x or -1 past its end; the
-  ranges are the contiguous runs of cells whose work midpoints fall in the
-  x-th eighth of the total work (a row costs ceil(length / 64) + 1), every
-  cell occurs once, and a range's rows go by decreasing length, ties by cell;
+* both orders: entry 8 j + x is the j-th unit of XCD range x or -1 past its
+  end; every unit (P2P work item, M2L cell) occurs once; the eight ranges
+  are contiguous runs of units, in order;
+* M2L, recomputed here from the lists: range x holds the cells whose work
+  midpoints fall in the x-th eighth of the total work (a row costs
+  ceil(length / 64) + 1), and a range's rows go by decreasing length, ties
+  by cell;
 * host-built lists (ordered at their upload) and device-built lists give
   the same orders.
 Whether the orders leave results unchanged is checked elsewhere: the target
@@ -32,32 +33,40 @@ def expected_m2l_ranges(ptr):
     return np.minimum(7, (8 * (2 * pre + c)) // (2 * tot)), ln
 
 
-def check_orders(t, lst):
-    n_items = lst.stats()["p2p_work_items"]
-    po = lst.dispatch_order(fmm.FMM_P2P)
-    assert po.size == n_items
-    assert np.array_equal(np.sort(po), np.arange(n_items))
-
-    ptr, _ = lst.csr(fmm.FMM_M2L)
-    n_cells = ptr.size - 1
-    mo = lst.dispatch_order(fmm.FMM_M2L)
-    assert mo.size % 8 == 0
-    valid = mo[mo >= 0]
-    assert np.array_equal(np.sort(valid), np.arange(n_cells))
-    xr, ln = expected_m2l_ranges(ptr)
-    widest = 0
+def check_ranges(order, n_units):
+    """The common structure; returns the units of each range."""
+    assert order.size % 8 == 0
+    valid = order[order >= 0]
+    assert np.array_equal(np.sort(valid), np.arange(n_units))
+    ranges, widest, last = [], 0, -1
     for x in range(8):
-        col = mo[x::8]
+        col = order[x::8]
         k = int(np.sum(col >= 0))
         widest = max(widest, k)
         assert np.all(col[:k] >= 0) and np.all(col[k:] == -1)
-        cells = col[:k]
+        units = np.sort(col[:k])
+        if k:
+            assert units[-1] - units[0] == k - 1  # contiguous
+            assert units[0] == last + 1           # ranges in order
+            last = units[-1]
+        ranges.append(col[:k])
+    assert order.size == 8 * widest
+    return ranges
+
+
+def check_orders(t, lst):
+    po = lst.dispatch_order(fmm.FMM_P2P)
+    check_ranges(po, lst.stats()["p2p_work_items"])
+
+    ptr, _ = lst.csr(fmm.FMM_M2L)
+    mo = lst.dispatch_order(fmm.FMM_M2L)
+    ranges = check_ranges(mo, ptr.size - 1)
+    xr, ln = expected_m2l_ranges(ptr)
+    for x, cells in enumerate(ranges):
         # exactly the cells the rule assigns to range x
         assert np.array_equal(np.sort(cells), np.flatnonzero(xr == x))
         # by decreasing length, ties by cell index
-        key = np.lexsort((cells, -ln[cells]))
-        assert np.array_equal(key, np.arange(k))
-    assert mo.size == 8 * widest
+        assert np.array_equal(np.lexsort((cells, -ln[cells])), np.arange(cells.size))
     return po, mo
 
 
