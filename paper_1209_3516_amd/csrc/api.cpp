@@ -354,10 +354,6 @@ int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
   dp.release();
   if (int rc = dev_upload(&dv.m2l_ptr, ld.m2l_ptr.data(), ld.m2l_ptr.size())) return rc;
   if (int rc = dev_upload(&dv.m2l_col, ld.m2l_col.data(), ld.m2l_col.size())) return rc;
-  if (dv.m2l_order) (void)hipFree(dv.m2l_order);
-  if (int rc = fmmlib::dev::order_m2l_rows(dv.m2l_ptr, ld.n_rows, &dv.m2l_order,
-                                           &dv.m2l_order_len, nullptr))
-    return hip_fail((hipError_t)rc, "order_m2l_rows");
   if (!ld.m2p_col.empty()) {
     std::vector<int32_t> rows;
     for (int64_t c = 0; c < ld.n_rows; ++c)
@@ -381,8 +377,9 @@ int ensure_lists_device(fmm_tree *t, fmm_lists *l) {
   dp.n_partials = pl.n_partials;
   dp.max_row_sources = pl.max_row_sources;
   dp.p2p_pairs = ld.p2p_pairs;
-  if (int rc = fmmlib::dev::order_p2p_items(dp, nullptr))
-    return hip_fail((hipError_t)rc, "order_p2p_items");
+  if (int rc = fmmlib::dev::dispatch_orders(dp, dv.m2l_ptr, ld.n_rows, &dv.m2l_order,
+                                            &dv.m2l_order_len, nullptr))
+    return hip_fail((hipError_t)rc, "dispatch_orders");
   dv.leaf_nchunk_host = pl.leaf_nchunk;
   dv.device = t->dev.device;
   dv.uploaded = true;
@@ -1271,14 +1268,11 @@ int fmm_traverse_gpu(const fmm_tree *t, double theta, unsigned flags, fmm_lists 
         fmm_lists_free(l);
         return hip_fail((hipError_t)rc, "build_p2p_plan_gpu");
       }
-      if (const int rc2 = fmmlib::dev::order_p2p_items(dv.plan, stream)) {
+      if (const int rc2 = fmmlib::dev::dispatch_orders(dv.plan, dv.m2l_ptr, td.n_cells(),
+                                                       &dv.m2l_order, &dv.m2l_order_len,
+                                                       stream)) {
         fmm_lists_free(l);
-        return hip_fail((hipError_t)rc2, "order_p2p_items");
-      }
-      if (const int rc2 = fmmlib::dev::order_m2l_rows(dv.m2l_ptr, td.n_cells(), &dv.m2l_order,
-                                                      &dv.m2l_order_len, stream)) {
-        fmm_lists_free(l);
-        return hip_fail((hipError_t)rc2, "order_m2l_rows");
+        return hip_fail((hipError_t)rc2, "dispatch_orders");
       }
       if (std::getenv("FMM_LOG"))
         std::fprintf(stderr, "[fmm] device work plan: %.2f ms (%lld items, %lld runs)\n",

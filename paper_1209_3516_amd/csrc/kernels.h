@@ -35,7 +35,7 @@ enum EvalMode { kCharges = 0, kDipoles = 1, kHessVec = 2 };
 // far field's M2L waves, running beside P2P, fit in what its waves leave.
 // order: NULL (n_items work-groups; work-group w takes item xcd_remap(w), so
 // that each XCD works on an equal-count contiguous range of the
-// Morton-ordered items), or the n_order entries of an order_p2p_items order
+// Morton-ordered items), or the n_order entries of the dispatch_orders order
 // of the n_items items (n_order work-groups; work-group w takes item
 // order[w], none if it is -1).
 int p2p(bool fp64, int mode, bool mask_all, bool four_waves, int64_t n_items,
@@ -90,28 +90,13 @@ int m2l_mfma(int p, int64_t tile0, int64_t tile1, const int32_t *tile_cells,
 // Target cells [r0, r1) from the folded multipoles Mr; acc_fp64: the row
 // accumulates in FP64 into L64, else into L (FP32 in mixed mode).
 // order: NULL (r1 - r0 work-groups; work-group w takes cell r0 + xcd_remap(w)),
-// or the n_order entries of an order_m2l_rows order of the cells [r0, r1)
+// or the n_order entries of a dispatch_orders M2L order of the cells [r0, r1)
 // (n_order work-groups; work-group w takes cell order[w], none if it is -1).
 int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
         const int32_t *col, const double *geo, const void *Mr, void *L, double *L64,
         bool acc_fp64, const int32_t *order, int64_t n_order, void *stream);
 
-// Dispatch order of the M2L rows of n_cells cells (CSR row pointers ptr) for
-// a launch over all of them.  Work-groups go to the eight XCDs in turn
-// (work-group w to XCD w mod 8), and contiguous ranges of cells differ
-// widely in work (cells are numbered breadth first, and the upper levels'
-// rows are the longest), so the cells are cut into eight contiguous ranges
-// of about equal work (a row costs one pass of its wave per 64 entries,
-// plus one), range x going to XCD x: its rows keep their neighbourhood, and
-// with it the reuse of source multipoles in that XCD's L2.  Within a range
-// the rows go by decreasing length (ties in cell order), so that the long
-// rows start first.  *order (allocated here, freed by the caller with
-// hipFree) receives *n_order = 8 * (cells of the largest range) entries:
-// entry 8 j + x is the j-th cell of range x, or -1 past its end.
-// Synchronises the library's build stream (waiting for `stream` first).
-// Returns 0 or a hipError_t.
-int order_m2l_rows(const int64_t *ptr, int64_t n_cells, int32_t **order, int64_t *n_order,
-                   void *stream);
+// (dispatch_orders, declared with DevicePlan below, builds the orders.)
 
 // Children are the cells [c0, c1) of one level.
 int l2l(int p, bool fp64, int64_t c0, int64_t c1, const int32_t *parent, const double *geo,
@@ -208,7 +193,7 @@ struct PlanLayouts {
 struct DevicePlan {
   P2PItem *items = nullptr;
   // Dispatch order of the items for a P2P launch over all of them (see
-  // order_p2p_items; order_len entries), or NULL.
+  // dispatch_orders; order_len entries), or NULL.
   int32_t *order = nullptr;
   int64_t order_len = 0;
   int32_t *run_body = nullptr, *run_prefix = nullptr;
@@ -227,20 +212,32 @@ int build_p2p_plan_gpu(int64_t n, int64_t n_cells, int64_t n_leaves, const int32
                        const int32_t *p2p_col, const PlanLayouts &layouts, void *stream,
                        DevicePlan &out);
 
-// The dispatch order of plan.items for a P2P launch over all n_items of them
-// (replacing plan.order and plan.order_len), built as order_m2l_rows builds
-// the M2L order, with an item's estimated cost (the wave's VALU work: its
-// staged batches, the steps over its lanes' targets, the stream merge) as
-// both its work and its rank: eight contiguous (Morton) ranges of items of
-// about equal cost, one per XCD, so that each XCD's L2 keeps serving the
-// neighbouring sources its items share, each range's items by decreasing
-// cost, so that the long ones start first and the short ones fill the end
-// of the launch.  (By this estimate the equal-count ranges that xcd_remap
-// gives the XCDs differ in cost by up to 2.7x on a Plummer sphere of 10^6
-// bodies.)  The items themselves, their partial-sum slots and every result
-// are unchanged.  Synchronises the library's build stream (waiting for
-// `stream` first).  Returns 0 or a hipError_t.
-int order_p2p_items(DevicePlan &plan, void *stream);
+// The dispatch orders of a launch over all of the plan's P2P items and of
+// one over all n_cells M2L rows (CSR row pointers m2l_ptr), replacing
+// plan.order / plan.order_len and *m2l_order / *m2l_len (device arrays the
+// caller frees with hipFree).  Work-groups go to the eight XCDs in turn
+// (work-group w to XCD w mod 8), and contiguous ranges of units differ
+// widely in work, so each order cuts its units, in plan order, into eight
+// contiguous ranges of about equal estimated work, range x going to XCD x:
+// its units keep their neighbourhood, and with it the reuse of sources
+// (bodies, multipoles) in that XCD's L2.  Within a range the units go by
+// decreasing rank (ties in plan order), so that the long ones start first
+// and the short ones fill the end of the launch.  The order has 8 m
+// entries, m the units of the largest range: entry 8 j + x is the j-th unit
+// of range x, or -1 past its end.
+//   P2P item: work and rank are its estimated cost (the wave's VALU work:
+//     its staged batches, the steps over its lanes' targets, the stream
+//     merge, and a fixed part).  (By this estimate the equal-count ranges
+//     that xcd_remap gives the XCDs differ in cost by up to 2.7x on a
+//     Plummer sphere of 10^6 bodies.)
+//   M2L row: its work is one pass per 64 entries plus one; its rank, its
+//     length.  (Cells are numbered breadth first, and the upper levels'
+//     rows are the longest.)
+// The items, their partial-sum slots and every result are unchanged.
+// Synchronises the library's build stream (waiting for `stream` first).
+// Returns 0 or a hipError_t (then no order is set).
+int dispatch_orders(DevicePlan &plan, const int64_t *m2l_ptr, int64_t n_cells,
+                    int32_t **m2l_order, int64_t *m2l_len, void *stream);
 
 // pos: device [n][3] FP64 (Morton order) -> out: device [n] double4 (fp64)
 // or float4 (rounded to nearest), (x, y, z, 0).

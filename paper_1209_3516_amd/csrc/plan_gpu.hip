@@ -8,7 +8,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+
 
 #include "kernels.h"
 #include "prims.h"
@@ -398,31 +402,46 @@ struct M2LRowWork {
   }
 };
 
-// Keys of a balanced order: the XCD range of unit i (the eighth of the total
-// work that holds the middle of the unit's work, from the exclusive prefix
-// sums of the work) above its inverted rank; counts[x] = units of range x.
+// XCD range of unit i: the eighth of the total work t that holds the middle
+// of the unit's work (prefix: exclusive prefix sums of the work).  It does
+// not decrease with i, since 2 prefix[i] + w(i) = prefix[i] + prefix[i + 1]
+// grows.
+template <class Work>
+__device__ __forceinline__ int64_t xcd_range(int64_t i, const Work &w,
+                                             const int64_t *__restrict__ prefix, int64_t t) {
+  const int64_t x = t > 0 ? (8 * (2 * prefix[i] + w(i))) / (2 * t) : 0;
+  return x < 7 ? x : 7;
+}
+
+// Keys of a balanced order: the XCD range of unit i above its inverted rank.
+// As the ranges do not decrease with i, range r holds the units
+// [first[r], first[r + 1]) (first[8] = n): each unit whose range differs
+// from its predecessor's writes the first[] entries of the ranges between.
 template <class Work>
 __global__ __launch_bounds__(256) void balanced_order_keys(int64_t n, Work w,
                                                            const int64_t *__restrict__ prefix,
                                                            const int64_t *__restrict__ total,
                                                            uint32_t *__restrict__ keys,
                                                            int32_t *__restrict__ vals,
-                                                           int32_t *__restrict__ counts) {
+                                                           int32_t *__restrict__ first) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t t = *total, c = w(i);
-  int64_t x = t > 0 ? (8 * (2 * prefix[i] + c)) / (2 * t) : 0;
-  if (x > 7) x = 7;
+  const int64_t t = *total;
+  const int64_t x = xcd_range(i, w, prefix, t);
+  const int64_t xp = i > 0 ? xcd_range(i - 1, w, prefix, t) : -1;
   keys[i] = ((uint32_t)x << 16) | (0xffffu - w.rank(i));
   vals[i] = (int32_t)i;
-  atomicAdd(&counts[x], 1);
+  for (int64_t r = xp + 1; r <= x; ++r) first[r] = (int32_t)i;
+  if (i == n - 1)
+    for (int64_t r = x + 1; r <= 8; ++r) first[r] = (int32_t)n;
 }
 
 struct RangeStarts {
   int32_t first[8];
 };
 
-// order[8 j + x] = the j-th unit of range x (the units sorted by key).
+// order[8 j + x] = the j-th unit of range x (the units sorted by key, so
+// range x at sorted positions [first[x], first[x + 1])).
 __global__ __launch_bounds__(256) void balanced_order_scatter(int64_t n,
                                                               const uint32_t *__restrict__ keys,
                                                               const int32_t *__restrict__ vals,
@@ -439,94 +458,118 @@ __global__ __launch_bounds__(256) void fill_i32(int64_t n, int32_t v, int32_t *_
   if (k < n) p[k] = v;
 }
 
-// The XCD-balanced dispatch order of n units (see order_m2l_rows in
+// One XCD-balanced dispatch order of n units (see dispatch_orders in
 // kernels.h): eight contiguous ranges of about equal work, range x for XCD
 // x, each by decreasing rank (ties in unit order), interleaved as
-// order[8 j + x] with -1 past a range's end.
+// order[8 j + x] with -1 past a range's end.  sort() enqueues the work's
+// prefix sums, the keys (and the first unit of each range, into first[0..8])
+// and the sort; scatter() the order itself, from first[] read back.
 template <class Work>
-int xcd_balanced_order(int64_t n, Work w, int32_t **order, int64_t *n_order, void *stream) {
-  *order = nullptr;
-  *n_order = 0;
-  if (n <= 0) return 0;
-  hipStream_t st;
-  if (int rc = build_stream(stream, reinterpret_cast<void **>(&st))) return rc;
+struct OrderJob {
+  int64_t n;
+  Work w;
   int64_t *prefix = nullptr, *total = nullptr;
   uint32_t *keys = nullptr, *keys_alt = nullptr;
-  int32_t *vals = nullptr, *vals_alt = nullptr, *counts = nullptr;
+  int32_t *vals = nullptr, *vals_alt = nullptr;
   void *scratch = nullptr;
+  bool in_alt = false;
+
+  hipError_t sort(int32_t *first, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const size_t sb = std::max(prims::radix_scratch_bytes(n), prims::scan_scratch_bytes<int64_t>(n));
+    hipError_t e;
+    if ((e = hipMallocAsync((void **)&prefix, (size_t)n * 8, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&total, 8, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&keys, (size_t)n * 4, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&keys_alt, (size_t)n * 4, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&vals, (size_t)n * 4, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&vals_alt, (size_t)n * 4, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync(&scratch, sb, st)) != hipSuccess) return e;
+    e = prims::exclusive_scan<int64_t>(n, w, prims::StoreArray<int64_t, int64_t>{prefix},
+                                       (int64_t *)scratch, total, st);
+    if (e != hipSuccess) return e;
+    balanced_order_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, w, prefix, total, keys,
+                                                                      vals, first);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return prims::radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, n, 0, 19, scratch, st,
+                                       &in_alt);
+  }
+
+  hipError_t scatter(const int32_t *first, int32_t **order, int64_t *n_order, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    RangeStarts rs;
+    int64_t widest = 0;
+    for (int x = 0; x < 8; ++x) {
+      rs.first[x] = first[x];
+      widest = std::max<int64_t>(widest, (int64_t)first[x + 1] - first[x]);
+    }
+    const int64_t m = 8 * widest;
+    hipError_t e = hipMalloc((void **)order, (size_t)m * 4);
+    if (e != hipSuccess) return e;
+    *n_order = m;
+    fill_i32<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(m, -1, *order);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    balanced_order_scatter<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+        n, in_alt ? keys_alt : keys, in_alt ? vals_alt : vals, rs, *order);
+    return hipGetLastError();
+  }
+
+  void free_temps(hipStream_t st) {
+    void *ps[] = {prefix, total, keys, keys_alt, vals, vals_alt, scratch};
+    for (void *q : ps)
+      if (q) (void)hipFreeAsync(q, st);
+  }
+};
+
+}  // namespace
+
+int dispatch_orders(DevicePlan &plan, const int64_t *m2l_ptr, int64_t n_cells,
+                    int32_t **m2l_order, int64_t *m2l_len, void *stream) {
+  if (plan.order) (void)hipFree(plan.order);
+  if (*m2l_order) (void)hipFree(*m2l_order);
+  plan.order = *m2l_order = nullptr;
+  plan.order_len = *m2l_len = 0;
+  if (plan.n_items <= 0 && n_cells <= 0) return 0;
+  if (int rc = keep_pool_memory()) return rc;
+  hipStream_t st;
+  if (int rc = build_stream(stream, reinterpret_cast<void **>(&st))) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  OrderJob<P2PItemWork> pj{plan.n_items, P2PItemWork{plan.items}};
+  OrderJob<M2LRowWork> mj{n_cells, M2LRowWork{m2l_ptr}};
+  int32_t *first = nullptr;  // first unit of each range: P2P [0, 9), M2L [9, 18)
+  int32_t host_first[18] = {};
   hipError_t e = hipSuccess;
   auto ok = [&](hipError_t r) {
     if (e == hipSuccess) e = r;
     return e == hipSuccess;
   };
-  const unsigned nb = (unsigned)((n + 255) / 256);
-  const size_t sbytes =
-      std::max(prims::radix_scratch_bytes(n), prims::scan_scratch_bytes<int64_t>(n));
-  int32_t host_counts[8] = {};
-  bool in_alt = false;
-  if (ok(hipMallocAsync((void **)&prefix, (size_t)n * 8, st)) &&
-      ok(hipMallocAsync((void **)&total, 8, st)) &&
-      ok(hipMallocAsync((void **)&keys, (size_t)n * 4, st)) &&
-      ok(hipMallocAsync((void **)&keys_alt, (size_t)n * 4, st)) &&
-      ok(hipMallocAsync((void **)&vals, (size_t)n * 4, st)) &&
-      ok(hipMallocAsync((void **)&vals_alt, (size_t)n * 4, st)) &&
-      ok(hipMallocAsync((void **)&counts, 8 * 4, st)) &&
-      ok(hipMallocAsync(&scratch, sbytes, st))) {
-    fill_i32<<<1, 256, 0, st>>>(8, 0, counts);
-    if (ok(hipGetLastError()) &&
-        ok(prims::exclusive_scan<int64_t>(n, w, prims::StoreArray<int64_t, int64_t>{prefix},
-                                          (int64_t *)scratch, total, st))) {
-      balanced_order_keys<<<nb, 256, 0, st>>>(n, w, prefix, total, keys, vals, counts);
-      if (ok(hipGetLastError()) &&
-          ok(prims::radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, n, 0, 19, scratch, st,
-                                         &in_alt)) &&
-          ok(hipMemcpyAsync(host_counts, counts, sizeof(host_counts), hipMemcpyDeviceToHost,
-                            st)) &&
-          ok(hipStreamSynchronize(st))) {
-        RangeStarts rs;
-        int64_t first = 0, widest = 0;
-        for (int x = 0; x < 8; ++x) {
-          rs.first[x] = (int32_t)first;
-          first += host_counts[x];
-          widest = std::max<int64_t>(widest, host_counts[x]);
-        }
-        const int64_t m = 8 * widest;
-        if (ok(hipMalloc((void **)order, (size_t)m * 4))) {
-          fill_i32<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(m, -1, *order);
-          if (ok(hipGetLastError())) {
-            balanced_order_scatter<<<nb, 256, 0, st>>>(n, in_alt ? keys_alt : keys,
-                                                        in_alt ? vals_alt : vals, rs, *order);
-            if (ok(hipGetLastError())) *n_order = m;
-          }
-        }
-      }
+  double t_sorted = 0.0;
+  if (ok(hipMallocAsync((void **)&first, sizeof(host_first), st))) {
+    if (ok(pj.sort(first, st)) && ok(mj.sort(first + 9, st)) &&
+        ok(hipMemcpyAsync(host_first, first, sizeof(host_first), hipMemcpyDeviceToHost, st)) &&
+        ok(hipStreamSynchronize(st))) {
+      t_sorted = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                     .count();
+      if (ok(pj.scatter(host_first, &plan.order, &plan.order_len, st)))
+        ok(mj.scatter(host_first + 9, m2l_order, m2l_len, st));
     }
   }
-  void *ps[] = {prefix, total, keys, keys_alt, vals, vals_alt, counts, scratch};
-  for (void *q : ps)
-    if (q) (void)hipFreeAsync(q, st);
+  pj.free_temps(st);
+  mj.free_temps(st);
+  if (first) (void)hipFreeAsync(first, st);
   ok(hipStreamSynchronize(st));
   if (e != hipSuccess) {
-    if (*order) (void)hipFree(*order);
-    *order = nullptr;
-    *n_order = 0;
+    if (plan.order) (void)hipFree(plan.order);
+    if (*m2l_order) (void)hipFree(*m2l_order);
+    plan.order = *m2l_order = nullptr;
+    plan.order_len = *m2l_len = 0;
+  } else if (std::getenv("FMM_LOG")) {
+    std::fprintf(stderr, "[fmm] dispatch orders: %.2f ms (sorted and counted %.2f ms)\n",
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                     .count(),
+                 t_sorted);
   }
   return (int)e;
-}
-
-}  // namespace
-
-int order_p2p_items(DevicePlan &plan, void *stream) {
-  if (plan.order) (void)hipFree(plan.order);
-  plan.order = nullptr;
-  plan.order_len = 0;
-  return xcd_balanced_order(plan.n_items, P2PItemWork{plan.items}, &plan.order, &plan.order_len,
-                            stream);
-}
-
-int order_m2l_rows(const int64_t *ptr, int64_t n_cells, int32_t **order, int64_t *n_order,
-                   void *stream) {
-  return xcd_balanced_order(n_cells, M2LRowWork{ptr}, order, n_order, stream);
 }
 
 void DevicePlan::release() {
