@@ -796,9 +796,12 @@ int enqueue_evaluation(fmm_tree *t, fmm_lists *l, const fmm_eval_opts *o, const 
     // every cell is an M2L row (one without entries writes zeros); the top
     // n_top cells accumulate in FP64.  A target range takes, level by level,
     // the cells holding its bodies.
-    // a launch over all cells takes the cells in the lists' dispatch order
-    auto order_for = [&](int64_t a, int64_t b) -> const int32_t * {
-      return a == 0 && b == td.n_cells() ? dv.m2l_order : nullptr;
+    // In an evaluation of all targets, a launch that runs to the last cell
+    // takes the cells in the lists' dispatch order (its kernel skips the
+    // cells below its range: the FP64 top levels, launched apart, are a
+    // small share of the work).
+    auto order_for = [&](int64_t, int64_t b) -> const int32_t * {
+      return !ranged && b == td.n_cells() ? dv.m2l_order : nullptr;
     };
     auto m2l_cells = [&](int64_t c0, int64_t c1) -> int {
       const int64_t split = std::max(c0, std::min(n_top, c1));

@@ -266,7 +266,8 @@ __device__ __forceinline__ void m2l_row(int64_t r0, const int64_t *__restrict__ 
   constexpr int T = nterms(P), S = pad4(T), TR = rterms(P), SR = pad4(TR);
   const int lane = threadIdx.x;
   const int A = order ? order[blockIdx.x] : (int)(r0 + xcd_remap(blockIdx.x, gridDim.x));
-  if (A < 0) return;  // padding of an ordered launch
+  // an ordered launch: padding, or a cell of [0, r0) (left to another launch)
+  if (A < r0) return;
   const double4 ga = geo[A];
   Acc acc[TR];
   static_for<TR>([&](auto I) { acc[decltype(I)::value] = Acc(0); });

@@ -90,8 +90,9 @@ int m2l_mfma(int p, int64_t tile0, int64_t tile1, const int32_t *tile_cells,
 // Target cells [r0, r1) from the folded multipoles Mr; acc_fp64: the row
 // accumulates in FP64 into L64, else into L (FP32 in mixed mode).
 // order: NULL (r1 - r0 work-groups; work-group w takes cell r0 + xcd_remap(w)),
-// or the n_order entries of a dispatch_orders M2L order of the cells [r0, r1)
-// (n_order work-groups; work-group w takes cell order[w], none if it is -1).
+// or, when r1 is the number of cells, the n_order entries of the
+// dispatch_orders M2L order of all cells (n_order work-groups; work-group w
+// takes cell order[w], none if it is -1 or below r0).
 int m2l(int p, bool fp64, int64_t r0, int64_t r1, const int64_t *ptr,
         const int32_t *col, const double *geo, const void *Mr, void *L, double *L64,
         bool acc_fp64, const int32_t *order, int64_t n_order, void *stream);
