@@ -50,8 +50,50 @@ __device__ __forceinline__ double lane_shuffle(double v, int addr) {
 }
 static_assert(kP2PMaxRuns == 256, "LDS run table size");
 
-template <typename Real, int MODE, int R, bool KAHAN, bool MASK, typename IndexFn>
-__device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
+// Staged positions of a batch -> source bodies: stage(off, nb, bi) gives
+// lane l in bi[q] the body of position off + 64 q + l of the phase's source
+// list, or 0 past nb (a lambda, so that the host pass of the compiler, which
+// sees p2p_phase's LDS builtins, accepts the call).
+constexpr int kStageRows = kNB / 64;
+
+// An item's runs (in LDS): run r starts at position rp[r] and holds bodies
+// from rp[r] + delta[r] on, so position c is body c + delta[run of c].  Per
+// batch the starts of the runs that begin in it are flagged in a bit mask
+// (one bit per staged position, 2 kStageRows words in LDS); lane l of row q
+// then counts the flags at or below its position and adds the flags of the
+// rows before and the run before the batch: its run, without a search.
+// *nxt: the first run that starts at or after position off (0 at first).
+__device__ __forceinline__ void stage_runs(const int32_t *rp, const int32_t *delta,
+                                           uint32_t *mask, int n_runs, int &nxt, int off, int nb,
+                                           int (&bi)[kStageRows]) {
+  const int lane = threadIdx.x;
+  if (lane < 2 * kStageRows) mask[lane] = 0u;
+  __syncthreads();
+  const int before = nxt - 1;  // the run of position off - 1 (-1 before the first)
+  int cnt;
+  do {  // flag up to 64 run starts at a time
+    const int r = nxt + lane;
+    const int pos = r < n_runs ? rp[r] - off : nb;
+    const bool in = pos < nb;
+    if (in) atomicOr(&mask[pos >> 5], 1u << (pos & 31));
+    cnt = __popcll(__ballot(in));
+    nxt += cnt;
+  } while (cnt == 64);
+  __syncthreads();
+  const uint64_t upto_lane = __lanemask_lt() | __lanemask_eq();
+  int seen = 0;
+#pragma unroll
+  for (int q = 0; q < kStageRows; ++q) {
+    const uint64_t m = ((uint64_t)mask[2 * q + 1] << 32) | mask[2 * q];
+    const int pos = q * 64 + lane;
+    const int d = delta[before + seen + __popcll(m & upto_lane)];
+    bi[q] = pos < nb ? off + pos + d : 0;
+    seen += __popcll(m);
+  }
+}
+
+template <typename Real, int MODE, int R, bool KAHAN, bool MASK, typename StageFn>
+__device__ __forceinline__ void p2p_phase(int nsrc, StageFn stage,
                                           const typename Vec<Real>::V4 *__restrict__ bodies,
                                           const typename Vec<Real>::V4 *__restrict__ dipoles,
                                           typename Vec<Real>::V4 *src,
@@ -95,13 +137,9 @@ __device__ __forceinline__ void p2p_phase(int nsrc, IndexFn body_of,
     // zero-charge bodies.  FP64 bodies (32 bytes) are staged through
     // registers, with all indices computed and all loads issued before the
     // stores.
-    constexpr int NL = kNB / 64;  // positions that can hold sources
+    constexpr int NL = kStageRows;  // positions that can hold sources
     int bi[NL];
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int pos = q * 64 + lane;
-      bi[q] = pos < nb ? body_of(off + pos) : 0;
-    }
+    stage(off, nb, bi);
     if constexpr (sizeof(V4) == 16) {
 #pragma unroll
       for (int q = 0; q < NL; ++q) {
@@ -251,7 +289,8 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
                                          typename Vec<Real>::V4 *__restrict__ out_s,
                                          typename Vec<Real>::V4 *__restrict__ out_c,
                                          typename Vec<Real>::V4 *src,
-                                         typename Vec<Real>::V4 *srcd, int32_t *rb, int32_t *rp) {
+                                         typename Vec<Real>::V4 *srcd, int32_t *delta,
+                                         int32_t *rp, uint32_t *mask) {
   using V4 = typename Vec<Real>::V4;
   const int lane = threadIdx.x;
   const int nt = it.tgt_cfg & 0xff;
@@ -290,39 +329,29 @@ __device__ __forceinline__ void p2p_item(const P2PItem &it, const int32_t *__res
   if (it.self_n > 0) {
     const int b0 = it.self_begin;
     p2p_phase<Real, MODE, R, KAHAN, true>(
-        it.self_n, [&](int c) { return b0 + c; }, bodies, vec, src, srcd, s, K, xi, yi, zi, vt, S,
-        C);
+        it.self_n,
+        [&](int off, int nb, int (&bi)[kStageRows]) {
+#pragma unroll
+          for (int q = 0; q < kStageRows; ++q) {
+            const int pos = q * 64 + lane;
+            bi[q] = pos < nb ? b0 + off + pos : 0;
+          }
+        },
+        bodies, vec, src, srcd, s, K, xi, yi, zi, vt, S, C);
   }
   if (it.n_src > 0) {
     for (int r = lane; r < it.n_runs; r += 64) {
-      rb[r] = run_body[it.run_begin + r];
-      rp[r] = run_prefix[it.run_begin + r];
+      const int32_t p0 = run_prefix[it.run_begin + r];
+      rp[r] = p0;
+      delta[r] = run_body[it.run_begin + r] - p0;
     }
-    // the prefixes end with n_src, twice (the lookup reads one run ahead)
-    if (lane < 2) rp[it.n_runs + lane] = it.n_src;
     __syncthreads();
-    // Positions only grow, so the run of c is found by moving forward from
-    // the last one.  Its first position and body and the first positions of
-    // the next two runs stay in registers: a lookup that stays in its run
-    // reads no LDS, and each step forward (one or two runs) reads three
-    // independent values.
-    int ri = 0, run_pos = rp[0], run_body0 = rb[0], next_pos = rp[1], next2_pos = rp[2];
+    int nxt = 0;
+    const int n_runs = it.n_runs;
     p2p_phase<Real, MODE, R, KAHAN, MASK_ALL>(
         it.n_src,
-        [&](int c) {
-          while (next_pos <= c) {
-            if (next2_pos <= c) {
-              ri += 2;
-              run_pos = next2_pos;
-            } else {
-              ri += 1;
-              run_pos = next_pos;
-            }
-            run_body0 = rb[ri];
-            next_pos = rp[ri + 1];
-            next2_pos = rp[ri + 2];
-          }
-          return run_body0 + (c - run_pos);
+        [&](int off, int nb, int (&bi)[kStageRows]) {
+          stage_runs(rp, delta, mask, n_runs, nxt, off, nb, bi);
         },
         bodies, vec, src, srcd, s, K, xi, yi, zi, vt, S, C);
   }
@@ -344,8 +373,9 @@ __device__ __forceinline__ void p2p_wave(const P2PItem *__restrict__ items,
   using V4 = typename Vec<Real>::V4;
   __shared__ V4 src[kNB + 64];
   __shared__ V4 srcd[MODE == kDipoles ? kNB + 64 : 1];
-  __shared__ int32_t rb[kP2PMaxRuns];
-  __shared__ int32_t rp[kP2PMaxRuns + 2];
+  __shared__ int32_t delta[kP2PMaxRuns];
+  __shared__ int32_t rp[kP2PMaxRuns];
+  __shared__ uint32_t mask[2 * (kNB / 64)];
   const int64_t w = order ? order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
   if (w < 0) return;  // padding of an ordered launch
   const P2PItem it = items[w];
@@ -355,7 +385,7 @@ __device__ __forceinline__ void p2p_wave(const P2PItem *__restrict__ items,
   case RR:                                                                                  \
     if constexpr (RR <= MAXR)                                                               \
       p2p_item<Real, MODE, RR, KAHAN, MASK_ALL>(it, run_body, run_prefix, bodies, vec, out_s, \
-                                                out_c, src, srcd, rb, rp);                   \
+                                                out_c, src, srcd, delta, rp, mask);          \
     break;
     FMM_P2P_CASE(1)
     FMM_P2P_CASE(2)
@@ -608,8 +638,15 @@ __device__ __forceinline__ void p2p_mutual_item(
     // copy s of the targets reads every K-th of A's bodies
     const int b0 = it.self_begin;
     p2p_phase<float, kCharges, R, true, true>(
-        it.self_n, [&](int c) { return b0 + c; }, bodies, nullptr, src, nullptr, s, K, xi, yi,
-        zi, vt, S, C);
+        it.self_n,
+        [&](int off, int nb, int (&bi)[kStageRows]) {
+#pragma unroll
+          for (int q = 0; q < kStageRows; ++q) {
+            const int pos = q * 64 + lane;
+            bi[q] = pos < nb ? b0 + off + pos : 0;
+          }
+        },
+        bodies, nullptr, src, nullptr, s, K, xi, yi, zi, vt, S, C);
   }
   if (it.n_src > 0) {
     for (int r = lane; r < it.n_runs; r += 64) {
