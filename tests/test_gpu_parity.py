@@ -187,6 +187,42 @@ def test_long_rows_are_chunked():
         assert_close(g, ref["grad"], tol(prec, 4), "grad")
 
 
+def max_run_starts_per_batch(t, lst, batch=384):
+    """The most starts of source runs among the positions of one staged batch
+    of 384 sources in any P2P row (entries of consecutive leaves whose bodies
+    follow each other in memory form one run; the leaf itself is not a run)."""
+    v = t.view()
+    ptr, col = lst.csr(fmm.FMM_P2P)
+    nb, bb = v["n_body"], v["body_begin"]
+    best = 0
+    for a in np.flatnonzero(v["n_child"] == 0):
+        c = col[ptr[a]:ptr[a + 1]]
+        c = c[c != a]
+        if c.size == 0:
+            continue
+        new = np.ones(c.size, bool)
+        new[1:] = bb[c[1:]] != bb[c[:-1]] + nb[c[:-1]]
+        pos = np.concatenate([[0], np.cumsum(nb[c])[:-1]])[new]
+        best = max(best, int(np.bincount(pos // batch).max()))
+    return best
+
+
+def test_many_run_starts_per_batch():
+    """Leaves of at most 4 bodies on a Plummer sphere at theta = 0.25: more than
+    64 runs start inside one staged batch, so the staging flags the run starts
+    in more than one round of 64 lanes."""
+    x = W.plummer(5000, seed=27)
+    q = W.charges(5000, seed=28)
+    t = fmm.Tree(x, 4)
+    lst = fmm.Lists(t, 0.25)
+    assert max_run_starts_per_batch(t, lst) > 64
+    ref = O.OracleFMM(x, 4, 0.25).evaluate(q, 4)
+    for prec in ("fp64", "mixed"):
+        _, _, phi, g = gpu_eval(x, q, 4, 0.25, 4, prec)
+        assert_close(phi, ref["phi"], tol(prec, 4), "phi")
+        assert_close(g, ref["grad"], tol(prec, 4), "grad")
+
+
 def test_repeat_is_bitwise_identical():
     x = W.plummer(20_000, seed=23)
     q = W.charges(20_000, seed=24)
